@@ -1,0 +1,246 @@
+"""Seeded synthetic inputs for the source update (host side, numpy).
+
+This module only draws inputs.  It holds none of the source-update
+arithmetic and is the one piece of code that both the oracle tests and the
+GPU path consume.  Every random number comes from a counter-based hash, so any
+subset of cells can be regenerated exactly from (seed, cell index):
+
+    splitmix64(z): z += 0x9E3779B97F4A7C15
+                   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9
+                   z = (z ^ (z >> 27)) * 0x94D049BB133111EB
+                   return z ^ (z >> 31)
+    draw(seed, field, cell, sub) = splitmix64(splitmix64(splitmix64(
+                                   splitmix64(seed) ^ field) ^ cell) ^ sub)
+    uniform = (draw >> 11) * 2^-53   in [0, 1)
+
+The device generator in ``csrc/synth.hip`` implements the same hash and the
+same transforms.
+
+Workloads (dimensionless, h/k = 1 so x = nu/T, rho = 1, c_v = 3/2):
+
+* ``config0``: 16^3 cells, 4 log-spaced groups over [1e-3, 1e3], opacity
+  kappa0 nu^-2 with kappa0 log-uniform in [1e-2, 1e2] per cell, ln T ~ N(0, 0.5^2),
+  E_g Planck at T_rad = T U(0.5, 2), F_g = f c E_g n with f ~ U(0, 0.5) and n a
+  random unit vector per (cell, group), v/c ~ U(-1e-3, 1e-3) per component,
+  dt c_hat = 1.
+* ``config1``: 128^3 cells, 16 groups, one opacity table per seed with
+  per-group exponent U(-4, 2) and jumps of 10^U(-1.5, 1.5) between adjacent
+  groups, anchored at chi(nu = 1) = 1; v/c ~ U(-1e-2, 1e-2).
+* ``config2``: 256^3 cells, 64 groups, T ~ 10^U(-1.5, 1.5), optical depth at
+  nu = 1 of 10^U(-3, 6) per cell, table as config1, v/c as config0.
+* ``patches``: AMR-like patches (cube sides {8,16,32,64}, N_g {8,16,32,64}),
+  each with its own edges over [10^U(-3.5,-2.5), 10^U(2.5,3.5)] and table.
+
+The speed of light c and the radiation constant a_R are per-workload unit
+choices; see ``UNITS``.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+M64 = np.uint64(0xFFFFFFFFFFFFFFFF)
+_G = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+# field identifiers of the hash
+F_T, F_T2, F_TRAD, F_V, F_KAPPA, F_FLUX, F_DIR, F_TAB_ALPHA, F_TAB_JUMP, F_PATCH = range(10)
+
+BASE_SEED = 20240718
+
+# Unit choices per workload (c, a_R); h/k = 1, c_v = 3/2 and rho = 1 always.
+# c = 1e3 puts v/c = 1e-3 at a Mach number of order one.  The radiation
+# constant keeps the radiation inertia E/(rho c^2) <= ~1e-3 in every cell: the
+# regime of O(v/c) radiation hydrodynamics, where the lagged-velocity outer
+# iteration contracts.  With T spread over three decades (config2 family)
+# a_R = 1 would give E/(rho c^2) ~ 10 in the hottest cells, so that family
+# uses a_R = 1e-4 (radiation/gas energy ratio from 1e-10 to ~30).
+UNITS = {
+    "config0": dict(c=1.0e3, a_rad=1.0),
+    "config1": dict(c=1.0e3, a_rad=1.0),
+    "config2": dict(c=1.0e3, a_rad=1.0e-4),
+    "patches": dict(c=1.0e3, a_rad=1.0e-4),
+}
+
+
+def splitmix64(z):
+    z = np.asarray(z, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = z + _G
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+    return z ^ (z >> np.uint64(31))
+
+
+def draw(seed, field, cell, sub=0):
+    z = splitmix64(np.uint64(seed))
+    z = splitmix64(z ^ np.uint64(field))
+    z = splitmix64(z ^ np.asarray(cell, dtype=np.uint64))
+    return splitmix64(z ^ np.asarray(sub, dtype=np.uint64))
+
+
+def uniform(seed, field, cell, sub=0):
+    """U[0,1) from the 53 high bits of the hash."""
+    return (draw(seed, field, cell, sub) >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+
+
+def normal(seed, field, cell):
+    """Box-Muller on two hashed uniforms (subs 0 and 1)."""
+    u1 = uniform(seed, field, cell, 0)
+    u2 = uniform(seed, field, cell, 1)
+    return np.sqrt(-2.0 * np.log1p(-u1)) * np.cos(2.0 * math.pi * u2)
+
+
+def log_uniform(u, lo, hi):
+    return np.exp(math.log(lo) + (math.log(hi) - math.log(lo)) * u)
+
+
+# ---------------------------------------------------------------------------
+# Planck-shaped initial radiation energies.  The generator's own 12-point
+# Gauss-Legendre rule in ln t on each group: an input recipe, not the method.
+_GL_X, _GL_W = np.polynomial.legendre.leggauss(12)
+
+
+def planck_group_energy(T, edges, a_rad):
+    """a_R T^4 (15/pi^4) int_{x-}^{x+} t^3/(e^t-1) dt per group, x = nu/T.
+    T: [n]; edges: [N_g+1] (finite, > 0).  Returns [N_g, n]."""
+    T = np.asarray(T, dtype=np.float64)
+    lnu = np.log(np.asarray(edges, dtype=np.float64))
+    lo, hi = lnu[:-1], lnu[1:]
+    half, mid = 0.5 * (hi - lo), 0.5 * (hi + lo)
+    out = np.zeros((len(lo), T.size))
+    lnT = np.log(T)
+    for xk, wk in zip(_GL_X, _GL_W):
+        u = (mid + half * xk)[:, None] - lnT[None, :]          # ln t
+        t = np.exp(u)
+        with np.errstate(over="ignore", under="ignore", invalid="ignore"):
+            f = np.exp(4.0 * u - t) / (-np.expm1(-t))           # t^4/(e^t-1)
+        f = np.where(np.isfinite(f), f, 0.0)
+        out += (wk * half)[:, None] * f
+    return a_rad * T[None, :] ** 4 * (15.0 / math.pi ** 4) * out
+
+
+# ---------------------------------------------------------------------------
+@dataclasses.dataclass
+class Workload:
+    """One batch of cells sharing a group structure and opacity table."""
+    name: str
+    n: int
+    edges: np.ndarray       # [N_g+1]
+    chi_lo: np.ndarray      # [N_g] opacity at lower edges per unit (rho kappa)
+    alpha_chi: np.ndarray   # [N_g]
+    kappa: np.ndarray       # [n] per-cell opacity scale
+    state: dict             # E_g [N_g,n], F_g [3,N_g,n], rho [n], e_gas [n], v [3,n]
+    T: np.ndarray           # [n] initial gas temperature (diagnostic only)
+    dt: float
+    c_hat: float
+    c: float
+    a_rad: float
+    c_v: float = 1.5
+    h_over_k: float = 1.0
+
+    @property
+    def ng(self):
+        return len(self.chi_lo)
+
+    def consts(self):
+        return dict(dt=self.dt, c_hat=self.c_hat, c=self.c, a_rad=self.a_rad,
+                    c_v=self.c_v, h_over_k=self.h_over_k)
+
+
+def log_edges(lo, hi, ng):
+    return np.logspace(math.log10(lo), math.log10(hi), ng + 1)
+
+
+def random_table(seed, edges, anchor_nu=1.0, field_offset=0, sub_base=0):
+    """Per-group powerlaw opacity table: exponents U(-4, 2), jumps of
+    10^U(-1.5, 1.5) between adjacent groups, chi(anchor_nu) = 1."""
+    ng = len(edges) - 1
+    g = np.arange(ng)
+    alpha = -4.0 + 6.0 * uniform(seed, F_TAB_ALPHA + field_offset, 0, sub_base + g)
+    jump = 10.0 ** (-1.5 + 3.0 * uniform(seed, F_TAB_JUMP + field_offset, 0, sub_base + g))
+    lr = np.log(edges[1:] / edges[:-1])
+    # group containing the anchor, and the table value at its lower edge
+    ga = int(np.clip(np.searchsorted(edges, anchor_nu, side="right") - 1, 0, ng - 1))
+    lchi = np.zeros(ng)  # ln chi at lower edges
+    lchi[ga] = -alpha[ga] * math.log(anchor_nu / edges[ga])
+    for k in range(ga + 1, ng):        # upward: end of k-1, then the jump
+        lchi[k] = lchi[k - 1] + alpha[k - 1] * lr[k - 1] + math.log(jump[k - 1])
+    for k in range(ga - 1, -1, -1):    # downward
+        lchi[k] = lchi[k + 1] - math.log(jump[k]) - alpha[k] * lr[k]
+    return np.exp(lchi), alpha
+
+
+def _state(seed, cells, edges, T, trad_lo, trad_hi, vmax, c, a_rad, c_v=1.5):
+    n = cells.size
+    ng = len(edges) - 1
+    trad = T * (trad_lo + (trad_hi - trad_lo) * uniform(seed, F_TRAD, cells))
+    E = planck_group_energy(trad, edges, a_rad)
+    v = np.stack([(2.0 * uniform(seed, F_V, cells, d) - 1.0) * vmax * c for d in range(3)])
+    g = np.arange(ng, dtype=np.uint64)[:, None]
+    f = 0.5 * uniform(seed, F_FLUX, cells[None, :], g)
+    z = 2.0 * uniform(seed, F_DIR, cells[None, :], 2 * g) - 1.0
+    ph = 2.0 * math.pi * uniform(seed, F_DIR, cells[None, :], 2 * g + 1)
+    s = np.sqrt(np.maximum(0.0, 1.0 - z * z))
+    nvec = np.stack([s * np.cos(ph), s * np.sin(ph), z])   # [3, N_g, n]
+    F = f[None] * c * E[None] * nvec
+    rho = np.ones(n)
+    e_gas = rho * c_v * T + 0.5 * rho * (v * v).sum(0)
+    return {"E_g": np.ascontiguousarray(E), "F_g": np.ascontiguousarray(F), "rho": rho,
+            "e_gas": e_gas, "v": np.ascontiguousarray(v)}
+
+
+def _cells(n, cells):
+    return np.arange(n, dtype=np.uint64) if cells is None else np.asarray(cells, np.uint64)
+
+
+def config0(cells=None, seed=BASE_SEED + 0, n=16 ** 3):
+    cells = _cells(n, cells)
+    u = UNITS["config0"]
+    edges = log_edges(1e-3, 1e3, 4)
+    T = np.exp(0.5 * normal(seed, F_T, cells))
+    kappa = log_uniform(uniform(seed, F_KAPPA, cells), 1e-2, 1e2)
+    st = _state(seed, cells, edges, T, 0.5, 2.0, 1e-3, u["c"], u["a_rad"])
+    return Workload("config0", cells.size, edges, edges[:-1] ** -2.0, np.full(4, -2.0),
+                    kappa, st, T, dt=1.0 / u["c"], c_hat=u["c"], **u)
+
+
+def config1(cells=None, seed=BASE_SEED + 1, n=128 ** 3, ng=16):
+    cells = _cells(n, cells)
+    u = UNITS["config1"]
+    edges = log_edges(1e-3, 1e3, ng)
+    chi_lo, alpha = random_table(seed, edges)
+    T = np.exp(0.5 * normal(seed, F_T, cells))
+    kappa = log_uniform(uniform(seed, F_KAPPA, cells), 1e-2, 1e2)
+    st = _state(seed, cells, edges, T, 0.5, 2.0, 1e-2, u["c"], u["a_rad"])
+    return Workload("config1", cells.size, edges, chi_lo, alpha, kappa, st, T,
+                    dt=1.0 / u["c"], c_hat=u["c"], **u)
+
+
+def config2(cells=None, seed=BASE_SEED + 2, n=256 ** 3, ng=64, units="config2"):
+    cells = _cells(n, cells)
+    u = UNITS[units]
+    edges = log_edges(1e-3, 1e3, ng)
+    chi_lo, alpha = random_table(seed, edges)
+    T = 10.0 ** (-1.5 + 3.0 * uniform(seed, F_T, cells))
+    tau = 10.0 ** (-3.0 + 9.0 * uniform(seed, F_KAPPA, cells))
+    dt = 1.0 / u["c"]
+    kappa = tau / (dt * u["c"] * 1.0 * 1.0)   # tau = dt c_hat rho chi(nu=1) kappa
+    st = _state(seed, cells, edges, T, 0.5, 2.0, 1e-3, u["c"], u["a_rad"])
+    return Workload("config2", cells.size, edges, chi_lo, alpha, kappa, st, T,
+                    dt=dt, c_hat=u["c"], **u)
+
+
+def subset(w: Workload, idx) -> Workload:
+    """Cells ``idx`` of a workload, as an independent Workload."""
+    idx = np.asarray(idx)
+    st = {"E_g": np.ascontiguousarray(w.state["E_g"][:, idx]),
+          "F_g": np.ascontiguousarray(w.state["F_g"][:, :, idx]),
+          "rho": np.ascontiguousarray(w.state["rho"][idx]),
+          "e_gas": np.ascontiguousarray(w.state["e_gas"][idx]),
+          "v": np.ascontiguousarray(w.state["v"][:, idx])}
+    return dataclasses.replace(w, n=idx.size, kappa=np.ascontiguousarray(w.kappa[idx]),
+                               state=st, T=np.ascontiguousarray(w.T[idx]))
