@@ -1,0 +1,178 @@
+#!/usr/bin/env python3
+"""Benchmark of the multigroup source update on one MI355X.
+
+A step is one full source update (inner Newton, energy, flux and momentum
+updates, outer passes) of every cell of the workload.  The inputs are drawn
+in HBM by the device generator; before every step the pristine inputs are
+copied back over the in-place state (a device copy, inside the timed region),
+so every step solves the same input distribution.
+
+Prints one JSON line (see the repository's benchmark contract)."""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOADS = {
+    "config1": "128^3 cells, 16 groups, PPL-fixed, FP64 (random powerlaw opacity table)",
+    "config2": "256^3 cells, 64 groups, PPL-fixed, FP64 (T over 3 decades, tau 1e-3..1e6)",
+    "config0": "16^3 cells, 4 groups, PPL-fixed, FP64",
+}
+PEAK_HBM = 8.0e12            # bytes/s
+PEAK_FP64 = 78.6e12          # FP64 vector FLOP/s
+
+
+def bytes_per_cell(ng: int) -> int:
+    """Algorithmic HBM bytes per cell-update: E_g, F_g, E_gas, v read and
+    written (8(4 N_g + 4) each way), rho and the opacity scale read (16), and
+    the int32 iteration count and status written (8)."""
+    return 2 * 8 * (4 * ng + 4) + 16 + 8
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="config1", choices=list(WORKLOADS))
+    ap.add_argument("--mode", type=int, default=1, help="0 PC, 1 PPL-fixed, 2 PPL-free")
+    ap.add_argument("--cells", type=int, default=0, help="override the cell count")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target CPU time of the oracle baseline sample (0 = skip)")
+    ap.add_argument("--variant", default="", help="LPCxG kernel variant override, e.g. 8x8")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the source update has "
+                                   "no cross-GPU step (each GPU would own its own cells)",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2407_18304_amd import mgrhd, synth
+    from paper_2407_18304_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    name = args.workload
+    n = args.cells or W.SPECS[name]["n"]
+    dw = synth.device_workload(name, n=n)
+    ng = dw.ng
+    if args.variant:
+        lpc, g = (int(x) for x in args.variant.split("x"))
+        mgrhd.set_variant(ng, lpc, g)
+    pristine = {k: v.clone() for k, v in dw.state.items()}
+    st = dw.state
+    iters = torch.zeros(n, dtype=torch.int32, device=dev)
+    outer = torch.zeros(n, dtype=torch.int32, device=dev)
+    status = torch.zeros(n, dtype=torch.int32, device=dev)
+    tab = dw.tables
+    stream = torch.cuda.current_stream(dev)
+
+    def restore():
+        for k in ("E_g", "F_g", "e_gas", "v"):
+            st[k].copy_(pristine[k])
+
+    def solve():
+        mgrhd.source_update(st["E_g"], st["F_g"], st["rho"], st["e_gas"], st["v"], tab["edges"],
+                            tab["chi_lo"], alpha_chi=tab["alpha"], kappa_scale=dw.kappa,
+                            mean_mode=args.mode, polish=1, iters=iters, outer=outer,
+                            status=status, stream=stream.cuda_stream, **dw.consts())
+
+    for _ in range(args.warmup):
+        restore()
+        solve()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        restore()
+        ev[k][0].record(stream)
+        solve()
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern_ms = [a.elapsed_time(b) for a, b in ev]
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = n * args.steps / (t1 - t0)
+
+    it = iters.cpu().numpy()
+    ou = outer.cpu().numpy()
+    stt = status.cpu().numpy()
+    kern_s = float(np.mean(kern_ms)) * 1e-3
+    bpc = bytes_per_cell(ng)
+    achieved_bw = bpc * n / kern_s
+
+    result = {
+        "metric": "cell-updates/s of multigroup source solve (N_g=16,64); Newton iters/cell",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded counter-based generator, drawn in HBM)",
+        "config": {"workload": WORKLOADS[name], "cells": n, "n_groups": ng,
+                   "mean_mode": ["PC", "PPL-fixed", "PPL-free"][args.mode],
+                   "kernel_variant": "x".join(map(str, mgrhd.get_variant(ng, args.mode))),
+                   "eps_newton": 1e-11, "polish": 1, "closure": "M1"},
+        "newton_iters_per_cell": {"mean": float(it.mean()), "p50": float(np.percentile(it, 50)),
+                                  "p99": float(np.percentile(it, 99)), "max": int(it.max())},
+        "outer_passes_per_cell": {"mean": float(ou.mean()), "max": int(ou.max())},
+        "status_counts": {str(k): int(v) for k, v in enumerate(np.bincount(stt)) if v},
+        "kernel_ms": {"mean": float(np.mean(kern_ms)), "min": float(np.min(kern_ms))},
+        "roofline": {"bound": "hbm", "achieved": achieved_bw / 1e9, "peak": PEAK_HBM / 1e9,
+                     "unit": "GB/s", "frac": achieved_bw / PEAK_HBM, "traffic": None,
+                     "bytes_per_cell": bpc},
+    }
+
+    if args.cpu_seconds > 0:
+        result["cpu_baseline"] = cpu_baseline(dw, args.mode, args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+
+
+def cpu_baseline(dw, mode, target_s):
+    """The oracle (as it stands) on the host cores, on a bounded random sample
+    of the same cells (inputs copied back from HBM)."""
+    import numpy as np
+    sys.path.insert(0, os.path.join(ROOT, "oracle"))
+    import oracle
+    from paper_2407_18304_amd import synth
+    cores = os.cpu_count() or 1
+    rng = np.random.default_rng(7)
+    m = min(dw.n, 4096)
+    idx = np.sort(rng.choice(dw.n, m, replace=False))
+    w = synth.to_host(dw, idx)
+    t0 = time.perf_counter()
+    oracle.source_update(w.state, w.edges, w.chi_lo, alpha_chi=w.alpha_chi, kappa_scale=w.kappa,
+                         mean_mode=mode, polish=1, n_threads=cores, **w.consts())
+    dt = time.perf_counter() - t0
+    m2 = int(min(dw.n, max(m, m * target_s / max(dt, 1e-3))))
+    if m2 > m:
+        idx = np.sort(rng.choice(dw.n, m2, replace=False))
+        w = synth.to_host(dw, idx)
+        t0 = time.perf_counter()
+        oracle.source_update(w.state, w.edges, w.chi_lo, alpha_chi=w.alpha_chi,
+                             kappa_scale=w.kappa, mean_mode=mode, polish=1, n_threads=cores,
+                             **w.consts())
+        dt = time.perf_counter() - t0
+        m = m2
+    return {"value": m / dt, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"{m} random cells of the same workload, {dt:.1f} s on {cores} threads"}
+
+
+if __name__ == "__main__":
+    main()

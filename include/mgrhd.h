@@ -1,0 +1,150 @@
+/*
+ * mgrhd.h -- C ABI of the MI355X (gfx950) implementation of the per-cell
+ * implicit matter-radiation source update of mixed-frame multigroup
+ * radiation hydrodynamics (He, Wibking & Krumholz 2024, arXiv:2407.18304).
+ *
+ * What one call computes, per cell (Sec. 3, eqs. egupdate-fupdate):
+ *   inner stage  Newton-Raphson on x = (E_gas, R_1..R_Ng) for eqs. FGFR and
+ *                Rnew, with the arrowhead Jacobian of eqs. linear/matrix
+ *                eliminated in O(N_g), stopped by the E_tot-relative test
+ *                with eps (default 1e-11);
+ *   energy       E_g <- E_g + R_g + S_g, E_gas <- E_gas - (c/c_hat) sum_g R_g;
+ *   outer stage  flux update eq. numF1 with the outdated velocity, momentum
+ *                update, repeated until the velocity/flux terms of eq. Rnew
+ *                change by less than eps_outer E_tot (default 1e-13).
+ * Group-mean opacities: piecewise constant (eq. m1e1), piecewise powerlaw
+ * with fixed slopes alpha_Q = -1 (eq. equality) or with the slope fit of
+ * Appendix A (eqs. sg, minmod); eq. chiQg for chi_0B and chi_0E, eq. chiDiff
+ * for chi_0F, Doppler factors (1 + alpha_chi) of eqs. G0_3 and G1_3.
+ *
+ * Units: every constant is an argument.  B~_g = 4 pi B_g / c is normalised
+ * as a_R T^4 times the Planck fraction of the group, x = (h/k) nu / T.
+ *
+ * Memory: all arrays are DEVICE pointers owned by the caller, FP64, structure
+ * of arrays with the cell index fastest:
+ *   E_g[g*n + i], F_g[(d*N_g + g)*n + i], v[d*n + i], rho[i], e_gas[i].
+ * The state is updated in place.  Nothing is allocated by mgrhd_source_update.
+ * Calls are asynchronous on `stream`; results and per-cell status are valid
+ * after the caller synchronises the stream.
+ *
+ * Errors: a negative return is an argument error found on the host (nothing
+ * was enqueued); a positive return is a HIP runtime error from the launch.
+ * Errors that can only be seen on the device (a non-ascending edge table, a
+ * non-positive opacity entry) are reported per cell as MGRHD_ST_BAD_TABLE and
+ * leave the state untouched.
+ */
+#ifndef MGRHD_H
+#define MGRHD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* mgrhd_stream_t; /* a hipStream_t */
+
+/* group-mean opacity model */
+enum {
+  MGRHD_MEAN_PC = 0,        /* piecewise constant, Sec. 2.2.1                */
+  MGRHD_MEAN_PPL_FIXED = 1, /* powerlaw, alpha_B = alpha_E = -1, Sec. 2.2.2  */
+  MGRHD_MEAN_PPL_FREE = 2   /* powerlaw, slopes by Appendix A                 */
+};
+/* closure for the group pressure tensor in the flux update (Sec. 2.1) */
+enum { MGRHD_CLOSURE_M1 = 0, MGRHD_CLOSURE_EDDINGTON = 1 };
+
+/* per-cell status bits (int32 array, optional) */
+enum {
+  MGRHD_ST_OK = 0,
+  MGRHD_ST_NEWTON_MAXIT = 1, /* an inner Newton pass reached max_newton          */
+  MGRHD_ST_OUTER_MAXIT = 2,  /* the outer flux/momentum loop reached max_outer   */
+  MGRHD_ST_FALLBACK = 4,     /* the warm start failed; plain Newton was rerun     */
+  MGRHD_ST_INVALID = 8,      /* invalid cell input or T <= 0: cell untouched      */
+  MGRHD_ST_NONFINITE = 16,   /* non-finite result: cell untouched                 */
+  MGRHD_ST_BAD_TABLE = 32    /* edge/opacity table rejected on the device         */
+};
+
+/* host-side argument errors (negative returns) */
+enum {
+  MGRHD_E_NULL = -1,     /* a required pointer is NULL                          */
+  MGRHD_E_SIZE = -2,     /* n_cells < 0 or n_groups outside [1, MGRHD_MAX_GROUPS] */
+  MGRHD_E_MODE = -3,     /* unknown mean_mode or closure                         */
+  MGRHD_E_TABLE = -4,    /* powerlaw mode without alpha_chi or chi_hi            */
+  MGRHD_E_SCALAR = -5,   /* dt, c_hat or a physical constant not positive/finite */
+  MGRHD_E_OPTION = -6,   /* eps, max_newton, max_outer or polish out of range    */
+  MGRHD_E_DEVICE = -7    /* no usable device / kernel image                      */
+};
+
+#define MGRHD_MAX_GROUPS 256
+
+/* Opacity description.  chi_0(nu) in group g is
+ *   rho * kappa_scale[i] * chi_lo[g] * (nu / nu_g-)^alpha_chi[g]
+ * (Sec. 2.2.2).  chi_lo, alpha_chi, chi_hi are DEVICE arrays of N_g entries;
+ * when alpha_chi is NULL the index is ln(chi_hi/chi_lo)/ln(nu_g+/nu_g-)
+ * (tabulated opacity).  PC ignores both and uses chi_lo as the group value.
+ * kappa_scale is a DEVICE array of n_cells entries or NULL (= 1). */
+typedef struct {
+  int32_t n_groups;
+  int32_t mean_mode;
+  const double* chi_lo;
+  const double* alpha_chi;
+  const double* chi_hi;
+  const double* kappa_scale;
+} mgrhd_opacity_params;
+
+/* Options; mgrhd_default_options() fills the paper's values. */
+typedef struct {
+  double c, a_rad, h_over_k, c_v; /* c_v per unit mass (C_v = rho c_v)            */
+  double eps_newton;              /* inner stop tolerance, default 1e-11 (Sec. 3)  */
+  double eps_outer;               /* outer stop tolerance, default 1e-13 (Sec. 3)  */
+  int32_t max_newton;             /* default 100                                   */
+  int32_t max_outer;              /* default 10                                    */
+  int32_t closure;                /* MGRHD_CLOSURE_*                               */
+  int32_t polish;                 /* extra Newton steps after convergence, 0..4    */
+  const double* S_g;              /* [N_g][n] optional source term (eq. FGFR), or NULL */
+  const double* guess;            /* [N_g+1][n] warm start (E_gas, R_g), or NULL   */
+  int32_t* iters;                 /* [n] out: Newton steps summed over passes, or NULL */
+  int32_t* outer;                 /* [n] out: outer passes, or NULL                */
+  int32_t* status;                /* [n] out: MGRHD_ST_* bits, or NULL             */
+} mgrhd_options;
+
+/* Fill *opt with the defaults: c = a_rad = h_over_k = 1, c_v = 3/2,
+ * eps_newton = 1e-11, eps_outer = 1e-13, max_newton = 100, max_outer = 10,
+ * M1 closure, polish = 0, all optional arrays NULL. */
+void mgrhd_default_options(mgrhd_options* opt);
+
+/* The source update of n_cells cells, in place (see the top of this file).
+ *   E_g          [N_g][n]    in/out  group radiation energy densities
+ *   F_g          [3][N_g][n] in/out  group radiation fluxes
+ *   rho          [n]         in      gas density
+ *   e_gas        [n]         in/out  gas total energy density E_gas
+ *   v            [3][n]      in/out  gas velocity
+ *   group_edges  [N_g+1]     in      DEVICE array, strictly ascending; > 0 and
+ *                                    finite in the powerlaw modes, 0 / +inf
+ *                                    allowed in PC
+ *   opacity      host struct describing device tables
+ *   dt           theta * Delta t of the IMEX stage (eqs. egupdate-fupdate)
+ *   c_hat        reduced speed of light
+ *   stream       HIP stream (NULL = default stream)
+ *   opt          NULL for defaults
+ * Returns 0 when enqueued, MGRHD_E_* < 0 on a host-side argument error, or a
+ * positive hipError_t. */
+int mgrhd_source_update(double* E_g, double* F_g, const double* rho, double* e_gas, double* v,
+                        int64_t n_cells, const double* group_edges,
+                        const mgrhd_opacity_params* opacity, double dt, double c_hat,
+                        mgrhd_stream_t stream, const mgrhd_options* opt);
+
+/* Kernel variant used for a given group count: lanes per cell and groups per
+ * lane.  mgrhd_set_variant overrides the built-in choice for n_groups (0, 0
+ * restores it); unknown variants return MGRHD_E_OPTION. */
+int mgrhd_get_variant(int32_t n_groups, int32_t mean_mode, int32_t* lanes_per_cell,
+                      int32_t* groups_per_lane);
+int mgrhd_set_variant(int32_t n_groups, int32_t lanes_per_cell, int32_t groups_per_lane);
+
+/* Library version string. */
+const char* mgrhd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

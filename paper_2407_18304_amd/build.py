@@ -1,0 +1,57 @@
+"""Build the HIP libraries in-tree with hipcc for gfx950.
+
+    libmgrhd.so        the source-update kernels and the C ABI of include/mgrhd.h
+    libmgrhd_synth.so  the seeded synthetic-input generator (test/bench inputs)
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+ARCH = os.environ.get("MGRHD_ARCH", "gfx950")
+
+HIPCC_FLAGS = [
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+    # no packed FP32 instructions anywhere in this library
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wno-unused-command-line-argument", "-I", os.path.join(ROOT, "include"),
+]
+
+LIBS = {
+    "libmgrhd.so": ["source_update.hip"],
+    "libmgrhd_synth.so": ["synth.hip"],
+}
+
+
+def hipcc() -> str:
+    for p in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc"):
+        if p and os.path.exists(p):
+            return p
+    return "hipcc"
+
+
+def build_lib(name: str, verbose: bool = True) -> str:
+    srcs = [os.path.join(CSRC, s) for s in LIBS[name]]
+    out = os.path.join(PKG, name)
+    tmp = out + ".tmp"
+    cmd = [hipcc(), *HIPCC_FLAGS, "-o", tmp, *srcs]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
+    return out
+
+
+def build_all(verbose: bool = True):
+    return [build_lib(n, verbose) for n in LIBS if all(
+        os.path.exists(os.path.join(CSRC, s)) for s in LIBS[n])]
+
+
+if __name__ == "__main__":
+    names = sys.argv[1:] or list(LIBS)
+    for n in names:
+        build_lib(n)

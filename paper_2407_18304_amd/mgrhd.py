@@ -1,0 +1,143 @@
+"""Python binding of the C ABI in include/mgrhd.h (argument marshalling only).
+
+Every step of the source update runs in the HIP kernels of ``libmgrhd.so``;
+this module checks tensor shapes/dtypes/devices, passes device pointers and
+the current HIP stream, and raises on a non-zero return.  There is no CPU
+fallback: without the built library or a GPU the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libmgrhd.so")
+
+MEAN_PC, MEAN_PPL_FIXED, MEAN_PPL_FREE = 0, 1, 2
+CLOSURE_M1, CLOSURE_EDDINGTON = 0, 1
+ST_OK, ST_NEWTON_MAXIT, ST_OUTER_MAXIT, ST_FALLBACK, ST_INVALID, ST_NONFINITE, ST_BAD_TABLE = (
+    0, 1, 2, 4, 8, 16, 32)
+MAX_GROUPS = 256
+
+ERRORS = {-1: "NULL pointer", -2: "size out of range", -3: "unknown mode or closure",
+          -4: "powerlaw mode needs alpha_chi or chi_hi", -5: "non-positive scalar",
+          -6: "option out of range", -7: "no usable device"}
+
+
+class MgrhdError(RuntimeError):
+    def __init__(self, code: int, what: str = "mgrhd_source_update"):
+        msg = ERRORS.get(code, f"HIP error {code}")
+        super().__init__(f"{what} failed: {msg} (code {code})")
+        self.code = code
+
+
+class OpacityParams(C.Structure):
+    _fields_ = [("n_groups", C.c_int32), ("mean_mode", C.c_int32), ("chi_lo", C.c_void_p),
+                ("alpha_chi", C.c_void_p), ("chi_hi", C.c_void_p), ("kappa_scale", C.c_void_p)]
+
+
+class Options(C.Structure):
+    _fields_ = [("c", C.c_double), ("a_rad", C.c_double), ("h_over_k", C.c_double),
+                ("c_v", C.c_double), ("eps_newton", C.c_double), ("eps_outer", C.c_double),
+                ("max_newton", C.c_int32), ("max_outer", C.c_int32), ("closure", C.c_int32),
+                ("polish", C.c_int32), ("S_g", C.c_void_p), ("guess", C.c_void_p),
+                ("iters", C.c_void_p), ("outer", C.c_void_p), ("status", C.c_void_p)]
+
+
+_lib = None
+
+# exported symbols of include/mgrhd.h
+SYMBOLS = ["mgrhd_source_update", "mgrhd_default_options", "mgrhd_get_variant",
+           "mgrhd_set_variant", "mgrhd_version"]
+
+
+def lib():
+    """Load libmgrhd.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        L.mgrhd_source_update.restype = C.c_int
+        L.mgrhd_source_update.argtypes = [C.c_void_p] * 5 + [C.c_int64, C.c_void_p,
+                                                              C.POINTER(OpacityParams),
+                                                              C.c_double, C.c_double, C.c_void_p,
+                                                              C.POINTER(Options)]
+        L.mgrhd_default_options.restype = None
+        L.mgrhd_default_options.argtypes = [C.POINTER(Options)]
+        L.mgrhd_get_variant.restype = C.c_int
+        L.mgrhd_get_variant.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_int32),
+                                        C.POINTER(C.c_int32)]
+        L.mgrhd_set_variant.restype = C.c_int
+        L.mgrhd_set_variant.argtypes = [C.c_int32, C.c_int32, C.c_int32]
+        L.mgrhd_version.restype = C.c_char_p
+        L.mgrhd_version.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _ptr(t, shape=None, dtype=torch.float64, name="array"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t.data_ptr()
+
+
+def default_options() -> Options:
+    o = Options()
+    lib().mgrhd_default_options(C.byref(o))
+    return o
+
+
+def get_variant(n_groups: int, mean_mode: int = MEAN_PPL_FIXED):
+    lpc, gpl = C.c_int32(), C.c_int32()
+    rc = lib().mgrhd_get_variant(n_groups, mean_mode, C.byref(lpc), C.byref(gpl))
+    if rc:
+        raise MgrhdError(rc, "mgrhd_get_variant")
+    return lpc.value, gpl.value
+
+
+def set_variant(n_groups: int, lanes_per_cell: int, groups_per_lane: int):
+    rc = lib().mgrhd_set_variant(n_groups, lanes_per_cell, groups_per_lane)
+    if rc:
+        raise MgrhdError(rc, "mgrhd_set_variant")
+
+
+def source_update(E_g, F_g, rho, e_gas, v, group_edges, chi_lo, *, dt, c_hat,
+                  mean_mode=MEAN_PPL_FIXED, alpha_chi=None, chi_hi=None, kappa_scale=None,
+                  c=1.0, a_rad=1.0, h_over_k=1.0, c_v=1.5, eps_newton=1e-11, eps_outer=1e-13,
+                  max_newton=100, max_outer=10, closure=CLOSURE_M1, polish=0, S_g=None,
+                  guess=None, iters=None, outer=None, status=None, stream=None):
+    """In-place source update of the device state (see include/mgrhd.h)."""
+    ng, n = E_g.shape
+    o = default_options()
+    o.c, o.a_rad, o.h_over_k, o.c_v = c, a_rad, h_over_k, c_v
+    o.eps_newton, o.eps_outer = eps_newton, eps_outer
+    o.max_newton, o.max_outer, o.closure, o.polish = max_newton, max_outer, closure, polish
+    o.S_g = _ptr(S_g, (ng, n), name="S_g")
+    o.guess = _ptr(guess, (ng + 1, n), name="guess")
+    o.iters = _ptr(iters, (n,), torch.int32, "iters")
+    o.outer = _ptr(outer, (n,), torch.int32, "outer")
+    o.status = _ptr(status, (n,), torch.int32, "status")
+    op = OpacityParams(ng, mean_mode, _ptr(chi_lo, (ng,), name="chi_lo"),
+                       _ptr(alpha_chi, (ng,), name="alpha_chi"),
+                       _ptr(chi_hi, (ng,), name="chi_hi"),
+                       _ptr(kappa_scale, (n,), name="kappa_scale"))
+    if stream is None:
+        stream = torch.cuda.current_stream(E_g.device).cuda_stream
+    rc = lib().mgrhd_source_update(
+        _ptr(E_g, (ng, n), name="E_g"), _ptr(F_g, (3, ng, n), name="F_g"),
+        _ptr(rho, (n,), name="rho"), _ptr(e_gas, (n,), name="e_gas"), _ptr(v, (3, n), name="v"),
+        n, _ptr(group_edges, (ng + 1,), name="group_edges"), C.byref(op), float(dt),
+        float(c_hat), stream, C.byref(o))
+    if rc != 0:
+        raise MgrhdError(rc)

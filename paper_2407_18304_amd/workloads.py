@@ -197,41 +197,75 @@ def _cells(n, cells):
     return np.arange(n, dtype=np.uint64) if cells is None else np.asarray(cells, np.uint64)
 
 
-def config0(cells=None, seed=BASE_SEED + 0, n=16 ** 3):
-    cells = _cells(n, cells)
-    u = UNITS["config0"]
-    edges = log_edges(1e-3, 1e3, 4)
-    T = np.exp(0.5 * normal(seed, F_T, cells))
-    kappa = log_uniform(uniform(seed, F_KAPPA, cells), 1e-2, 1e2)
-    st = _state(seed, cells, edges, T, 0.5, 2.0, 1e-3, u["c"], u["a_rad"])
-    return Workload("config0", cells.size, edges, edges[:-1] ** -2.0, np.full(4, -2.0),
-                    kappa, st, T, dt=1.0 / u["c"], c_hat=u["c"], **u)
+# Per-workload parameters, shared by the host generator below and the device
+# generator (synth.py / csrc/synth.hip).
+#   t_kind 0: T = exp(t_p[1] N(0,1));  1: T = 10^U(t_p[0], t_p[1])
+#   k_kind 0: kappa log-uniform in [k_p[0], k_p[1]];
+#          1: optical depth tau = dt c_hat rho chi(nu=1) kappa = 10^U(k_p[0], k_p[1])
+SPECS = {
+    "config0": dict(seed=BASE_SEED + 0, n=16 ** 3, ng=4, table="nu^-2", t_kind=0, t_p=(0.0, 0.5),
+                    k_kind=0, k_p=(1e-2, 1e2), vmax=1e-3),
+    "config1": dict(seed=BASE_SEED + 1, n=128 ** 3, ng=16, table="random", t_kind=0,
+                    t_p=(0.0, 0.5), k_kind=0, k_p=(1e-2, 1e2), vmax=1e-2),
+    "config2": dict(seed=BASE_SEED + 2, n=256 ** 3, ng=64, table="random", t_kind=1,
+                    t_p=(-1.5, 1.5), k_kind=1, k_p=(-3.0, 6.0), vmax=1e-3),
+}
+TRAD_RANGE = (0.5, 2.0)
 
 
-def config1(cells=None, seed=BASE_SEED + 1, n=128 ** 3, ng=16):
-    cells = _cells(n, cells)
-    u = UNITS["config1"]
+def spec_tables(name, ng=None, seed=None):
+    sp = SPECS[name]
+    ng = ng or sp["ng"]
+    seed = sp["seed"] if seed is None else seed
     edges = log_edges(1e-3, 1e3, ng)
+    if sp["table"] == "nu^-2":
+        return edges, edges[:-1] ** -2.0, np.full(ng, -2.0)
     chi_lo, alpha = random_table(seed, edges)
-    T = np.exp(0.5 * normal(seed, F_T, cells))
-    kappa = log_uniform(uniform(seed, F_KAPPA, cells), 1e-2, 1e2)
-    st = _state(seed, cells, edges, T, 0.5, 2.0, 1e-2, u["c"], u["a_rad"])
-    return Workload("config1", cells.size, edges, chi_lo, alpha, kappa, st, T,
-                    dt=1.0 / u["c"], c_hat=u["c"], **u)
+    return edges, chi_lo, alpha
 
 
-def config2(cells=None, seed=BASE_SEED + 2, n=256 ** 3, ng=64, units="config2"):
-    cells = _cells(n, cells)
-    u = UNITS[units]
-    edges = log_edges(1e-3, 1e3, ng)
-    chi_lo, alpha = random_table(seed, edges)
-    T = 10.0 ** (-1.5 + 3.0 * uniform(seed, F_T, cells))
-    tau = 10.0 ** (-3.0 + 9.0 * uniform(seed, F_KAPPA, cells))
+def draw_T(name, cells, seed):
+    sp = SPECS[name]
+    if sp["t_kind"] == 0:
+        return np.exp(sp["t_p"][1] * normal(seed, F_T, cells))
+    lo, hi = sp["t_p"]
+    return 10.0 ** (lo + (hi - lo) * uniform(seed, F_T, cells))
+
+
+def draw_kappa(name, cells, seed, dt, c_hat):
+    sp = SPECS[name]
+    u = uniform(seed, F_KAPPA, cells)
+    if sp["k_kind"] == 0:
+        return log_uniform(u, *sp["k_p"])
+    lo, hi = sp["k_p"]
+    return 10.0 ** (lo + (hi - lo) * u) * (1.0 / (dt * c_hat))   # rho = chi(nu=1) = 1
+
+
+def make(name, cells=None, seed=None, n=None, ng=None, units=None):
+    """Host-side workload ``name`` (cells = indices into the full workload)."""
+    sp = SPECS[name]
+    seed = sp["seed"] if seed is None else seed
+    cells = _cells(n or sp["n"], cells)
+    u = UNITS[units or name]
+    edges, chi_lo, alpha = spec_tables(name, ng, seed)
     dt = 1.0 / u["c"]
-    kappa = tau / (dt * u["c"] * 1.0 * 1.0)   # tau = dt c_hat rho chi(nu=1) kappa
-    st = _state(seed, cells, edges, T, 0.5, 2.0, 1e-3, u["c"], u["a_rad"])
-    return Workload("config2", cells.size, edges, chi_lo, alpha, kappa, st, T,
-                    dt=dt, c_hat=u["c"], **u)
+    T = draw_T(name, cells, seed)
+    kappa = draw_kappa(name, cells, seed, dt, u["c"])
+    st = _state(seed, cells, edges, T, *TRAD_RANGE, sp["vmax"], u["c"], u["a_rad"])
+    return Workload(name, cells.size, edges, chi_lo, alpha, kappa, st, T, dt=dt, c_hat=u["c"],
+                    **u)
+
+
+def config0(cells=None, seed=None, n=None):
+    return make("config0", cells, seed, n)
+
+
+def config1(cells=None, seed=None, n=None, ng=None):
+    return make("config1", cells, seed, n, ng)
+
+
+def config2(cells=None, seed=None, n=None, ng=None, units=None):
+    return make("config2", cells, seed, n, ng, units)
 
 
 def subset(w: Workload, idx) -> Workload:

@@ -1,0 +1,82 @@
+"""The device-side Planck and group-mean routines, compiled for the host with
+hipcc, pinned against mpmath (polylogarithms, Bernoulli numbers, quadrature).
+CPU only: this checks the formulas and constants of the kernels' math; the
+GPU parity tests check the device build."""
+import ctypes as C
+import os
+import shutil
+import subprocess
+
+import mpmath as mp
+import numpy as np
+import pytest
+
+import mp_ref
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "hostbuild", "device_math_host.hip")
+
+
+@pytest.fixture(scope="module")
+def dm(tmp_path_factory):
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    out = str(tmp_path_factory.mktemp("dm") / "libdm.so")
+    subprocess.run([hipcc, "-O2", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
+                    "-o", out, SRC], check=True, capture_output=True)
+    L = C.CDLL(out)
+    dp = C.POINTER(C.c_double)
+    L.dm_edge.argtypes = [C.c_double, dp]
+    L.dm_group.argtypes = [C.c_double, C.c_double, dp]
+    L.dm_mean_ratio.restype = C.c_double
+    L.dm_mean_ratio.argtypes = [C.c_double, C.c_double, C.c_double]
+    L.dm_bern.restype = C.c_double
+    L.dm_bern.argtypes = [C.c_int]
+    return L
+
+
+def _call(fn, *args, n=5):
+    out = np.zeros(n)
+    fn(*args, out.ctypes.data_as(C.POINTER(C.c_double)))
+    return out
+
+
+def test_bernoulli_coefficients(dm):
+    for m in range(1, 20):
+        ref = mp.bernoulli(2 * m) / mp.factorial(2 * m)
+        assert abs(dm.dm_bern(m) - ref) <= 2e-16 * abs(ref), m
+
+
+@pytest.mark.parametrize("x", [0.0, 1e-4, 0.3, 1.0, 1.9, 2.0, 2.01, 3.5, 8.0, 30.0, 300.0, 5000.0])
+def test_edge_values(dm, x):
+    val, eps, u, wien = _call(dm.dm_edge, x, n=4)
+    if x <= 2.0:
+        assert wien == 0.0
+        p = 1 - mp_ref.Q_polylog(x) if x > 0 else 0
+        assert abs(val - p) <= 2e-15 * p + 1e-300
+        assert abs(eps - mp_ref.edge_term(x)) <= 2e-15 * mp_ref.edge_term(x) + 1e-300
+    else:
+        qs = mp_ref.Q_polylog(x) * mp.exp(x)
+        assert abs(val - qs) <= 2e-15 * qs
+        es = mp_ref.edge_term(x) * mp.exp(x)
+        assert abs(eps - es) <= 2e-15 * es
+
+
+@pytest.mark.parametrize("xl,xh", [(1e-3, 0.03), (0.5, 1.5), (1.5, 2.5), (1.9, 2.1), (2.5, 6.0),
+                                   (40.0, 60.0), (0.0, float("inf")), (3.0, float("inf"))])
+def test_group_values(dm, xl, xh):
+    b, elo, ehi, sig, scale = _call(dm.dm_group, xl, xh)
+    ref = mp_ref.group_fraction(xl, xh)
+    assert abs(b * scale - ref) <= 1e-13 * ref
+    assert abs(elo * scale - mp_ref.edge_term(xl)) <= 2e-15 * mp_ref.edge_term(xl) + 1e-300
+    assert abs(ehi * scale - mp_ref.edge_term(xh)) <= 2e-15 * mp_ref.edge_term(xh) + 1e-300
+
+
+@pytest.mark.parametrize("ac,aq,L", [(-2.0, -1.0, 3.45), (1.7, -1.0, 0.86), (-3.2, 0.4, 0.216),
+                                     (0.0, 0.7, 1.0), (2.0, -3.0, 1.0), (-2.0, 4000.0, 0.216)])
+def test_mean_ratio(dm, ac, aq, L):
+    num = mp.quad(lambda u: mp.exp((ac + aq + 1) * u), [0, L])
+    den = mp.quad(lambda u: mp.exp((aq + 1) * u), [0, L])
+    ref = num / den
+    assert abs(dm.dm_mean_ratio(ac, aq, L) - ref) <= 1e-13 * ref
