@@ -291,10 +291,11 @@ static void solve_cell(const problem* p, work* w, int64_t i) {
       dW += fabs(p->chat * p->dt * (1.0 + p->achi[g]) * w->chiF[g] * (vf_new - vf_old)) /
             (p->c * p->c);
     }
-    /* READING: the next inner pass starts from this pass's temperature, so
-     * its E_gas iterate carries the change of the kinetic energy */
+    /* READING: the next inner pass starts from the temperature of this
+     * outer stage, i.e. from the conservatively updated E_gas carrying the
+     * change of the kinetic energy, and from this pass's R_g */
     double ke_new = 0.5 * rho * (vn[0] * vn[0] + vn[1] * vn[1] + vn[2] * vn[2]);
-    egv += ke_new - ke;
+    egv = egas_new + (ke_new - ke);
     v[0] = vn[0];
     v[1] = vn[1];
     v[2] = vn[2];
