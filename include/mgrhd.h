@@ -141,6 +141,64 @@ int mgrhd_get_variant(int32_t n_groups, int32_t mean_mode, int32_t* lanes_per_ce
                       int32_t* groups_per_lane);
 int mgrhd_set_variant(int32_t n_groups, int32_t lanes_per_cell, int32_t groups_per_lane);
 
+/* ---- Batched AMR-like patches: one persistent launch over many patches ----
+ * Each patch holds its own SoA block (same layout as mgrhd_source_update,
+ * with its own n_cells), its own group count (1..128), edges and opacity
+ * table; dt and c_hat are per patch, the options per batch.  All pointers are
+ * DEVICE pointers owned by the caller and must stay valid while the batch is
+ * used.  The patches are cut into work items of at most `chunk_cells` cells,
+ * ordered by decreasing group count; waves take items from a global counter
+ * (cleared by a tiny kernel before the solver kernel, so the pair can be
+ * captured in a hipGraph) and run the per-cell solver of mgrhd_source_update
+ * with lanes per cell = next power of two >= N_g / groups_per_lane.
+ * A batch owns a small device work list and counter (allocated by
+ * mgrhd_batch_create, freed by mgrhd_batch_destroy); runs of one batch on
+ * several streams at once race on that counter. */
+typedef struct {
+  double* E_g;                /* [N_g][n] in/out */
+  double* F_g;                /* [3][N_g][n] in/out */
+  const double* rho;          /* [n] */
+  double* e_gas;              /* [n] in/out */
+  double* v;                  /* [3][n] in/out */
+  const double* kappa_scale;  /* [n] or NULL */
+  const double* S_g;          /* [N_g][n] or NULL */
+  const double* guess;        /* [N_g+1][n] warm start or NULL */
+  int32_t* iters;             /* [n] or NULL */
+  int32_t* outer;             /* [n] or NULL */
+  int32_t* status;            /* [n] or NULL */
+  const double* group_edges;  /* [N_g+1] */
+  const double* chi_lo;       /* [N_g] */
+  const double* alpha_chi;    /* [N_g] or NULL */
+  const double* chi_hi;       /* [N_g] or NULL */
+  int64_t n_cells;
+  int32_t n_groups;
+  int32_t reserved;
+  double dt;
+  double c_hat;
+} mgrhd_patch;
+
+typedef struct mgrhd_batch mgrhd_batch;
+
+/* Validate the descriptors (host array of n_patches) and build the batch.
+ * Returns 0 or MGRHD_E_*; *out is NULL on error. */
+int mgrhd_batch_create(const mgrhd_patch* patches, int32_t n_patches, int32_t mean_mode,
+                       const mgrhd_options* opt, mgrhd_batch** out);
+/* Tuning knobs (see the autotuner): groups per lane (2 or 4), resident
+ * workgroups per CU (0 = as many as fit), cells per work item. */
+int mgrhd_batch_set_tuning(mgrhd_batch* b, int32_t groups_per_lane, int32_t blocks_per_cu,
+                           int64_t chunk_cells);
+int mgrhd_batch_get_tuning(const mgrhd_batch* b, int32_t* groups_per_lane,
+                           int32_t* blocks_per_cu, int64_t* chunk_cells);
+/* Enqueue the counter reset and the persistent solver on `stream`. */
+int mgrhd_batch_run(mgrhd_batch* b, mgrhd_stream_t stream);
+/* Capture mgrhd_batch_run into a hipGraph kept by the batch; launch replays
+ * it (capturing on first use). */
+int mgrhd_batch_capture(mgrhd_batch* b, mgrhd_stream_t stream);
+int mgrhd_batch_launch(mgrhd_batch* b, mgrhd_stream_t stream);
+/* Total cells of the batch. */
+int64_t mgrhd_batch_cells(const mgrhd_batch* b);
+void mgrhd_batch_destroy(mgrhd_batch* b);
+
 /* Library version string. */
 const char* mgrhd_version(void);
 

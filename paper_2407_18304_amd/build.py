@@ -18,11 +18,14 @@ HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed FP32 instructions anywhere in this library
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # keep loop-invariant FP64 constants (polynomial and exp coefficients) out of
+    # registers across the persistent loop: rematerialising them is cheaper
+    "-mllvm", "-disable-machine-licm",
     "-Wno-unused-command-line-argument", "-I", os.path.join(ROOT, "include"),
 ]
 
 LIBS = {
-    "libmgrhd.so": ["source_update.hip"],
+    "libmgrhd.so": ["source_update.hip", "batch.hip"],
     "libmgrhd_synth.so": ["synth.hip"],
 }
 

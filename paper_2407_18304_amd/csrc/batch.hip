@@ -1,0 +1,459 @@
+// batch.hip -- one persistent launch over many AMR-like patches, each with its
+// own cell count, group count, group edges and opacity table (the patch
+// layout of an adaptive mesh, where every patch holds its own SoA block).
+//
+// Work list: the patches are cut into items of at most `chunk` cells, ordered
+// by decreasing group count (the costliest work first, so the tail of the
+// launch is made of cheap items).  A wave takes the next item with one atomic
+// increment of a global counter, stages that patch's tables in its own LDS
+// slot, sets its lane count per cell to the next power of two >= N_g/G, and
+// runs the same per-cell state machine as the single-table kernel (cell
+// groups refill from the item's cells as their cells finish).  A tiny kernel
+// clears the counter before the persistent kernel, so the pair can be
+// captured in a hipGraph and replayed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/mgrhd.h"
+#include "solver_device.hpp"
+
+namespace mgrhd {
+
+constexpr int kBatchNGM = 128;  // group capacity of a wave's LDS table slot
+
+struct Item {
+  int32_t patch;
+  int32_t pad;
+  int64_t c0, c1;
+};
+
+struct BatchArgs {
+  const KArgs* patches;  // device array, one KArgs per patch
+  const Item* items;     // device array
+  int32_t* counter;      // device, cleared before each launch
+  int64_t n_items;
+};
+
+__global__ void k_clear_counter(int32_t* counter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Stage the tables of one patch into this wave's LDS slot (wave scope).
+template <int MODE>
+__device__ __forceinline__ bool stage_tables_wave(const KArgs& a, Tables<kBatchNGM>& t, int lane) {
+  if (lane == 0) t.bad = 0;
+  wave_sync();
+  const int ng = a.ng;
+  if (ng > kBatchNGM) {
+    t.bad = 1;
+    wave_sync();
+    return false;
+  }
+  for (int g = lane; g <= ng; g += kWave) {
+    const double nu = a.edges[g];
+    t.nu[g] = nu;
+    bool ok = nu >= 0.0;
+    if (MODE != MGRHD_MEAN_PC) ok = ok && nu > 0.0 && !is_pinf(nu);
+    if (!ok) atomicOr(&t.bad, 1);
+  }
+  wave_sync();
+  for (int g = lane; g < ng; g += kWave) {
+    const double lo = t.nu[g], hi = t.nu[g + 1];
+    const double chl = a.chi_lo[g];
+    bool ok = hi > lo && chl > 0.0 && !is_pinf(chl);
+    double L = 0.0, ac = 0.0, mf = 1.0, rac = 1.0, ldn = 0.0, lc = 0.0;
+    if (MODE != MGRHD_MEAN_PC) {
+      L = log(hi / lo);
+      if (a.alpha) {
+        ac = a.alpha[g];
+      } else {
+        const double chh = a.chi_hi[g];
+        ok = ok && chh > 0.0 && !is_pinf(chh);
+        ac = log(chh / chl) / L;
+      }
+      ok = ok && isfinite(ac);
+      mf = mean_ratio(ac, -1.0, L);
+      rac = exp(ac * L);
+      ldn = log(hi - lo);
+      lc = 0.5 * (log(lo) + log(hi));
+    }
+    t.lnr[g] = L;
+    t.achi[g] = ac;
+    t.chit[g] = chl;
+    t.mfix[g] = mf;
+    t.rac[g] = rac;
+    t.lndnu[g] = ldn;
+    t.lnc[g] = lc;
+    if (!ok) atomicOr(&t.bad, 1);
+  }
+  wave_sync();
+  return t.bad == 0;
+}
+
+template <int G, int MODE>
+__global__ __launch_bounds__(kBlock, 2) void k_batch(BatchArgs b) {
+  __shared__ Tables<kBatchNGM> tabs[kBlock / kWave];
+  const int lane = threadIdx.x % kWave;
+  Tables<kBatchNGM>& tab = tabs[threadIdx.x / kWave];
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+
+  CellState<G> s;
+  s.phase = P_IDLE;
+  s.i = -1;
+  s.lpc = 1;
+  Cache<G> c;
+  int cur_patch = -1;
+  bool table_ok = false;
+  int64_t next = 0, hi = 0;
+  const KArgs* ap = b.patches;
+  int j = 0;
+  for (;;) {
+    // all cell groups idle: take the next work item
+    if (__ballot(s.phase != P_IDLE) == 0) {
+      int it = 0;
+      if (lane == 0) it = atomicAdd(b.counter, 1);
+      it = __shfl(it, 0, kWave);
+      if (it >= b.n_items) break;
+      const Item item = b.items[it];
+      ap = b.patches + item.patch;
+      if (item.patch != cur_patch) {
+        table_ok = stage_tables_wave<MODE>(*ap, tab, lane);
+        cur_patch = item.patch;
+      }
+      int lpc = 1;
+      while (lpc * G < ap->ng) lpc <<= 1;
+      s.lpc = lpc;
+      j = lane % lpc;
+      next = item.c0;
+      hi = item.c1;
+      if (!table_ok) {
+        for (int64_t i = next + lane; i < hi; i += kWave) {
+          if (ap->status) ap->status[i] = MGRHD_ST_BAD_TABLE;
+          if (ap->iters) ap->iters[i] = 0;
+          if (ap->outer) ap->outer[i] = 0;
+        }
+        continue;
+      }
+      s.phase = P_EMPTY;
+    }
+    const KArgs& a = *ap;
+    // refill from the item
+    const bool need = s.phase == P_EMPTY;
+    const uint64_t m = __ballot(need && j == 0);
+    if (m) {
+      const int rank = __popcll(m & below);
+      int64_t mine = next + rank;
+      next += __popcll(m);
+      mine = __shfl(mine, lane - j, kWave);
+      if (need) {
+        if (mine < hi) {
+          load_cell<G, 0, MODE, kBatchNGM>(a, tab, j, mine, s);
+          if (s.phase == P_EMPTY) finish_cell<G, 0>(a, j, s, false);
+        } else {
+          s.phase = P_IDLE;
+        }
+      }
+    }
+    if (s.phase != P_NEWTON && s.phase != P_FLUX) continue;
+
+    const double T = ((s.phase == P_FLUX ? s.egas_new : s.egv) - s.ke) / (s.rho * a.cv);
+    if (!(T > 0.0) || !isfinite(T)) {
+      if (s.phase == P_NEWTON)
+        newton_done<G, 0>(a, j, s, 2);
+      else {
+        s.st |= MGRHD_ST_INVALID;
+        finish_cell<G, 0>(a, j, s, false);
+      }
+      continue;
+    }
+    double Ecur[G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) Ecur[k] = s.E0[k] + s.R[k];
+    const double aT4 = a.a * (T * T) * (T * T);
+    evaluate<G, 0, MODE, kBatchNGM>(tab, a.ng, j, T, aT4, a.hk, s.rho_kappa, Ecur, s.chiK, c);
+    if (s.phase == P_FLUX) {
+      if (!flux_step<G, 0, MODE, kBatchNGM>(a, tab, j, s, c)) continue;
+    }
+    newton_step<G, 0, MODE, kBatchNGM>(a, tab, j, s, c);
+  }
+}
+
+using BatchFn = void (*)(BatchArgs);
+static const int kBatchG[] = {2, 4};
+static BatchFn batch_fn(int g, int mode) {
+  static const BatchFn fns[2][3] = {
+      {k_batch<2, MGRHD_MEAN_PC>, k_batch<2, MGRHD_MEAN_PPL_FIXED>, k_batch<2, MGRHD_MEAN_PPL_FREE>},
+      {k_batch<4, MGRHD_MEAN_PC>, k_batch<4, MGRHD_MEAN_PPL_FIXED>, k_batch<4, MGRHD_MEAN_PPL_FREE>}};
+  return fns[g == 4 ? 1 : 0][mode];
+}
+
+}  // namespace mgrhd
+
+using namespace mgrhd;
+
+struct mgrhd_batch {
+  int32_t n_patches = 0;
+  int32_t mode = 0;
+  int64_t n_cells = 0;
+  int32_t max_groups = 0;
+  KArgs* d_patches = nullptr;
+  Item* d_items = nullptr;
+  int32_t* d_counter = nullptr;
+  int64_t n_items = 0;
+  std::vector<KArgs> h_patches;
+  // tuning
+  int32_t groups_per_lane = 4;
+  int32_t blocks_per_cu = 0;  // 0 = all resident
+  int64_t chunk = 2048;
+  bool items_dirty = true;
+  // graph
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+static int build_items(mgrhd_batch* bt) {
+  std::vector<Item> items;
+  std::vector<int32_t> order(bt->n_patches);
+  for (int32_t p = 0; p < bt->n_patches; ++p) order[p] = p;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+    return bt->h_patches[x].ng > bt->h_patches[y].ng;
+  });
+  for (int32_t p : order) {
+    const int64_t n = bt->h_patches[p].n;
+    for (int64_t c0 = 0; c0 < n; c0 += bt->chunk)
+      items.push_back(Item{p, 0, c0, std::min(n, c0 + bt->chunk)});
+  }
+  if (bt->d_items) hipFree(bt->d_items);
+  bt->d_items = nullptr;
+  bt->n_items = (int64_t)items.size();
+  if (!items.empty()) {
+    if (hipMalloc(&bt->d_items, sizeof(Item) * items.size()) != hipSuccess) return MGRHD_E_DEVICE;
+    if (hipMemcpy(bt->d_items, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice) !=
+        hipSuccess)
+      return MGRHD_E_DEVICE;
+  }
+  bt->items_dirty = false;
+  return 0;
+}
+
+static void drop_graph(mgrhd_batch* bt) {
+  if (bt->exec) hipGraphExecDestroy(bt->exec);
+  if (bt->graph) hipGraphDestroy(bt->graph);
+  bt->exec = nullptr;
+  bt->graph = nullptr;
+}
+
+extern "C" {
+
+int mgrhd_batch_create(const mgrhd_patch* patches, int32_t n_patches, int32_t mean_mode,
+                       const mgrhd_options* opt_in, mgrhd_batch** out) {
+  if (!out) return MGRHD_E_NULL;
+  *out = nullptr;
+  if (n_patches < 0 || (n_patches > 0 && !patches)) return MGRHD_E_NULL;
+  if (mean_mode < 0 || mean_mode > 2) return MGRHD_E_MODE;
+  mgrhd_options defaults;
+  mgrhd_default_options(&defaults);
+  const mgrhd_options* opt = opt_in ? opt_in : &defaults;
+  if (opt->closure < 0 || opt->closure > 1) return MGRHD_E_MODE;
+  auto pos = [](double x) { return x > 0.0 && std::isfinite(x); };
+  if (!pos(opt->c) || !pos(opt->a_rad) || !pos(opt->h_over_k) || !pos(opt->c_v))
+    return MGRHD_E_SCALAR;
+  if (!pos(opt->eps_newton) || !pos(opt->eps_outer) || opt->max_newton < 1 ||
+      opt->max_outer < 1 || opt->polish < 0 || opt->polish > 4)
+    return MGRHD_E_OPTION;
+  mgrhd_batch* bt = new (std::nothrow) mgrhd_batch();
+  if (!bt) return MGRHD_E_DEVICE;
+  bt->n_patches = n_patches;
+  bt->mode = mean_mode;
+  bt->h_patches.resize(n_patches);
+  for (int32_t p = 0; p < n_patches; ++p) {
+    const mgrhd_patch& q = patches[p];
+    if (q.n_cells < 0 || q.n_groups < 1 || q.n_groups > kBatchNGM) {
+      delete bt;
+      return MGRHD_E_SIZE;
+    }
+    if (q.n_cells > 0 && (!q.E_g || !q.F_g || !q.rho || !q.e_gas || !q.v || !q.group_edges ||
+                          !q.chi_lo)) {
+      delete bt;
+      return MGRHD_E_NULL;
+    }
+    if (mean_mode != MGRHD_MEAN_PC && !q.alpha_chi && !q.chi_hi) {
+      delete bt;
+      return MGRHD_E_TABLE;
+    }
+    if (!pos(q.dt) || !pos(q.c_hat)) {
+      delete bt;
+      return MGRHD_E_SCALAR;
+    }
+    KArgs& a = bt->h_patches[p];
+    std::memset(&a, 0, sizeof(a));
+    a.E = q.E_g;
+    a.F = q.F_g;
+    a.rho = q.rho;
+    a.egas = q.e_gas;
+    a.v = q.v;
+    a.kappa = q.kappa_scale;
+    a.S = q.S_g;
+    a.guess = q.guess;
+    a.iters = q.iters;
+    a.outer = q.outer;
+    a.status = q.status;
+    a.edges = q.group_edges;
+    a.chi_lo = q.chi_lo;
+    a.alpha = q.alpha_chi;
+    a.chi_hi = q.chi_hi;
+    a.n = q.n_cells;
+    a.ng = q.n_groups;
+    a.closure = opt->closure;
+    a.dt = q.dt;
+    a.chat = q.c_hat;
+    a.c = opt->c;
+    a.a = opt->a_rad;
+    a.hk = opt->h_over_k;
+    a.cv = opt->c_v;
+    a.eps = opt->eps_newton;
+    a.eps_out = opt->eps_outer;
+    a.max_newton = opt->max_newton;
+    a.max_outer = opt->max_outer;
+    a.polish = opt->polish;
+    bt->n_cells += q.n_cells;
+    bt->max_groups = std::max(bt->max_groups, q.n_groups);
+  }
+  if (n_patches > 0) {
+    if (hipMalloc(&bt->d_patches, sizeof(KArgs) * n_patches) != hipSuccess ||
+        hipMemcpy(bt->d_patches, bt->h_patches.data(), sizeof(KArgs) * n_patches,
+                  hipMemcpyHostToDevice) != hipSuccess) {
+      mgrhd_batch_destroy(bt);
+      return MGRHD_E_DEVICE;
+    }
+  }
+  if (hipMalloc(&bt->d_counter, sizeof(int32_t)) != hipSuccess) {
+    mgrhd_batch_destroy(bt);
+    return MGRHD_E_DEVICE;
+  }
+  const int rc = build_items(bt);
+  if (rc) {
+    mgrhd_batch_destroy(bt);
+    return rc;
+  }
+  *out = bt;
+  return 0;
+}
+
+int mgrhd_batch_set_tuning(mgrhd_batch* bt, int32_t groups_per_lane, int32_t blocks_per_cu,
+                           int64_t chunk_cells) {
+  if (!bt) return MGRHD_E_NULL;
+  if (groups_per_lane != 2 && groups_per_lane != 4) return MGRHD_E_OPTION;
+  if (blocks_per_cu < 0 || chunk_cells < 1) return MGRHD_E_OPTION;
+  if (bt->max_groups > groups_per_lane * 64) return MGRHD_E_OPTION;
+  const bool changed = groups_per_lane != bt->groups_per_lane ||
+                       blocks_per_cu != bt->blocks_per_cu || chunk_cells != bt->chunk;
+  bt->groups_per_lane = groups_per_lane;
+  bt->blocks_per_cu = blocks_per_cu;
+  if (chunk_cells != bt->chunk) {
+    bt->chunk = chunk_cells;
+    bt->items_dirty = true;
+  }
+  if (changed) drop_graph(bt);
+  return 0;
+}
+
+int mgrhd_batch_get_tuning(const mgrhd_batch* bt, int32_t* groups_per_lane,
+                           int32_t* blocks_per_cu, int64_t* chunk_cells) {
+  if (!bt) return MGRHD_E_NULL;
+  if (groups_per_lane) *groups_per_lane = bt->groups_per_lane;
+  if (blocks_per_cu) *blocks_per_cu = bt->blocks_per_cu;
+  if (chunk_cells) *chunk_cells = bt->chunk;
+  return 0;
+}
+
+static int enqueue(mgrhd_batch* bt, hipStream_t stream) {
+  if (bt->items_dirty) {
+    const int rc = build_items(bt);
+    if (rc) return rc;
+  }
+  if (bt->n_items == 0) return 0;
+  BatchFn fn = batch_fn(bt->groups_per_lane, bt->mode);
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kBlock, 0) != hipSuccess || nb < 1)
+    nb = 1;
+  if (bt->blocks_per_cu > 0 && bt->blocks_per_cu < nb) nb = bt->blocks_per_cu;
+  int dev = 0, cus = 256;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    cus = prop.multiProcessorCount;
+  int64_t blocks = (int64_t)cus * nb;
+  const int64_t waves_needed = bt->n_items;
+  if (blocks * (kBlock / kWave) > waves_needed) blocks = (waves_needed + 3) / 4;
+  hipLaunchKernelGGL(k_clear_counter, dim3(1), dim3(64), 0, stream, bt->d_counter);
+  BatchArgs args{bt->d_patches, bt->d_items, bt->d_counter, bt->n_items};
+  hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(kBlock), 0, stream, args);
+  const hipError_t err = hipGetLastError();
+  return err == hipSuccess ? 0 : (int)err;
+}
+
+int mgrhd_batch_run(mgrhd_batch* bt, mgrhd_stream_t stream) {
+  if (!bt) return MGRHD_E_NULL;
+  return enqueue(bt, (hipStream_t)stream);
+}
+
+int mgrhd_batch_capture(mgrhd_batch* bt, mgrhd_stream_t stream) {
+  if (!bt) return MGRHD_E_NULL;
+  drop_graph(bt);
+  if (bt->items_dirty) {
+    const int rc = build_items(bt);
+    if (rc) return rc;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return (int)e;
+  const int rc = enqueue(bt, st);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(st, &g);
+  if (rc) {
+    if (g) hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return (int)e;
+  bt->graph = g;
+  e = hipGraphInstantiate(&bt->exec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    drop_graph(bt);
+    return (int)e;
+  }
+  return 0;
+}
+
+int mgrhd_batch_launch(mgrhd_batch* bt, mgrhd_stream_t stream) {
+  if (!bt) return MGRHD_E_NULL;
+  if (!bt->exec) {
+    const int rc = mgrhd_batch_capture(bt, stream);
+    if (rc) return rc;
+  }
+  const hipError_t e = hipGraphLaunch(bt->exec, (hipStream_t)stream);
+  return e == hipSuccess ? 0 : (int)e;
+}
+
+int64_t mgrhd_batch_cells(const mgrhd_batch* bt) { return bt ? bt->n_cells : -1; }
+
+void mgrhd_batch_destroy(mgrhd_batch* bt) {
+  if (!bt) return;
+  drop_graph(bt);
+  if (bt->d_patches) hipFree(bt->d_patches);
+  if (bt->d_items) hipFree(bt->d_items);
+  if (bt->d_counter) hipFree(bt->d_counter);
+  delete bt;
+}
+
+}  // extern "C"

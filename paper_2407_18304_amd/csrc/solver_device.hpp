@@ -1,0 +1,568 @@
+// solver_device.hpp -- device side of the multigroup source update shared by
+// the single-table kernel (source_update.hip) and the batched patch kernel
+// (batch.hip): group tables in LDS, material evaluation, the Newton and
+// outer-stage consumers, and the per-cell state machine.
+//
+// A "cell group" of LPC consecutive lanes owns one cell; lane j of the group
+// owns groups j*G .. j*G+G-1.  The lane count per cell is a template
+// parameter in the single-table kernel and a run-time value (uniform over the
+// wave) in the batched kernel: LPC = 0 in the templates below means "read
+// lpc at run time".
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "../../include/mgrhd.h"
+#include "planck_device.hpp"
+
+namespace mgrhd {
+
+struct KArgs {
+  double* E;
+  double* F;
+  const double* rho;
+  double* egas;
+  double* v;
+  const double* kappa;
+  const double* S;
+  const double* guess;
+  int32_t* iters;
+  int32_t* outer;
+  int32_t* status;
+  const double* edges;
+  const double* chi_lo;
+  const double* alpha;
+  const double* chi_hi;
+  int64_t n;
+  int32_t ng;
+  int32_t closure;
+  double dt, chat, c, a, hk, cv, eps, eps_out;
+  int32_t max_newton, max_outer, polish, pad;
+};
+
+constexpr int kBlock = 256;
+constexpr int kWave = 64;
+
+// LDS copy of the group tables with per-group constants (NGM = G * LPC).
+template <int NGM>
+struct Tables {
+  double nu[NGM + 1];
+  double lnr[NGM];    // ln(nu_g+ / nu_g-)
+  double achi[NGM];   // opacity powerlaw index (0 in PC)
+  double chit[NGM];   // chi_lo table entry (per unit rho * kappa)
+  double mfix[NGM];   // PPL-fixed mean ratio chi_0B/chi_0,g- = chi_0E/chi_0,g-
+  double rac[NGM];    // r_g^alpha_chi
+  double lndnu[NGM];  // ln(nu_g+ - nu_g-)
+  double lnc[NGM];    // (ln nu_g- + ln nu_g+)/2
+  int bad;
+};
+
+// Sum over the lanes of one cell group (bit-identical in every lane).  LPC = 0:
+// the group size lpc is a run-time value, uniform over the wave.
+template <int LPC>
+__device__ __forceinline__ double cell_sum(double v, int lpc) {
+  if (LPC > 0) {
+#pragma unroll
+    for (int m = 1; m < LPC; m <<= 1) v += __shfl_xor(v, m, kWave);
+  } else {
+    for (int m = 1; m < lpc; m <<= 1) v += __shfl_xor(v, m, kWave);
+  }
+  return v;
+}
+
+template <int NGM, int MODE>
+__device__ __forceinline__ bool stage_tables(const KArgs& a, Tables<NGM>& t) {
+  if (threadIdx.x == 0) t.bad = 0;
+  __syncthreads();
+  const int ng = a.ng;
+  for (int g = threadIdx.x; g <= ng; g += blockDim.x) {
+    const double nu = a.edges[g];
+    t.nu[g] = nu;
+    bool ok = nu >= 0.0;
+    if (MODE != MGRHD_MEAN_PC) ok = ok && nu > 0.0 && !is_pinf(nu);
+    if (!ok) atomicOr(&t.bad, 1);
+  }
+  __syncthreads();
+  for (int g = threadIdx.x; g < ng; g += blockDim.x) {
+    const double lo = t.nu[g], hi = t.nu[g + 1];
+    const double chl = a.chi_lo[g];
+    bool ok = hi > lo && chl > 0.0 && !is_pinf(chl);
+    double L = 0.0, ac = 0.0, mf = 1.0, rac = 1.0, ldn = 0.0, lc = 0.0;
+    if (MODE != MGRHD_MEAN_PC) {
+      L = log(hi / lo);
+      if (a.alpha) {
+        ac = a.alpha[g];
+      } else {
+        const double chh = a.chi_hi[g];
+        ok = ok && chh > 0.0 && !is_pinf(chh);
+        ac = log(chh / chl) / L;  // tabulated opacity: index from the edge values
+      }
+      ok = ok && isfinite(ac);
+      mf = mean_ratio(ac, -1.0, L);
+      rac = exp(ac * L);
+      ldn = log(hi - lo);
+      lc = 0.5 * (log(lo) + log(hi));
+    }
+    t.lnr[g] = L;
+    t.achi[g] = ac;
+    t.chit[g] = chl;
+    t.mfix[g] = mf;
+    t.rac[g] = rac;
+    t.lndnu[g] = ldn;
+    t.lnc[g] = lc;
+    if (!ok) atomicOr(&t.bad, 1);
+  }
+  __syncthreads();
+  return t.bad == 0;
+}
+
+// Material data of this lane's groups at one temperature.
+template <int G>
+struct Cache {
+  double Bt[G];    // B~_g
+  double dBdT[G];  // dB~_g/dT
+  double chiF[G];  // flux mean (eq. chiDiff)
+  double emit[G];  // chi_0B B~_g - Delta_g(nu chi_0 B~)/3  (flux source, eq. numF1)
+  double chiB[G];  // PPL-free only (otherwise the per-cell constants)
+  double chiE[G];
+};
+
+template <int G, int LPC, int NGM>
+__device__ __forceinline__ void slopes_free(const Tables<NGM>& t, int ng, int j, const double* lq,
+                                            double* alpha) {
+  const int lane = __lane_id();
+  const double left = __shfl(lq[G - 1], lane > 0 ? lane - 1 : 0, kWave);
+  const double right = __shfl(lq[0], lane < kWave - 1 ? lane + 1 : kWave - 1, kWave);
+#pragma unroll
+  for (int k = 0; k < G; ++k) {
+    const int g = j * G + k;
+    alpha[k] = -1.0;
+    if (g <= 0 || g >= ng - 1) continue;
+    const double lm = (k == 0) ? left : lq[k - 1];
+    const double lp = (k == G - 1) ? right : lq[k + 1];
+    const double sl = (lq[k] - lm) / (t.lnc[g] - t.lnc[g - 1]);
+    const double sr = (lp - lq[k]) / (t.lnc[g + 1] - t.lnc[g]);
+    if (isnan(sl) || isnan(sr)) continue;
+    const double m = minmod(sl, sr);
+    if (isfinite(m)) alpha[k] = m;
+  }
+}
+
+// One material evaluation: Planck data, slopes (PPL-free), group means.
+// chiK holds the per-cell constant chi_0E (= chi_0B) of PC and PPL-fixed.
+template <int G, int LPC, int MODE, int NGM>
+__device__ __forceinline__ void evaluate(const Tables<NGM>& t, int ng, int j, double T, double aT4,
+                                         double hk, double rho_kappa, const double* Ecur,
+                                         const double* chiK, Cache<G>& c) {
+  const double invT = 1.0 / T;
+  const double hkT = hk * invT;
+  Edge lo = planck_edge(hkT * t.nu[min(j * G, ng)]);
+  if (MODE != MGRHD_MEAN_PPL_FREE) {
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      const int g = j * G + k;
+      if (g >= ng) break;
+      const Edge hi = planck_edge(hkT * t.nu[g + 1]);
+      const GroupPlanck p = group_planck(lo, hi);
+      lo = hi;
+      const double Bt = aT4 * p.b * p.scale;
+      const double Dnu = aT4 * (p.ehi - p.elo) * p.scale;
+      c.Bt[k] = Bt;
+      c.dBdT[k] = (4.0 * Bt - Dnu) * invT;
+      const double ch = chiK[k];
+      if (MODE == MGRHD_MEAN_PC) {
+        c.chiF[k] = ch;
+        c.emit[k] = ch * (Bt - Dnu / 3.0);
+      } else {
+        const double ac = t.achi[g];
+        const double dchib = rho_kappa * t.chit[g] * (t.rac[g] * p.ehi - p.elo);
+        const double num = (ch + ch / 3.0) * p.b + (ac * ch * p.b - dchib) / 3.0;
+        const double den = (4.0 * p.b - (p.ehi - p.elo)) / 3.0;
+        const double f = num / den;
+        c.chiF[k] = (den > 0.0 && isfinite(f)) ? f : ch;
+        c.emit[k] = ch * Bt - aT4 * dchib * p.scale / 3.0;
+      }
+    }
+  } else {
+    double b[G], elo[G], ehi[G], sig[G], scale[G], lqB[G], lqE[G], aB[G], aE[G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      const int g = j * G + k;
+      lqB[k] = -INFINITY;
+      lqE[k] = -INFINITY;
+      b[k] = elo[k] = ehi[k] = sig[k] = 0.0;
+      scale[k] = 1.0;
+      if (g >= ng) continue;
+      const Edge hi = planck_edge(hkT * t.nu[g + 1]);
+      const GroupPlanck p = group_planck(lo, hi);
+      lo = hi;
+      b[k] = p.b;
+      elo[k] = p.elo;
+      ehi[k] = p.ehi;
+      sig[k] = p.sigma;
+      scale[k] = p.scale;
+      if (p.b > 0.0) lqB[k] = log(p.b) - p.sigma - t.lndnu[g];
+      if (Ecur[k] > 0.0) lqE[k] = log(Ecur[k]) - t.lndnu[g];
+    }
+    slopes_free<G, LPC, NGM>(t, ng, j, lqB, aB);
+    slopes_free<G, LPC, NGM>(t, ng, j, lqE, aE);
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      const int g = j * G + k;
+      if (g >= ng) break;
+      const double ac = t.achi[g], L = t.lnr[g];
+      const double chl = rho_kappa * t.chit[g];
+      const double Bt = aT4 * b[k] * scale[k];
+      const double Dnu = aT4 * (ehi[k] - elo[k]) * scale[k];
+      c.Bt[k] = Bt;
+      c.dBdT[k] = (4.0 * Bt - Dnu) * invT;
+      const double chB = chl * mean_ratio(ac, aB[k], L);
+      const double chE = chl * mean_ratio(ac, aE[k], L);
+      c.chiB[k] = chB;
+      c.chiE[k] = chE;
+      const double dchib = chl * (t.rac[g] * ehi[k] - elo[k]);
+      const double num = (chB + chE / 3.0) * b[k] + (ac * chE * b[k] - dchib) / 3.0;
+      const double den = (4.0 * b[k] - (ehi[k] - elo[k])) / 3.0;
+      const double f = num / den;
+      c.chiF[k] = (den > 0.0 && isfinite(f)) ? f : chE;
+      c.emit[k] = chB * Bt - aT4 * dchib * scale[k] / 3.0;
+    }
+  }
+}
+
+// P_g . v of the group closure (Sec. 2.1: M1 per group, or Eddington)
+__device__ __forceinline__ void pressure_dot_v(int closure, double c, double E, double F0,
+                                               double F1, double F2, const double* v,
+                                               double* Pv) {
+  if (!(E > 0.0)) {
+    Pv[0] = Pv[1] = Pv[2] = 0.0;
+    return;
+  }
+  const double fm = sqrt(F0 * F0 + F1 * F1 + F2 * F2);
+  if (closure == MGRHD_CLOSURE_EDDINGTON || fm == 0.0) {
+    Pv[0] = E * v[0] / 3.0;
+    Pv[1] = E * v[1] / 3.0;
+    Pv[2] = E * v[2] / 3.0;
+    return;
+  }
+  double f = fm / (c * E);
+  f = f > 1.0 ? 1.0 : f;
+  const double chi = (3.0 + 4.0 * f * f) / (5.0 + 2.0 * sqrt(4.0 - 3.0 * f * f));
+  const double n0 = F0 / fm, n1 = F1 / fm, n2 = F2 / fm;
+  const double nv = n0 * v[0] + n1 * v[1] + n2 * v[2];
+  const double p = 0.5 * (1.0 - chi), q = 0.5 * (3.0 * chi - 1.0);
+  Pv[0] = E * (p * v[0] + q * n0 * nv);
+  Pv[1] = E * (p * v[1] + q * n1 * nv);
+  Pv[2] = E * (p * v[2] + q * n2 * nv);
+}
+
+enum Phase : int { P_EMPTY = 0, P_NEWTON = 1, P_FLUX = 2, P_IDLE = 3 };
+
+// Per-cell-group registers.
+template <int G>
+struct CellState {
+  int64_t i;
+  int lpc;  // lanes per cell (run-time copy of the template value)
+  int phase, st, steps, passes, k_out, polish_left;
+  bool warm, fell_back;
+  double rho, rho_kappa, egas0, etot, ke, egv, egas_new;
+  double v[3];
+  double R[G], E0[G], Fk[3][G];      // F_g^(t) and v^(t) stay in global memory
+  double chiK[G], itau[G], iJgg[G];  // PC / PPL-fixed constants
+};
+
+template <int G, int LPC, int MODE, int NGM>
+__device__ __forceinline__ void load_cell(const KArgs& a, const Tables<NGM>& t, int j, int64_t i,
+                          CellState<G>& s) {
+  const int64_t n = a.n;
+  const int ng = a.ng;
+  s.i = i;
+  s.st = MGRHD_ST_OK;
+  s.steps = 0;
+  s.passes = 1;
+  s.k_out = 0;
+  s.polish_left = -1;
+  s.fell_back = false;
+  s.rho = a.rho[i];
+  s.egas0 = a.egas[i];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) s.v[d] = a.v[(int64_t)d * n + i];
+  const double kap = a.kappa ? a.kappa[i] : 1.0;
+  bool ok = s.rho > 0.0 && isfinite(s.rho) && kap > 0.0 && isfinite(kap) && isfinite(s.egas0) &&
+            isfinite(s.v[0]) && isfinite(s.v[1]) && isfinite(s.v[2]);
+  s.rho_kappa = s.rho * kap;
+  const double cdt = a.chat * a.dt;
+  double sumE = 0.0;
+#pragma unroll
+  for (int k = 0; k < G; ++k) {
+    const int g = j * G + k;
+    s.R[k] = 0.0;
+    s.E0[k] = 0.0;
+    s.chiK[k] = 1.0;
+    s.itau[k] = 0.0;
+    s.iJgg[k] = -1.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) s.Fk[d][k] = 0.0;
+    if (g < ng) {
+      const double e = a.E[(int64_t)g * n + i];
+      const double sg = a.S ? a.S[(int64_t)g * n + i] : 0.0;
+      ok = ok && e >= 0.0 && isfinite(e) && isfinite(sg);
+      s.E0[k] = e + sg;
+      sumE += e + sg;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const double f = a.F[((int64_t)d * ng + g) * n + i];
+        ok = ok && isfinite(f);
+        s.Fk[d][k] = f;
+      }
+      if (MODE != MGRHD_MEAN_PPL_FREE) {
+        const double chl = s.rho_kappa * t.chit[g];
+        const double ch = (MODE == MGRHD_MEAN_PC) ? chl : chl * t.mfix[g];
+        s.chiK[k] = ch;
+        s.itau[k] = 1.0 / (cdt * ch);
+        s.iJgg[k] = 1.0 / (-s.itau[k] - 1.0);
+      }
+    }
+  }
+  sumE = cell_sum<LPC>(sumE, s.lpc);
+  const double bad = cell_sum<LPC>(ok ? 0.0 : 1.0, s.lpc);
+  s.ke = 0.5 * s.rho * (s.v[0] * s.v[0] + s.v[1] * s.v[1] + s.v[2] * s.v[2]);
+  s.etot = s.egas0 + (a.chat / a.c) * sumE;  // E_tot of Sec. 3
+  ok = bad == 0.0 && (s.egas0 - s.ke) > 0.0 && s.etot > 0.0;
+  s.warm = a.guess != nullptr;
+  s.egv = s.egas0;
+  s.egas_new = s.egas0;
+  if (ok && s.warm) {
+    s.egv = a.guess[i];
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      const int g = j * G + k;
+      if (g < ng) s.R[k] = a.guess[(int64_t)(g + 1) * n + i];
+    }
+  }
+  if (ok) {
+    s.phase = P_NEWTON;
+  } else {
+    s.st = MGRHD_ST_INVALID;
+    s.phase = P_EMPTY;
+  }
+}
+
+template <int G, int LPC>
+__device__ __forceinline__ void finish_cell(const KArgs& a, int j, CellState<G>& s, bool store) {
+  const int64_t n = a.n, i = s.i;
+  const int ng = a.ng;
+  if (store) {
+    double bad = (isfinite(s.egas_new) && isfinite(s.v[0]) && isfinite(s.v[1]) && isfinite(s.v[2]))
+                     ? 0.0 : 1.0;
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      if (j * G + k >= ng) continue;
+      if (!isfinite(s.E0[k] + s.R[k])) bad = 1.0;
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+        if (!isfinite(s.Fk[d][k])) bad = 1.0;
+    }
+    bad = cell_sum<LPC>(bad, s.lpc);
+    if (bad != 0.0) {
+      s.st |= MGRHD_ST_NONFINITE;
+    } else {
+#pragma unroll
+      for (int k = 0; k < G; ++k) {
+        const int g = j * G + k;
+        if (g >= ng) continue;
+        a.E[(int64_t)g * n + i] = s.E0[k] + s.R[k];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) a.F[((int64_t)d * ng + g) * n + i] = s.Fk[d][k];
+      }
+      if (j == 0) {
+        a.egas[i] = s.egas_new;
+        a.v[i] = s.v[0];
+        a.v[n + i] = s.v[1];
+        a.v[2 * n + i] = s.v[2];
+      }
+    }
+  }
+  if (j == 0) {
+    if (a.status) a.status[i] = s.st;
+    if (a.iters) a.iters[i] = s.steps;
+    if (a.outer) a.outer[i] = s.passes;
+  }
+  s.phase = P_EMPTY;
+}
+
+// End of an inner pass with result rc (0 converged, 1 max_newton, 2 T <= 0).
+template <int G, int LPC>
+__device__ __forceinline__ void newton_done(const KArgs& a, int j, CellState<G>& s, int rc) {
+  if (s.k_out == 0 && s.warm && rc != 0 && !s.fell_back) {
+    // warm start failed: plain Newton from the old state (status bit 4)
+    s.st |= MGRHD_ST_FALLBACK;
+    s.fell_back = true;
+    s.egv = s.egas0;
+#pragma unroll
+    for (int k = 0; k < G; ++k) s.R[k] = 0.0;
+    s.polish_left = -1;
+    return;  // stays in P_NEWTON
+  }
+  if (rc == 1) s.st |= MGRHD_ST_NEWTON_MAXIT;
+  if (rc == 2) {
+    s.st |= MGRHD_ST_INVALID;
+    finish_cell<G, LPC>(a, j, s, false);
+    return;
+  }
+  // conservative energy update (Sec. 3)
+  double sumR = 0.0;
+#pragma unroll
+  for (int k = 0; k < G; ++k) sumR += s.R[k];
+  sumR = cell_sum<LPC>(sumR, s.lpc);
+  s.egas_new = s.egas0 - (a.c / a.chat) * sumR;
+  s.phase = P_FLUX;
+}
+
+// Newton consumer: residual of eq. FGFR at the cached material state, the
+// elimination of eq. matrix, and the step.
+template <int G, int LPC, int MODE, int NGM>
+__device__ __forceinline__ void newton_step(const KArgs& a, const Tables<NGM>& t, int j, CellState<G>& s,
+                            const Cache<G>& c) {
+  const int ng = a.ng;
+  const double cc = a.c / a.chat;
+  const double cdt = a.chat * a.dt;
+  const double ic2 = 1.0 / (a.c * a.c);
+  const double ircv = 1.0 / (s.rho * a.cv);
+  double sumR = 0.0, sumAbs = 0.0, sumA = 0.0, sumB = 0.0;
+  double ag[G], bg[G];
+#pragma unroll
+  for (int k = 0; k < G; ++k) {
+    ag[k] = 0.0;
+    bg[k] = 0.0;
+    const int g = j * G + k;
+    if (g >= ng) continue;
+    double ratio = 1.0, itau = s.itau[k], iJgg = s.iJgg[k];
+    if (MODE == MGRHD_MEAN_PPL_FREE) {
+      ratio = c.chiB[k] / c.chiE[k];
+      itau = 1.0 / (cdt * c.chiE[k]);
+      iJgg = 1.0 / (-itau - 1.0);
+    }
+    const double vF = s.v[0] * s.Fk[0][k] + s.v[1] * s.Fk[1][k] + s.v[2] * s.Fk[2][k];
+    const double W = cdt * (1.0 + t.achi[g]) * c.chiF[k] * vF * ic2;  // eq. Rnew
+    const double Eg = ratio * c.Bt[k] + (W - s.R[k]) * itau;  // eq. Rnew solved for E_g
+    const double FR = Eg - s.E0[k] - s.R[k];
+    const double Jg0 = ratio * c.dBdT[k] * ircv;               // eq. linear
+    ag[k] = FR * iJgg;
+    bg[k] = Jg0 * iJgg;
+    sumR += s.R[k];
+    sumAbs += fabs(FR);
+    sumA += ag[k];
+    sumB += bg[k];
+  }
+  sumR = cell_sum<LPC>(sumR, s.lpc);
+  sumAbs = cell_sum<LPC>(sumAbs, s.lpc);
+  sumA = cell_sum<LPC>(sumA, s.lpc);
+  sumB = cell_sum<LPC>(sumB, s.lpc);
+  const double FG = s.egv - s.egas0 + cc * sumR;
+  const bool conv = fabs(FG) / s.etot < a.eps && cc * sumAbs / s.etot < a.eps;
+  if (s.polish_left < 0 && conv) s.polish_left = a.polish;
+  if (s.polish_left == 0) {
+    newton_done<G, LPC>(a, j, s, 0);
+    return;
+  }
+  if (s.polish_left < 0 && s.steps >= a.max_newton) {
+    newton_done<G, LPC>(a, j, s, 1);
+    return;
+  }
+  // eq. matrix eliminated: dx0, then dx_g = -a_g - b_g dx0
+  const double dx0 = (-FG + cc * sumA) / (1.0 - cc * sumB);
+  double lam = 1.0;
+  for (int h = 0; h < 30 && !(s.egv + lam * dx0 - s.ke > 0.0); ++h) lam *= 0.5;
+  if (!(s.egv + lam * dx0 - s.ke > 0.0)) {
+    newton_done<G, LPC>(a, j, s, 2);
+    return;
+  }
+  s.egv += lam * dx0;
+#pragma unroll
+  for (int k = 0; k < G; ++k) s.R[k] += lam * (-ag[k] - bg[k] * dx0);
+  if (s.polish_left > 0)
+    --s.polish_left;
+  else
+    ++s.steps;
+  if (s.polish_left == 0) newton_done<G, LPC>(a, j, s, 0);
+}
+
+// Outer-stage consumer: flux update eq. numF1 with the outdated velocity,
+// momentum update, outer test.  Returns true when the next inner pass starts
+// (at the same temperature, so the caller reuses this evaluation).
+template <int G, int LPC, int MODE, int NGM>
+__device__ __forceinline__ bool flux_step(const KArgs& a, const Tables<NGM>& t, int j, CellState<G>& s,
+                          const Cache<G>& c) {
+  const int ng = a.ng;
+  const int64_t n = a.n, i = s.i;
+  const double cdt = a.chat * a.dt;
+  double dmom[3] = {0.0, 0.0, 0.0};
+  double Fn[3][G];
+#pragma unroll
+  for (int k = 0; k < G; ++k) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) Fn[d][k] = 0.0;
+    const int g = j * G + k;
+    if (g >= ng) continue;
+    const double Enew = s.E0[k] + s.R[k];
+    const double chE = (MODE == MGRHD_MEAN_PPL_FREE) ? c.chiE[k] : s.chiK[k];
+    double Pv[3];
+    pressure_dot_v(a.closure, a.c, Enew, s.Fk[0][k], s.Fk[1][k], s.Fk[2][k], s.v, Pv);
+    const double den = 1.0 + cdt * c.chiF[k];
+    const double q = (1.0 + t.achi[g]) * chE;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double f0 = a.F[((int64_t)d * ng + g) * n + i];  // F_g^(t)
+      const double f = (f0 + cdt * (s.v[d] * c.emit[k] + q * Pv[d])) / den;
+      Fn[d][k] = f;
+      dmom[d] += f - f0;
+    }
+  }
+  const double ccc = 1.0 / (a.c * a.chat);
+  double vn[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    dmom[d] = cell_sum<LPC>(dmom[d], s.lpc);
+    vn[d] = (s.rho * a.v[(int64_t)d * n + i] - dmom[d] * ccc) / s.rho;  // momentum update
+  }
+  double dW = 0.0;
+#pragma unroll
+  for (int k = 0; k < G; ++k) {
+    const int g = j * G + k;
+    if (g >= ng) continue;
+    const double vf_new = vn[0] * Fn[0][k] + vn[1] * Fn[1][k] + vn[2] * Fn[2][k];
+    const double vf_old = s.v[0] * s.Fk[0][k] + s.v[1] * s.Fk[1][k] + s.v[2] * s.Fk[2][k];
+    dW += fabs(cdt * (1.0 + t.achi[g]) * c.chiF[k] * (vf_new - vf_old)) / (a.c * a.c);
+  }
+  dW = cell_sum<LPC>(dW, s.lpc);
+  const double ke_new = 0.5 * s.rho * (vn[0] * vn[0] + vn[1] * vn[1] + vn[2] * vn[2]);
+  s.egv = s.egas_new + (ke_new - s.ke);
+  s.ke = ke_new;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) s.v[d] = vn[d];
+#pragma unroll
+  for (int k = 0; k < G; ++k)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) s.Fk[d][k] = Fn[d][k];
+  if (dW < a.eps_out * s.etot) {
+    finish_cell<G, LPC>(a, j, s, true);
+    return false;
+  }
+  if (s.k_out + 1 >= a.max_outer) {
+    s.st |= MGRHD_ST_OUTER_MAXIT;
+    finish_cell<G, LPC>(a, j, s, true);
+    return false;
+  }
+  ++s.k_out;
+  ++s.passes;
+  s.polish_left = -1;
+  s.phase = P_NEWTON;
+  return true;
+}
+
+// WPE: minimum resident waves per SIMD the register allocation must allow
+
+}  // namespace mgrhd

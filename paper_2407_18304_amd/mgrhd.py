@@ -141,3 +141,130 @@ def source_update(E_g, F_g, rho, e_gas, v, group_edges, chi_lo, *, dt, c_hat,
         float(c_hat), stream, C.byref(o))
     if rc != 0:
         raise MgrhdError(rc)
+
+
+# --------------------------------------------------------------------------
+# Batched patches (include/mgrhd.h, mgrhd_batch_*)
+class Patch(C.Structure):
+    _fields_ = [("E_g", C.c_void_p), ("F_g", C.c_void_p), ("rho", C.c_void_p),
+                ("e_gas", C.c_void_p), ("v", C.c_void_p), ("kappa_scale", C.c_void_p),
+                ("S_g", C.c_void_p), ("guess", C.c_void_p), ("iters", C.c_void_p),
+                ("outer", C.c_void_p), ("status", C.c_void_p), ("group_edges", C.c_void_p),
+                ("chi_lo", C.c_void_p), ("alpha_chi", C.c_void_p), ("chi_hi", C.c_void_p),
+                ("n_cells", C.c_int64), ("n_groups", C.c_int32), ("reserved", C.c_int32),
+                ("dt", C.c_double), ("c_hat", C.c_double)]
+
+
+SYMBOLS += ["mgrhd_batch_create", "mgrhd_batch_set_tuning", "mgrhd_batch_get_tuning",
+            "mgrhd_batch_run", "mgrhd_batch_capture", "mgrhd_batch_launch", "mgrhd_batch_cells",
+            "mgrhd_batch_destroy"]
+
+
+def _batch_lib():
+    L = lib()
+    if not hasattr(L, "_batch_ready"):
+        L.mgrhd_batch_create.restype = C.c_int
+        L.mgrhd_batch_create.argtypes = [C.POINTER(Patch), C.c_int32, C.c_int32,
+                                         C.POINTER(Options), C.POINTER(C.c_void_p)]
+        L.mgrhd_batch_set_tuning.restype = C.c_int
+        L.mgrhd_batch_set_tuning.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int64]
+        L.mgrhd_batch_get_tuning.restype = C.c_int
+        L.mgrhd_batch_get_tuning.argtypes = [C.c_void_p, C.POINTER(C.c_int32),
+                                             C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
+        for f in ("mgrhd_batch_run", "mgrhd_batch_capture", "mgrhd_batch_launch"):
+            getattr(L, f).restype = C.c_int
+            getattr(L, f).argtypes = [C.c_void_p, C.c_void_p]
+        L.mgrhd_batch_cells.restype = C.c_int64
+        L.mgrhd_batch_cells.argtypes = [C.c_void_p]
+        L.mgrhd_batch_destroy.restype = None
+        L.mgrhd_batch_destroy.argtypes = [C.c_void_p]
+        L._batch_ready = True
+    return L
+
+
+class Batch:
+    """A set of patches solved by one persistent launch (optionally replayed
+    from a captured hipGraph).  ``patches``: list of dicts with the device
+    tensors of each patch (E_g, F_g, rho, e_gas, v, edges, chi_lo, and
+    optionally alpha_chi, chi_hi, kappa_scale, S_g, guess, iters, outer,
+    status) and its dt, c_hat."""
+
+    def __init__(self, patches, *, mean_mode=MEAN_PPL_FIXED, c=1.0, a_rad=1.0, h_over_k=1.0,
+                 c_v=1.5, eps_newton=1e-11, eps_outer=1e-13, max_newton=100, max_outer=10,
+                 closure=CLOSURE_M1, polish=0):
+        L = _batch_lib()
+        arr = (Patch * len(patches))()
+        self._keep = patches      # the tensors must outlive the batch
+        for k, p in enumerate(patches):
+            ng, n = p["E_g"].shape
+            q = arr[k]
+            q.E_g = _ptr(p["E_g"], (ng, n), name="E_g")
+            q.F_g = _ptr(p["F_g"], (3, ng, n), name="F_g")
+            q.rho = _ptr(p["rho"], (n,), name="rho")
+            q.e_gas = _ptr(p["e_gas"], (n,), name="e_gas")
+            q.v = _ptr(p["v"], (3, n), name="v")
+            q.kappa_scale = _ptr(p.get("kappa_scale"), (n,), name="kappa_scale")
+            q.S_g = _ptr(p.get("S_g"), (ng, n), name="S_g")
+            q.guess = _ptr(p.get("guess"), (ng + 1, n), name="guess")
+            q.iters = _ptr(p.get("iters"), (n,), torch.int32, "iters")
+            q.outer = _ptr(p.get("outer"), (n,), torch.int32, "outer")
+            q.status = _ptr(p.get("status"), (n,), torch.int32, "status")
+            q.group_edges = _ptr(p["edges"], (ng + 1,), name="edges")
+            q.chi_lo = _ptr(p["chi_lo"], (ng,), name="chi_lo")
+            q.alpha_chi = _ptr(p.get("alpha_chi"), (ng,), name="alpha_chi")
+            q.chi_hi = _ptr(p.get("chi_hi"), (ng,), name="chi_hi")
+            q.n_cells, q.n_groups = n, ng
+            q.dt, q.c_hat = float(p["dt"]), float(p["c_hat"])
+        o = default_options()
+        o.c, o.a_rad, o.h_over_k, o.c_v = c, a_rad, h_over_k, c_v
+        o.eps_newton, o.eps_outer = eps_newton, eps_outer
+        o.max_newton, o.max_outer, o.closure, o.polish = max_newton, max_outer, closure, polish
+        h = C.c_void_p()
+        rc = L.mgrhd_batch_create(arr, len(patches), mean_mode, C.byref(o), C.byref(h))
+        if rc != 0:
+            raise MgrhdError(rc, "mgrhd_batch_create")
+        self._h = h
+
+    def _stream(self, stream):
+        return torch.cuda.current_stream().cuda_stream if stream is None else stream
+
+    def set_tuning(self, groups_per_lane, blocks_per_cu, chunk_cells):
+        rc = _batch_lib().mgrhd_batch_set_tuning(self._h, groups_per_lane, blocks_per_cu,
+                                                 chunk_cells)
+        if rc:
+            raise MgrhdError(rc, "mgrhd_batch_set_tuning")
+
+    def get_tuning(self):
+        g, b, ch = C.c_int32(), C.c_int32(), C.c_int64()
+        _batch_lib().mgrhd_batch_get_tuning(self._h, C.byref(g), C.byref(b), C.byref(ch))
+        return g.value, b.value, ch.value
+
+    def run(self, stream=None):
+        rc = _batch_lib().mgrhd_batch_run(self._h, self._stream(stream))
+        if rc:
+            raise MgrhdError(rc, "mgrhd_batch_run")
+
+    def capture(self, stream=None):
+        rc = _batch_lib().mgrhd_batch_capture(self._h, self._stream(stream))
+        if rc:
+            raise MgrhdError(rc, "mgrhd_batch_capture")
+
+    def launch(self, stream=None):
+        rc = _batch_lib().mgrhd_batch_launch(self._h, self._stream(stream))
+        if rc:
+            raise MgrhdError(rc, "mgrhd_batch_launch")
+
+    @property
+    def n_cells(self):
+        return _batch_lib().mgrhd_batch_cells(self._h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _batch_lib().mgrhd_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

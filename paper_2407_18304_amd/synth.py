@@ -112,3 +112,61 @@ def to_host(dw: DeviceWorkload, idx) -> W.Workload:
     return W.Workload(dw.name, len(idx), dw.edges, dw.chi_lo, dw.alpha_chi,
                       dw.kappa[idx_t].cpu().numpy(), st, dw.T[idx_t].cpu().numpy(), dt=dw.dt,
                       c_hat=dw.c_hat, c=dw.c, a_rad=dw.a_rad)
+
+
+@dataclasses.dataclass
+class DevicePatch:
+    layout: "W.PatchLayout"
+    state: dict          # device tensors E_g, F_g, rho, e_gas, v
+    kappa: torch.Tensor
+    T: torch.Tensor
+    tables: dict         # device tensors edges, chi_lo, alpha
+    dt: float
+    c_hat: float
+
+
+def device_patches(layouts, dev="cuda", stream=None):
+    """Allocate and fill every patch of ``layouts`` in HBM (state as config2,
+    units of the patch family); cell numbers are the layouts' global ones."""
+    sp = W.SPECS["config2"]
+    u = W.UNITS["patches"]
+    dt = 1.0 / u["c"]
+    gl = torch.from_numpy(np.concatenate([W._GL_X, W._GL_W])).to(dev)
+    f64 = dict(dtype=torch.float64, device=dev)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+    if stream is None:
+        stream = torch.cuda.current_stream(torch.device(dev)).cuda_stream
+    out = []
+    for L in layouts:
+        n, ng = L.n, L.ng
+        st = {"E_g": torch.empty((ng, n), **f64), "F_g": torch.empty((3, ng, n), **f64),
+              "rho": torch.empty(n, **f64), "e_gas": torch.empty(n, **f64),
+              "v": torch.empty((3, n), **f64)}
+        kap, T = torch.empty(n, **f64), torch.empty(n, **f64)
+        tabs = {"edges": t(L.edges), "chi_lo": t(L.chi_lo), "alpha": t(L.alpha_chi)}
+        rc = lib().mgrhd_synth_state(
+            st["E_g"].data_ptr(), st["F_g"].data_ptr(), st["rho"].data_ptr(),
+            st["e_gas"].data_ptr(), st["v"].data_ptr(), kap.data_ptr(), T.data_ptr(),
+            tabs["edges"].data_ptr(), gl.data_ptr(), n, L.cell0,
+            np.uint64(W.PATCH_SPEC["seed"]).item(), ng, len(W._GL_X), sp["t_kind"], sp["t_p"][0],
+            sp["t_p"][1], sp["k_kind"], sp["k_p"][0], sp["k_p"][1], 1.0 / (dt * u["c"]),
+            W.TRAD_RANGE[0], W.TRAD_RANGE[1], sp["vmax"], u["c"], u["a_rad"], 1.5, stream)
+        if rc != 0:
+            raise RuntimeError(f"mgrhd_synth_state failed ({rc})")
+        out.append(DevicePatch(L, st, kap, T, tabs, dt, u["c"]))
+    torch.cuda.synchronize()
+    return out
+
+
+def patch_to_host(dp: DevicePatch, idx=None) -> W.Workload:
+    """Copy (cells idx of) a device patch back as a host Workload."""
+    n = dp.layout.n
+    idx = np.arange(n) if idx is None else np.asarray(idx)
+    it = torch.as_tensor(idx, device=dp.kappa.device, dtype=torch.long)
+    st = {"E_g": dp.state["E_g"][:, it], "F_g": dp.state["F_g"][:, :, it],
+          "rho": dp.state["rho"][it], "e_gas": dp.state["e_gas"][it], "v": dp.state["v"][:, it]}
+    st = {k: np.ascontiguousarray(v.cpu().numpy()) for k, v in st.items()}
+    u = W.UNITS["patches"]
+    return W.Workload(f"patch{dp.layout.index}", len(idx), dp.layout.edges, dp.layout.chi_lo,
+                      dp.layout.alpha_chi, dp.kappa[it].cpu().numpy(), st, dp.T[it].cpu().numpy(),
+                      dt=dp.dt, c_hat=dp.c_hat, **u)

@@ -268,6 +268,57 @@ def config2(cells=None, seed=None, n=None, ng=None, units=None):
     return make("config2", cells, seed, n, ng, units)
 
 
+# AMR-like patches: cube sides uniform in {8,16,32,64}, group counts uniform in
+# {8,16,32,64}, edges log-spaced over [10^U(-3.5,-2.5), 10^U(2.5,3.5)], one
+# random powerlaw table per patch (as config1), state as config2.
+PATCH_SPEC = dict(seed=BASE_SEED + 4, n_patches=2000, sides=(8, 16, 32, 64), ngs=(8, 16, 32, 64))
+
+
+@dataclasses.dataclass
+class PatchLayout:
+    index: int
+    n: int
+    ng: int
+    cell0: int            # offset of the patch's first cell in the batch numbering
+    edges: np.ndarray
+    chi_lo: np.ndarray
+    alpha_chi: np.ndarray
+
+
+def patch_layouts(n_patches=None, seed=None, sides=None, ngs=None):
+    sp = PATCH_SPEC
+    n_patches = sp["n_patches"] if n_patches is None else n_patches
+    seed = sp["seed"] if seed is None else seed
+    sides = sp["sides"] if sides is None else sides
+    ngs = sp["ngs"] if ngs is None else ngs
+    out, cell0 = [], 0
+    for p in range(n_patches):
+        side = sides[int(uniform(seed, F_PATCH, p, 0) * len(sides))]
+        ng = ngs[int(uniform(seed, F_PATCH, p, 1) * len(ngs))]
+        lo = 10.0 ** (-3.5 + uniform(seed, F_PATCH, p, 2))
+        hi = 10.0 ** (2.5 + uniform(seed, F_PATCH, p, 3))
+        edges = log_edges(lo, hi, ng)
+        chi_lo, alpha = random_table(seed, edges, field_offset=0, sub_base=1000 * (p + 1))
+        out.append(PatchLayout(p, side ** 3, ng, cell0, edges, chi_lo, alpha))
+        cell0 += side ** 3
+    return out
+
+
+def patch_workload(layout: PatchLayout, cells=None, seed=None) -> Workload:
+    """Host-side state of one patch (cells = indices within the patch)."""
+    seed = PATCH_SPEC["seed"] if seed is None else seed
+    local = np.arange(layout.n) if cells is None else np.asarray(cells)
+    gcells = (layout.cell0 + local).astype(np.uint64)
+    u = UNITS["patches"]
+    dt = 1.0 / u["c"]
+    T = draw_T("config2", gcells, seed)
+    kappa = draw_kappa("config2", gcells, seed, dt, u["c"])
+    st = _state(seed, gcells, layout.edges, T, *TRAD_RANGE, SPECS["config2"]["vmax"], u["c"],
+                u["a_rad"])
+    return Workload(f"patch{layout.index}", gcells.size, layout.edges, layout.chi_lo,
+                    layout.alpha_chi, kappa, st, T, dt=dt, c_hat=u["c"], **u)
+
+
 def subset(w: Workload, idx) -> Workload:
     """Cells ``idx`` of a workload, as an independent Workload."""
     idx = np.asarray(idx)

@@ -51,21 +51,26 @@ def run_oracle(w, mode, *, polish=1, closure=0, max_outer=10, max_newton=100, ep
 
 def field_errors(w, gpu, ora, mask=None):
     """Per field: max relative error with the floors of the parity metric.
-    Energies: floor 1e-16 E_tot (per cell).  Fluxes and velocity: floor
-    1e-16 of the cell's momentum scale |rho v| + sum |F_g|/(c c_hat)."""
+    Energies (E_g, E_gas): |a - b| / max(|b|, 1e-16 E_tot), per cell and group.
+    Vectors (F_g per group, v per cell) are compared as vectors:
+    max_d |a_d - b_d| / max(|b|_2, floor), with floor 1e-16 of the cell's
+    momentum scale |rho v| + sum_g |F_g|/(c c_hat) (in the field's units)."""
     st = w.state
     cc = w.c / w.c_hat
     etot = st["e_gas"] + (1.0 / cc) * st["E_g"].sum(0)
     pscale = np.abs(st["rho"] * st["v"]).sum(0) + np.abs(st["F_g"]).sum((0, 1)) / (w.c * w.c_hat)
-    floors = {"E_g": 1e-16 * etot, "e_gas": 1e-16 * etot,
-              "F_g": 1e-16 * pscale * w.c * w.c_hat, "v": 1e-16 * pscale / st["rho"]}
     out = {}
     for k in FIELDS:
         a, b = gpu[k], ora[k]
-        fl = floors[k]
-        den = np.maximum(np.abs(b), fl)
-        err = np.abs(a - b) / den
-        err = err.reshape(-1, w.n)
+        if k in ("E_g", "e_gas"):
+            err = (np.abs(a - b) / np.maximum(np.abs(b), 1e-16 * etot)).reshape(-1, w.n)
+        elif k == "F_g":
+            nrm = np.sqrt((b * b).sum(0))                        # [N_g, n]
+            fl = 1e-16 * pscale * w.c * w.c_hat
+            err = np.abs(a - b).max(0) / np.maximum(nrm, fl)
+        else:
+            nrm = np.sqrt((b * b).sum(0))
+            err = (np.abs(a - b).max(0) / np.maximum(nrm, 1e-16 * pscale / st["rho"]))[None]
         if mask is not None:
             err = err[:, mask]
         out[k] = float(err.max()) if err.size else 0.0

@@ -19,5 +19,4 @@ void dm_group(double xl, double xh, double* out) {
   out[4] = p.scale;
 }
 double dm_mean_ratio(double ac, double aq, double L) { return mgrhd::mean_ratio(ac, aq, L); }
-double dm_bern(int m) { return mgrhd::bern_over_fact(m); }
 }

@@ -1,0 +1,143 @@
+"""The batched patch launch (mgrhd_batch_*): uneven AMR-like patches with their
+own group counts, edges and tables in one persistent launch, direct and
+replayed from a captured hipGraph.  Checked per patch against the single-table
+entry point and against the oracle.  GPU only."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2407_18304_amd import mgrhd, synth
+from paper_2407_18304_amd import workloads as W
+
+import gpu_util as U
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+
+def _layouts(n=12):
+    # small cubes so the oracle can check whole patches
+    return W.patch_layouts(n_patches=n, sides=(4, 6, 8, 10), ngs=(8, 16, 32, 64))
+
+
+def _patch_dicts(dps, with_out=True):
+    out = []
+    for dp in dps:
+        n = dp.layout.n
+        d = dict(dp.state)
+        d.update(edges=dp.tables["edges"], chi_lo=dp.tables["chi_lo"], alpha_chi=dp.tables["alpha"],
+                 kappa_scale=dp.kappa, dt=dp.dt, c_hat=dp.c_hat)
+        if with_out:
+            d.update(iters=torch.zeros(n, dtype=torch.int32, device="cuda"),
+                     outer=torch.zeros(n, dtype=torch.int32, device="cuda"),
+                     status=torch.full((n,), -1, dtype=torch.int32, device="cuda"))
+        out.append(d)
+    return out
+
+
+def _consts():
+    u = W.UNITS["patches"]
+    return dict(c=u["c"], a_rad=u["a_rad"])
+
+
+@pytest.mark.parametrize("gpl", [2, 4])
+def test_batch_matches_single_table_and_oracle(gpl):
+    layouts = _layouts()
+    dps = synth.device_patches(layouts)
+    inputs = [synth.patch_to_host(dp) for dp in dps]          # pristine inputs
+    pd = _patch_dicts(dps)
+    b = mgrhd.Batch(pd, mean_mode=1, polish=1, **_consts())
+    b.set_tuning(gpl, 0, 300)                                   # several items per patch
+    assert b.n_cells == sum(L.n for L in layouts)
+    b.run()
+    torch.cuda.synchronize()
+    for L, w, d in zip(layouts, inputs, pd):
+        g = {k: d[k].cpu().numpy() for k in ("E_g", "F_g", "e_gas", "v")}
+        gs = d["status"].cpu().numpy()
+        assert (gs >= 0).all()
+        # the single-table entry point on the same patch
+        s, si, so, ss = U.run_gpu(w, 1)
+        same = (gs == ss) & (d["iters"].cpu().numpy() == si)
+        assert same.mean() > 0.99
+        err = U.field_errors(w, g, s, same & (ss == 0))
+        for k, e in err.items():
+            assert e < 1e-10, (L.index, k, e)
+        # the oracle
+        o, oi, oo, os_ = U.run_oracle(w, 1)
+        ok = (os_ == 0) & (gs == 0) & (oi == d["iters"].cpu().numpy()) & \
+             (oo == d["outer"].cpu().numpy())
+        assert ok.mean() > 0.98
+        for k, e in U.field_errors(w, g, o, ok).items():
+            assert e < 1e-10, (L.index, k, e)
+
+
+def test_batch_graph_replay_matches_direct_run():
+    """Capture [counter clear -> persistent solver] once, replay it several
+    times on restored inputs, with eager work between the replays: every
+    replay equals the direct run bit for bit."""
+    layouts = _layouts(8)
+    dps = synth.device_patches(layouts)
+    pristine = [{k: v.clone() for k, v in dp.state.items()} for dp in dps]
+    pd = _patch_dicts(dps)
+    b = mgrhd.Batch(pd, mean_mode=1, polish=1, **_consts())
+    b.set_tuning(4, 0, 256)
+
+    def restore():
+        for dp, p in zip(dps, pristine):
+            for k in ("E_g", "F_g", "e_gas", "v"):
+                dp.state[k].copy_(p[k])
+
+    b.run()
+    torch.cuda.synchronize()
+    ref = [{k: dp.state[k].clone() for k in ("E_g", "F_g", "e_gas", "v")} for dp in dps]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        restore()
+        b.capture(stream.cuda_stream)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        restore()
+        torch.cuda.synchronize()
+        x = torch.randn(1000, device="cuda").sum()      # eager work between replays
+        torch.cuda.synchronize()
+        b.launch(stream.cuda_stream)
+        stream.synchronize()
+        for dp, r in zip(dps, ref):
+            for k in r:
+                assert torch.equal(dp.state[k], r[k]), (rep, k)
+        del x
+
+
+def test_batch_ragged_and_empty_patches():
+    layouts = W.patch_layouts(n_patches=5, sides=(1, 3, 5), ngs=(1, 3, 8, 13, 33))
+    dps = synth.device_patches(layouts)
+    inputs = [synth.patch_to_host(dp) for dp in dps]
+    pd = _patch_dicts(dps)
+    # add an empty patch
+    e = {k: v[..., :0].contiguous() for k, v in pd[0].items() if isinstance(v, torch.Tensor)
+         and k not in ("edges", "chi_lo", "alpha_chi")}
+    e.update(edges=pd[0]["edges"], chi_lo=pd[0]["chi_lo"], alpha_chi=pd[0]["alpha_chi"],
+             dt=pd[0]["dt"], c_hat=pd[0]["c_hat"])
+    b = mgrhd.Batch(pd + [e], mean_mode=2, polish=1, **_consts())
+    b.run()
+    torch.cuda.synchronize()
+    for w, d in zip(inputs, pd):
+        g = {k: d[k].cpu().numpy() for k in ("E_g", "F_g", "e_gas", "v")}
+        o, oi, oo, os_ = U.run_oracle(w, 2)
+        gs = d["status"].cpu().numpy()
+        ok = (os_ == 0) & (gs == 0) & (oi == d["iters"].cpu().numpy()) & \
+             (oo == d["outer"].cpu().numpy())
+        for k, e in U.field_errors(w, g, o, ok).items():
+            assert e < 1e-10, (k, e)
+
+
+def test_batch_argument_errors():
+    layouts = _layouts(2)
+    dps = synth.device_patches(layouts)
+    pd = _patch_dicts(dps)
+    with pytest.raises(mgrhd.MgrhdError):
+        mgrhd.Batch(pd, mean_mode=5)
+    b = mgrhd.Batch(pd, mean_mode=1, **_consts())
+    with pytest.raises(mgrhd.MgrhdError):
+        b.set_tuning(3, 0, 100)
+    b.close()
