@@ -199,6 +199,61 @@ int mgrhd_batch_launch(mgrhd_batch* b, mgrhd_stream_t stream);
 int64_t mgrhd_batch_cells(const mgrhd_batch* b);
 void mgrhd_batch_destroy(mgrhd_batch* b);
 
+/* ---- Learned warm start --------------------------------------------------
+ * A multilayer perceptron n_in -> n_hidden -> n_hidden -> n_hidden -> n_out
+ * with SiLU activations, trained on (state, dt) -> (post-update T_gas, E_g)
+ * pairs produced by mgrhd_source_update, whose prediction becomes the
+ * Newton initial guess (opt->guess); plain Newton remains the fallback and
+ * the result is the solver's whatever the guess.  Every product runs on the
+ * matrix cores as BF16 x BF16 -> FP32; parameters, gradients and Adam moments
+ * are FP32.  Matrices: features feature-major X[f * ld_x + row], outputs
+ * and targets row-major Y[row * n_out + o].  All data pointers are DEVICE
+ * pointers except the host buffers of get/set_params.
+ * Features (n_in = 2 + 3 N_g): ln T, ln rho, ln(E_g/a T^4), |F_g|/(c E_g),
+ * ln(c_hat dt chi_0E,g); outputs (n_out = 1 + N_g): ln(T_new/T),
+ * ln(E_g,new/a T^4).  The handle owns its device buffers (allocated once in
+ * create for up to max_rows rows per call). */
+typedef struct mgrhd_mlp mgrhd_mlp;
+int mgrhd_mlp_create(int32_t n_in, int32_t n_hidden, int32_t n_out, int64_t max_rows,
+                     uint64_t seed, mgrhd_mlp** out);
+int64_t mgrhd_mlp_num_params(const mgrhd_mlp* m);
+/* which = 0: parameters, 1: last gradients; layout: W1..W4 (out x in,
+ * row-major) then b1..b4 */
+int mgrhd_mlp_get_params(const mgrhd_mlp* m, float* host, int32_t which);
+int mgrhd_mlp_set_params(mgrhd_mlp* m, const float* host);
+int mgrhd_mlp_forward(mgrhd_mlp* m, const float* X_fm, int64_t ld_x, int64_t rows, float* Y,
+                      mgrhd_stream_t stream);
+/* gradients of mean((Y - Y_target)^2) into the handle; loss_out (device, may
+ * be NULL) receives the loss */
+int mgrhd_mlp_gradients(mgrhd_mlp* m, const float* X_fm, int64_t ld_x, int64_t rows,
+                        const float* Y_target, float* loss_out, mgrhd_stream_t stream);
+int mgrhd_mlp_adam_step(mgrhd_mlp* m, float lr, mgrhd_stream_t stream);
+int mgrhd_mlp_train_step(mgrhd_mlp* m, const float* X_fm, int64_t ld_x, int64_t rows,
+                         const float* Y_target, float lr, float* loss_out, mgrhd_stream_t stream);
+/* features X_fm[(2 + 3 N_g) x n] of a state, z-scored with (mean, inv_std) */
+int mgrhd_mlp_features(const double* E_g, const double* F_g, const double* rho, const double* e_gas,
+                       const double* v, int64_t n, const double* group_edges,
+                       const mgrhd_opacity_params* opacity, double dt, double c_hat,
+                       const mgrhd_options* opt, const float* mean, const float* inv_std,
+                       float* X_fm, mgrhd_stream_t stream);
+/* training targets Y[n x (1 + N_g)] from the state before and after an update */
+int mgrhd_mlp_targets(const double* E_g, const double* F_g, const double* rho, const double* e_gas,
+                      const double* v, int64_t n, const double* group_edges,
+                      const mgrhd_opacity_params* opacity, double dt, double c_hat,
+                      const mgrhd_options* opt, const double* E_new, const double* e_gas_new,
+                      const double* v_new, float* Y, mgrhd_stream_t stream);
+/* Newton guess [(N_g+1) x n] (E_gas, R_g) from a normalised prediction */
+int mgrhd_mlp_guess(const double* E_g, const double* F_g, const double* rho, const double* e_gas,
+                    const double* v, int64_t n, const double* group_edges,
+                    const mgrhd_opacity_params* opacity, double dt, double c_hat,
+                    const mgrhd_options* opt, const float* Y_norm, const float* y_mean,
+                    const float* y_std, double* guess, mgrhd_stream_t stream);
+/* C = op(A) op(B) with the BF16 matrix-core kernel (FP32 in and out) */
+int mgrhd_mlp_gemm(const float* A, int32_t lda, int32_t trans_a, const float* B, int32_t ldb,
+                   int32_t trans_b, float* C, int32_t ldc, int64_t M, int32_t N, int32_t K,
+                   mgrhd_stream_t stream);
+void mgrhd_mlp_destroy(mgrhd_mlp* m);
+
 /* Library version string. */
 const char* mgrhd_version(void);
 

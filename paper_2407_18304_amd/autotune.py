@@ -1,0 +1,124 @@
+"""Autotuner for the source-update kernels.
+
+Single-table kernel: the compiled variants (lanes per cell x groups per lane)
+that cover N_g are timed on a sample of the workload (inputs restored before
+every timed launch, HIP events on the launch stream) and the fastest is
+installed with mgrhd_set_variant.  Batched launch: groups per lane, resident
+workgroups per CU and cells per work item are timed the same way.  Results are
+cached per (GPU architecture, N_g, mean mode) in a JSON file.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import torch
+
+from . import mgrhd
+
+CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json")
+# compiled variants of the single-table kernel: (lanes per cell, groups per lane)
+VARIANTS = [(1, 4), (2, 4), (4, 4), (8, 4), (16, 4), (32, 4), (64, 4), (2, 2), (4, 2), (8, 2),
+            (16, 2), (32, 2), (4, 1), (8, 1), (16, 1)]
+
+
+def arch() -> str:
+    p = torch.cuda.get_device_properties(0)
+    return getattr(p, "gcnArchName", p.name).split(":")[0]
+
+
+def load_cache(path=CACHE) -> dict:
+    if os.path.exists(path):
+        with open(path) as f:
+            return json.load(f)
+    return {}
+
+
+def save_cache(cache, path=CACHE):
+    with open(path, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+
+
+def apply_cache(path=CACHE) -> dict:
+    """Install the cached single-table choices for this GPU; returns them."""
+    cache = load_cache(path).get(arch(), {})
+    for key, rec in cache.get("single", {}).items():
+        ng = int(key.split(":")[0])
+        try:
+            mgrhd.set_variant(ng, rec["lanes_per_cell"], rec["groups_per_lane"])
+        except mgrhd.MgrhdError:
+            pass
+    return cache
+
+
+def _time(fn, restore, reps=3):
+    s = torch.cuda.current_stream()
+    best = float("inf")
+    for _ in range(reps):
+        restore()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(s)
+        fn()
+        b.record(s)
+        torch.cuda.synchronize()
+        best = min(best, a.elapsed_time(b))
+    return best
+
+
+def tune_single(dw, mode=mgrhd.MEAN_PPL_FIXED, reps=3, path=CACHE, log=print):
+    """Time every compiled variant covering dw.ng on the device workload dw."""
+    pristine = {k: v.clone() for k, v in dw.state.items()}
+    st = dw.state
+
+    def restore():
+        for k in ("E_g", "F_g", "e_gas", "v"):
+            st[k].copy_(pristine[k])
+
+    def run():
+        mgrhd.source_update(st["E_g"], st["F_g"], st["rho"], st["e_gas"], st["v"],
+                            dw.tables["edges"], dw.tables["chi_lo"], alpha_chi=dw.tables["alpha"],
+                            kappa_scale=dw.kappa, mean_mode=mode, polish=1, **dw.consts())
+
+    results = []
+    for lpc, g in VARIANTS:
+        if lpc * g < dw.ng or lpc * g >= 4 * dw.ng:
+            continue
+        mgrhd.set_variant(dw.ng, lpc, g)
+        run()                    # warm up (first launch loads the code object)
+        ms = _time(run, restore, reps)
+        results.append((ms, lpc, g))
+        log(f"  N_g={dw.ng} mode={mode}: {lpc} lanes x {g} groups -> {ms:.3f} ms")
+    restore()
+    ms, lpc, g = min(results)
+    mgrhd.set_variant(dw.ng, lpc, g)
+    cache = load_cache(path)
+    ent = cache.setdefault(arch(), {}).setdefault("single", {})
+    ent[f"{dw.ng}:{mode}"] = {"lanes_per_cell": lpc, "groups_per_lane": g, "ms": ms,
+                             "cells": dw.n, "all": [[m, l, gg] for m, l, gg in sorted(results)]}
+    save_cache(cache, path)
+    return lpc, g, ms
+
+
+def tune_batch(batch, restore, candidates=None, reps=2, path=CACHE, key="patches", log=print):
+    """Time batch tunings (groups per lane, blocks per CU, cells per item)."""
+    if candidates is None:
+        candidates = [(g, b, ch) for g in (2, 4) for b in (0, 1) for ch in (1024, 4096)]
+    results = []
+    for g, b, ch in candidates:
+        try:
+            batch.set_tuning(g, b, ch)
+        except mgrhd.MgrhdError:
+            continue
+        batch.run()
+        ms = _time(batch.run, restore, reps)
+        results.append((ms, g, b, ch))
+        log(f"  batch: {g} groups/lane, {b or 'all'} blocks/CU, {ch} cells/item -> {ms:.3f} ms")
+    restore()
+    ms, g, b, ch = min(results)
+    batch.set_tuning(g, b, ch)
+    cache = load_cache(path)
+    cache.setdefault(arch(), {}).setdefault("batch", {})[key] = {
+        "groups_per_lane": g, "blocks_per_cu": b, "chunk_cells": ch, "ms": ms,
+        "all": [list(r) for r in sorted(results)]}
+    save_cache(cache, path)
+    return g, b, ch, ms

@@ -234,7 +234,7 @@ static int build_items(mgrhd_batch* bt) {
     for (int64_t c0 = 0; c0 < n; c0 += bt->chunk)
       items.push_back(Item{p, 0, c0, std::min(n, c0 + bt->chunk)});
   }
-  if (bt->d_items) hipFree(bt->d_items);
+  if (bt->d_items) (void)hipFree(bt->d_items);
   bt->d_items = nullptr;
   bt->n_items = (int64_t)items.size();
   if (!items.empty()) {
@@ -248,8 +248,8 @@ static int build_items(mgrhd_batch* bt) {
 }
 
 static void drop_graph(mgrhd_batch* bt) {
-  if (bt->exec) hipGraphExecDestroy(bt->exec);
-  if (bt->graph) hipGraphDestroy(bt->graph);
+  if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
+  if (bt->graph) (void)hipGraphDestroy(bt->graph);
   bt->exec = nullptr;
   bt->graph = nullptr;
 }
@@ -422,7 +422,7 @@ int mgrhd_batch_capture(mgrhd_batch* bt, mgrhd_stream_t stream) {
   hipGraph_t g = nullptr;
   e = hipStreamEndCapture(st, &g);
   if (rc) {
-    if (g) hipGraphDestroy(g);
+    if (g) (void)hipGraphDestroy(g);
     return rc;
   }
   if (e != hipSuccess) return (int)e;
@@ -450,9 +450,9 @@ int64_t mgrhd_batch_cells(const mgrhd_batch* bt) { return bt ? bt->n_cells : -1;
 void mgrhd_batch_destroy(mgrhd_batch* bt) {
   if (!bt) return;
   drop_graph(bt);
-  if (bt->d_patches) hipFree(bt->d_patches);
-  if (bt->d_items) hipFree(bt->d_items);
-  if (bt->d_counter) hipFree(bt->d_counter);
+  if (bt->d_patches) (void)hipFree(bt->d_patches);
+  if (bt->d_items) (void)hipFree(bt->d_items);
+  if (bt->d_counter) (void)hipFree(bt->d_counter);
   delete bt;
 }
 

@@ -1,0 +1,652 @@
+// mlp.hip -- the learned warm start of the source update: a small MLP
+// (inputs -> 3 hidden SiLU layers -> outputs) trained on (state, dt) ->
+// (post-update T_gas, E_g) pairs produced by the FP64 solver, used to give the
+// Newton iteration its initial guess.  Plain Newton from the old state stays
+// the fallback and decides the result (the solver converges to the same root
+// whatever the guess).
+//
+// All tensors are FP32 in HBM; every matrix product runs on the gfx950 matrix
+// cores as BF16 x BF16 -> FP32 (v_mfma_f32_16x16x32_bf16): operands are
+// rounded to BF16 when a 64x32 / 32x64 tile is staged in LDS, accumulation is
+// FP32.  Master weights and Adam moments are FP32.
+//
+// Lane layout of v_mfma_f32_16x16x32_bf16 used below (checked by the GPU
+// tests against a reference product): lane l holds A[l%16][8(l/16) .. +7],
+// B[8(l/16) .. +7][l%16], and accumulators C[4(l/16) .. +3][l%16].
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/mgrhd.h"
+#include "planck_device.hpp"
+
+namespace mgrhd {
+namespace mlp {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 64, BN = 64, BK = 32;
+constexpr int LDK = BK + 8;  // LDS row pitch in bf16 (80 bytes: 16-byte aligned, skewed banks)
+
+enum Epi : int { EPI_NONE = 0, EPI_BIAS = 1, EPI_BIAS_SILU = 2 };
+
+// C[M x N] = op(A)[M x K] op(B)[K x N] (+ bias[N]) (SiLU, keeping the
+// pre-activation in Z).  op(A) = A (row-major, lda) or A^T (A stored K x M);
+// op(B) = B (row-major K x N, ldb) or B^T (B stored N x K).
+template <bool TA, bool TB, int EPI>
+__global__ __launch_bounds__(256) void k_gemm(const float* __restrict__ A, int lda,
+                                              const float* __restrict__ B, int ldb,
+                                              const float* __restrict__ bias, float* __restrict__ C,
+                                              int ldc, float* __restrict__ Z, int64_t M, int N,
+                                              int K) {
+  __shared__ __attribute__((aligned(16))) __bf16 As[BM][LDK];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[BN][LDK];
+  const int tid = threadIdx.x;
+  const int wave = tid / 64, lane = tid % 64;
+  const int64_t m0 = (int64_t)blockIdx.x * BM;
+  const int n0 = blockIdx.y * BN;
+  const int wm = (wave / 2) * 32, wn = (wave % 2) * 32;
+  floatx4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    // stage A tile (BM x BK) and B tile (BK x BN) as bf16, k contiguous
+#pragma unroll
+    for (int r = 0; r < (BM * BK) / 256; ++r) {
+      const int e = tid + 256 * r;
+      int mm, kk;
+      if (TA) {  // coalesced along m
+        mm = e % BM;
+        kk = e / BM;
+      } else {   // coalesced along k
+        kk = e % BK;
+        mm = e / BK;
+      }
+      const int64_t gm = m0 + mm;
+      const int gk = k0 + kk;
+      float x = 0.f;
+      if (gm < M && gk < K) x = TA ? A[(int64_t)gk * lda + gm] : A[gm * lda + gk];
+      As[mm][kk] = (__bf16)x;
+    }
+#pragma unroll
+    for (int r = 0; r < (BN * BK) / 256; ++r) {
+      const int e = tid + 256 * r;
+      int nn, kk;
+      if (TB) {  // B stored N x K: coalesced along k
+        kk = e % BK;
+        nn = e / BK;
+      } else {   // B stored K x N: coalesced along n
+        nn = e % BN;
+        kk = e / BN;
+      }
+      const int gn = n0 + nn, gk = k0 + kk;
+      float x = 0.f;
+      if (gn < N && gk < K) x = TB ? B[(int64_t)gn * ldb + gk] : B[(int64_t)gk * ldb + gn];
+      Bs[nn][kk] = (__bf16)x;
+    }
+    __syncthreads();
+    const int r16 = lane % 16, kq = 8 * (lane / 16);
+    bf16x8 af[2], bfr[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) af[a] = *(const bf16x8*)&As[wm + 16 * a + r16][kq];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) bfr[b] = *(const bf16x8*)&Bs[wn + 16 * b + r16][kq];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
+    __syncthreads();
+  }
+  // epilogue: lane holds C[4(l/16)+i][l%16] of each 16x16 tile
+  const int col16 = lane % 16, row4 = 4 * (lane / 16);
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int n = n0 + wn + 16 * b + col16;
+      if (n >= N) continue;
+      const float bv = (EPI != EPI_NONE) ? bias[n] : 0.f;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t m = m0 + wm + 16 * a + row4 + i;
+        if (m >= M) continue;
+        float z = acc[a][b][i] + bv;
+        if (EPI == EPI_BIAS_SILU) {
+          Z[m * ldc + n] = z;
+          z = z / (1.f + expf(-z));
+        }
+        C[m * ldc + n] = z;
+      }
+    }
+}
+
+// dZ = dH * SiLU'(Z), SiLU'(z) = s (1 + z (1 - s)), s = 1/(1+e^-z)
+__global__ void k_silu_bwd(const float* __restrict__ dH, const float* __restrict__ Z,
+                           float* __restrict__ dZ, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float z = Z[i];
+    const float s = 1.f / (1.f + expf(-z));
+    dZ[i] = dH[i] * (s * (1.f + z * (1.f - s)));
+  }
+}
+
+// column sums of a row-major [rows x N] matrix (bias gradients), one thread per column
+__global__ void k_colsum(const float* __restrict__ X, int64_t rows, int N, float* __restrict__ out) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  float s = 0.f;
+  for (int64_t r = 0; r < rows; ++r) s += X[r * N + n];
+  out[n] = s;
+}
+
+// mean-squared error: dY = 2 (Y - T) / (rows * N), loss = mean (Y - T)^2
+__global__ void k_mse(const float* __restrict__ Y, const float* __restrict__ T, int64_t n,
+                      float scale, float* __restrict__ dY, float* __restrict__ loss) {
+  __shared__ float part[256];
+  float acc = 0.f;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float d = Y[i] - T[i];
+    dY[i] = 2.f * d * scale;
+    acc += d * d;
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) part[threadIdx.x] += part[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && loss) atomicAdd(loss, part[0] * scale);
+}
+
+__global__ void k_zero(float* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.f;
+}
+
+// Adam on FP32 master parameters
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps,
+                       float c1, float c2) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Physics side: features, targets and the Newton guess (FP64 state).
+//
+// Features per cell (2 + 3 N_g), stored feature-major X[f * n + i]:
+//   ln T, ln rho, ln(E_g / a T^4) (clamped to [-50, 50]), |F_g| / (c E_g)
+//   (clamped to [0, 2]), ln(c_hat dt chi_0E,g) (PPL-fixed mean of the group),
+// each z-scored with the training statistics (mean, inv_std).
+// Targets per cell (1 + N_g), row-major Y[i * (1+N_g) + o]:
+//   ln(T_new / T), ln(E_g,new / a T^4) (clamped to [-50, 50]).
+struct PhysArgs {
+  const double* E;
+  const double* F;
+  const double* rho;
+  const double* egas;
+  const double* v;
+  const double* kappa;
+  const double* edges;
+  const double* chi_lo;
+  const double* alpha;
+  int64_t n;
+  int32_t ng;
+  int32_t pad;
+  double dt, chat, c, a, cv;
+};
+
+__device__ __forceinline__ double cell_T(const PhysArgs& p, int64_t i) {
+  const int64_t n = p.n;
+  const double v0 = p.v[i], v1 = p.v[n + i], v2 = p.v[2 * n + i];
+  const double rho = p.rho[i];
+  return (p.egas[i] - 0.5 * rho * (v0 * v0 + v1 * v1 + v2 * v2)) / (rho * p.cv);
+}
+
+__global__ void k_features(PhysArgs p, const float* __restrict__ mean,
+                           const float* __restrict__ istd, float* __restrict__ X) {
+  const int64_t n = p.n;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double T = fmax(cell_T(p, i), 1e-300);
+    const double rho = p.rho[i];
+    const double aT4 = p.a * (T * T) * (T * T);
+    const double kap = p.kappa ? p.kappa[i] : 1.0;
+    const int ng = p.ng;
+    auto put = [&](int f, double x) { X[(int64_t)f * n + i] = (float)((x - mean[f]) * istd[f]); };
+    put(0, log(T));
+    put(1, log(rho));
+    for (int g = 0; g < ng; ++g) {
+      const double E = p.E[(int64_t)g * n + i];
+      const double f0 = p.F[((int64_t)0 * ng + g) * n + i];
+      const double f1 = p.F[((int64_t)1 * ng + g) * n + i];
+      const double f2 = p.F[((int64_t)2 * ng + g) * n + i];
+      const double le = E > 0.0 ? fmin(fmax(log(E / aT4), -50.0), 50.0) : -50.0;
+      const double fr = E > 0.0 ? fmin(sqrt(f0 * f0 + f1 * f1 + f2 * f2) / (p.c * E), 2.0) : 0.0;
+      const double L = log(p.edges[g + 1] / p.edges[g]);
+      const double ac = p.alpha ? p.alpha[g] : 0.0;
+      const double chiE = rho * kap * p.chi_lo[g] * mean_ratio(ac, -1.0, L);
+      put(2 + g, le);
+      put(2 + ng + g, fr);
+      put(2 + 2 * ng + g, log(p.chat * p.dt * chiE));
+    }
+  }
+}
+
+// targets from the state before (p) and after (E_new, egas_new, v_new) the update
+__global__ void k_targets(PhysArgs p, const double* __restrict__ E_new,
+                          const double* __restrict__ egas_new, const double* __restrict__ v_new,
+                          float* __restrict__ Y) {
+  const int64_t n = p.n;
+  const int ng = p.ng, no = ng + 1;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double T = fmax(cell_T(p, i), 1e-300);
+    const double aT4 = p.a * (T * T) * (T * T);
+    const double w0 = v_new[i], w1 = v_new[n + i], w2 = v_new[2 * n + i];
+    const double rho = p.rho[i];
+    const double Tn = (egas_new[i] - 0.5 * rho * (w0 * w0 + w1 * w1 + w2 * w2)) / (rho * p.cv);
+    Y[i * no] = (float)(Tn > 0.0 ? log(Tn / T) : 0.0);
+    for (int g = 0; g < ng; ++g) {
+      const double E = E_new[(int64_t)g * n + i];
+      Y[i * no + 1 + g] = (float)(E > 0.0 ? fmin(fmax(log(E / aT4), -50.0), 50.0) : -50.0);
+    }
+  }
+}
+
+// Newton guess (E_gas, R_g) from the de-normalised prediction.
+__global__ void k_guess(PhysArgs p, const float* __restrict__ Yn, const float* __restrict__ ymean,
+                        const float* __restrict__ ystd, const double* __restrict__ S,
+                        double* __restrict__ guess) {
+  const int64_t n = p.n;
+  const int ng = p.ng, no = ng + 1;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double T = fmax(cell_T(p, i), 1e-300);
+    const double aT4 = p.a * (T * T) * (T * T);
+    const double v0 = p.v[i], v1 = p.v[n + i], v2 = p.v[2 * n + i];
+    const double rho = p.rho[i];
+    const double yT = (double)Yn[i * no] * ystd[0] + ymean[0];
+    const double Tg = T * exp(fmin(fmax(yT, -5.0), 5.0));
+    guess[i] = rho * p.cv * Tg + 0.5 * rho * (v0 * v0 + v1 * v1 + v2 * v2);
+    for (int g = 0; g < ng; ++g) {
+      const double yE = (double)Yn[i * no + 1 + g] * ystd[1 + g] + ymean[1 + g];
+      const double Eg = aT4 * exp(fmin(fmax(yE, -60.0), 60.0));
+      const double sg = S ? S[(int64_t)g * n + i] : 0.0;
+      guess[(int64_t)(g + 1) * n + i] = Eg - p.E[(int64_t)g * n + i] - sg;
+    }
+  }
+}
+
+}  // namespace mlp
+}  // namespace mgrhd
+
+using namespace mgrhd::mlp;
+
+// ---------------------------------------------------------------------------
+// The network handle: layer sizes, FP32 master parameters, gradients, Adam
+// moments and activation scratch for up to max_rows rows per call.
+struct mgrhd_mlp {
+  int n_in = 0, n_hidden = 0, n_out = 0;
+  static constexpr int kLayers = 4;  // 3 hidden SiLU layers + linear output
+  int64_t max_rows = 0;
+  int64_t n_params = 0;
+  int in_dim[kLayers], out_dim[kLayers];
+  int64_t w_off[kLayers], b_off[kLayers];
+  float* params = nullptr;  // [n_params] weights (out x in, row-major) then biases
+  float* grads = nullptr;
+  float* adam_m = nullptr;
+  float* adam_v = nullptr;
+  float* act = nullptr;     // H1..H3, Z1..Z3, Y, dY, dH, dZ scratch
+  float* loss = nullptr;    // device scalar
+  int64_t step = 0;
+  float* H[3];
+  float* Zs[3];
+  float* Y = nullptr;
+  float* dY = nullptr;
+  float* dA = nullptr;
+  float* dB = nullptr;
+};
+
+static inline dim3 grid1(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  if (b > 65535 * 4) b = 65535 * 4;
+  if (b < 1) b = 1;
+  return dim3((unsigned)b);
+}
+
+template <bool TA, bool TB, int EPI>
+static void gemm(hipStream_t s, const float* A, int lda, const float* B, int ldb, const float* bias,
+                 float* C, int ldc, float* Z, int64_t M, int N, int K) {
+  dim3 grid((unsigned)((M + BM - 1) / BM), (unsigned)((N + BN - 1) / BN));
+  hipLaunchKernelGGL((k_gemm<TA, TB, EPI>), grid, dim3(256), 0, s, A, lda, B, ldb, bias, C, ldc, Z,
+                     M, N, K);
+}
+
+// forward of `rows` rows.  X_fm: features feature-major [n_in x ld_x]; the
+// rows are X_fm[:, 0:rows].  Output Y row-major [rows x n_out].
+static void forward(mgrhd_mlp* m, hipStream_t s, const float* X_fm, int64_t ld_x, int64_t rows,
+                    float* Y) {
+  const float* in = X_fm;
+  for (int l = 0; l < 3; ++l) {
+    const float* W = m->params + m->w_off[l];
+    const float* b = m->params + m->b_off[l];
+    if (l == 0)
+      gemm<true, true, EPI_BIAS_SILU>(s, in, (int)ld_x, W, m->in_dim[l], b, m->H[l],
+                                      m->out_dim[l], m->Zs[l], rows, m->out_dim[l], m->in_dim[l]);
+    else
+      gemm<false, true, EPI_BIAS_SILU>(s, in, m->in_dim[l], W, m->in_dim[l], b, m->H[l],
+                                       m->out_dim[l], m->Zs[l], rows, m->out_dim[l],
+                                       m->in_dim[l]);
+    in = m->H[l];
+  }
+  gemm<false, true, EPI_BIAS>(s, in, m->in_dim[3], m->params + m->w_off[3], m->in_dim[3],
+                              m->params + m->b_off[3], Y, m->out_dim[3], nullptr, rows,
+                              m->out_dim[3], m->in_dim[3]);
+}
+
+// backward: gradients of mean((Y - T)^2) with respect to all parameters
+static void backward(mgrhd_mlp* m, hipStream_t s, const float* X_fm, int64_t ld_x, int64_t rows,
+                     const float* Tgt) {
+  const int64_t ny = rows * m->n_out;
+  hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, s, m->loss, (int64_t)1);
+  hipLaunchKernelGGL(k_mse, grid1(ny), dim3(256), 0, s, m->Y, Tgt, ny, 1.f / (float)ny, m->dY,
+                     m->loss);
+  const float* dOut = m->dY;  // gradient w.r.t. the current layer's output (pre-activation for l=3)
+  for (int l = 3; l >= 0; --l) {
+    const int no = m->out_dim[l], ni = m->in_dim[l];
+    float* dW = m->grads + m->w_off[l];
+    float* db = m->grads + m->b_off[l];
+    // dW = dOut^T [no x rows] . input [rows x ni]
+    if (l == 0)  // input X feature-major: op(B) = (X_fm)^T, stored ni x ld_x
+      gemm<true, true, EPI_NONE>(s, dOut, no, X_fm, (int)ld_x, nullptr, dW, ni, nullptr, no, ni,
+                                 (int)rows);
+    else
+      gemm<true, false, EPI_NONE>(s, dOut, no, m->H[l - 1], ni, nullptr, dW, ni, nullptr, no, ni,
+                                  (int)rows);
+    hipLaunchKernelGGL(k_colsum, dim3((no + 127) / 128), dim3(128), 0, s, dOut, rows, no, db);
+    if (l == 0) break;
+    // dH_{l-1} = dOut [rows x no] . W_l [no x ni]; then through SiLU
+    float* dH = m->dA;
+    gemm<false, false, EPI_NONE>(s, dOut, no, m->params + m->w_off[l], ni, nullptr, dH, ni,
+                                 nullptr, rows, ni, no);
+    float* dZ = (dOut == m->dB) ? m->dA : m->dB;
+    if (dZ == dH) dZ = m->dB;
+    hipLaunchKernelGGL(k_silu_bwd, grid1(rows * ni), dim3(256), 0, s, dH, m->Zs[l - 1], dZ,
+                       rows * (int64_t)ni);
+    dOut = dZ;
+  }
+}
+
+extern "C" {
+
+int mgrhd_mlp_create(int32_t n_in, int32_t n_hidden, int32_t n_out, int64_t max_rows,
+                     uint64_t seed, mgrhd_mlp** out) {
+  if (!out) return MGRHD_E_NULL;
+  *out = nullptr;
+  if (n_in < 1 || n_hidden < 1 || n_out < 1 || max_rows < 1) return MGRHD_E_SIZE;
+  mgrhd_mlp* m = new (std::nothrow) mgrhd_mlp();
+  if (!m) return MGRHD_E_DEVICE;
+  m->n_in = n_in;
+  m->n_hidden = n_hidden;
+  m->n_out = n_out;
+  m->max_rows = max_rows;
+  const int dims[5] = {n_in, n_hidden, n_hidden, n_hidden, n_out};
+  int64_t off = 0;
+  for (int l = 0; l < 4; ++l) {
+    m->in_dim[l] = dims[l];
+    m->out_dim[l] = dims[l + 1];
+    m->w_off[l] = off;
+    off += (int64_t)dims[l] * dims[l + 1];
+  }
+  for (int l = 0; l < 4; ++l) {
+    m->b_off[l] = off;
+    off += dims[l + 1];
+  }
+  m->n_params = off;
+  // He-uniform weights for SiLU layers, zero biases (host-side init, seeded)
+  std::vector<float> h(off, 0.f);
+  uint64_t z = seed ? seed : 0x9E3779B97F4A7C15ULL;
+  auto next = [&]() {
+    z += 0x9E3779B97F4A7C15ULL;
+    uint64_t x = z;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBULL;
+    x ^= x >> 31;
+    return (double)(x >> 11) * 0x1.0p-53;
+  };
+  for (int l = 0; l < 4; ++l) {
+    const double lim = std::sqrt(6.0 / dims[l]) * (l == 3 ? 0.5 : 1.0);
+    for (int64_t k = 0; k < (int64_t)dims[l] * dims[l + 1]; ++k)
+      h[m->w_off[l] + k] = (float)((2.0 * next() - 1.0) * lim);
+  }
+  const int64_t act = (int64_t)max_rows * (6 * n_hidden + 2 * n_out + 2 * std::max(n_hidden, n_out));
+  bool ok = hipMalloc(&m->params, sizeof(float) * off) == hipSuccess &&
+            hipMalloc(&m->grads, sizeof(float) * off) == hipSuccess &&
+            hipMalloc(&m->adam_m, sizeof(float) * off) == hipSuccess &&
+            hipMalloc(&m->adam_v, sizeof(float) * off) == hipSuccess &&
+            hipMalloc(&m->act, sizeof(float) * act) == hipSuccess &&
+            hipMalloc(&m->loss, sizeof(float)) == hipSuccess;
+  if (ok) {
+    ok = hipMemcpy(m->params, h.data(), sizeof(float) * off, hipMemcpyHostToDevice) == hipSuccess;
+    std::vector<float> zero(off, 0.f);
+    ok = ok && hipMemcpy(m->adam_m, zero.data(), sizeof(float) * off, hipMemcpyHostToDevice) ==
+                   hipSuccess;
+    ok = ok && hipMemcpy(m->adam_v, zero.data(), sizeof(float) * off, hipMemcpyHostToDevice) ==
+                   hipSuccess;
+    ok = ok && hipMemcpy(m->grads, zero.data(), sizeof(float) * off, hipMemcpyHostToDevice) ==
+                   hipSuccess;
+  }
+  if (!ok) {
+    mgrhd_mlp_destroy(m);
+    return MGRHD_E_DEVICE;
+  }
+  float* p = m->act;
+  for (int l = 0; l < 3; ++l) {
+    m->H[l] = p;
+    p += max_rows * n_hidden;
+    m->Zs[l] = p;
+    p += max_rows * n_hidden;
+  }
+  m->Y = p;
+  p += max_rows * n_out;
+  m->dY = p;
+  p += max_rows * n_out;
+  const int w = std::max(n_hidden, n_out);
+  m->dA = p;
+  p += max_rows * w;
+  m->dB = p;
+  *out = m;
+  return 0;
+}
+
+int64_t mgrhd_mlp_num_params(const mgrhd_mlp* m) { return m ? m->n_params : -1; }
+
+int mgrhd_mlp_get_params(const mgrhd_mlp* m, float* host, int32_t which) {
+  if (!m || !host) return MGRHD_E_NULL;
+  const float* src = which == 0 ? m->params : which == 1 ? m->grads : nullptr;
+  if (!src) return MGRHD_E_OPTION;
+  return hipMemcpy(host, src, sizeof(float) * m->n_params, hipMemcpyDeviceToHost) == hipSuccess
+             ? 0 : MGRHD_E_DEVICE;
+}
+
+int mgrhd_mlp_set_params(mgrhd_mlp* m, const float* host) {
+  if (!m || !host) return MGRHD_E_NULL;
+  return hipMemcpy(m->params, host, sizeof(float) * m->n_params, hipMemcpyHostToDevice) ==
+                 hipSuccess
+             ? 0 : MGRHD_E_DEVICE;
+}
+
+int mgrhd_mlp_forward(mgrhd_mlp* m, const float* X_fm, int64_t ld_x, int64_t rows, float* Y,
+                      mgrhd_stream_t stream) {
+  if (!m || !X_fm || !Y) return MGRHD_E_NULL;
+  if (rows < 0 || ld_x < rows) return MGRHD_E_SIZE;
+  hipStream_t s = (hipStream_t)stream;
+  for (int64_t r0 = 0; r0 < rows; r0 += m->max_rows) {
+    const int64_t r = std::min(m->max_rows, rows - r0);
+    forward(m, s, X_fm + r0, ld_x, r, Y + r0 * m->n_out);
+  }
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : (int)e;
+}
+
+int mgrhd_mlp_gradients(mgrhd_mlp* m, const float* X_fm, int64_t ld_x, int64_t rows,
+                        const float* Y_target, float* loss_out, mgrhd_stream_t stream) {
+  if (!m || !X_fm || !Y_target) return MGRHD_E_NULL;
+  if (rows < 1 || rows > m->max_rows || ld_x < rows) return MGRHD_E_SIZE;
+  hipStream_t s = (hipStream_t)stream;
+  forward(m, s, X_fm, ld_x, rows, m->Y);
+  backward(m, s, X_fm, ld_x, rows, Y_target);
+  if (loss_out)
+    (void)hipMemcpyAsync(loss_out, m->loss, sizeof(float), hipMemcpyDeviceToDevice, s);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : (int)e;
+}
+
+int mgrhd_mlp_adam_step(mgrhd_mlp* m, float lr, mgrhd_stream_t stream) {
+  if (!m) return MGRHD_E_NULL;
+  hipStream_t s = (hipStream_t)stream;
+  m->step += 1;
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = 1.f - std::pow(b1, (float)m->step), c2 = 1.f - std::pow(b2, (float)m->step);
+  hipLaunchKernelGGL(k_adam, grid1(m->n_params), dim3(256), 0, s, m->params, m->grads, m->adam_m,
+                     m->adam_v, m->n_params, lr, b1, b2, 1e-8f, c1, c2);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : (int)e;
+}
+
+int mgrhd_mlp_train_step(mgrhd_mlp* m, const float* X_fm, int64_t ld_x, int64_t rows,
+                         const float* Y_target, float lr, float* loss_out, mgrhd_stream_t stream) {
+  int rc = mgrhd_mlp_gradients(m, X_fm, ld_x, rows, Y_target, loss_out, stream);
+  if (rc) return rc;
+  return mgrhd_mlp_adam_step(m, lr, stream);
+}
+
+static int phys_args(PhysArgs& p, const double* E, const double* F, const double* rho,
+                     const double* egas, const double* v, int64_t n, const double* edges,
+                     const mgrhd_opacity_params* op, double dt, double c_hat,
+                     const mgrhd_options* opt) {
+  if (!E || !F || !rho || !egas || !v || !edges || !op || !op->chi_lo) return MGRHD_E_NULL;
+  if (n < 0 || op->n_groups < 1 || op->n_groups > MGRHD_MAX_GROUPS) return MGRHD_E_SIZE;
+  mgrhd_options d;
+  mgrhd_default_options(&d);
+  if (!opt) opt = &d;
+  std::memset(&p, 0, sizeof(p));
+  p.E = E;
+  p.F = F;
+  p.rho = rho;
+  p.egas = egas;
+  p.v = v;
+  p.kappa = op->kappa_scale;
+  p.edges = edges;
+  p.chi_lo = op->chi_lo;
+  p.alpha = op->alpha_chi;
+  p.n = n;
+  p.ng = op->n_groups;
+  p.dt = dt;
+  p.chat = c_hat;
+  p.c = opt->c;
+  p.a = opt->a_rad;
+  p.cv = opt->c_v;
+  return 0;
+}
+
+int mgrhd_mlp_features(const double* E_g, const double* F_g, const double* rho, const double* e_gas,
+                       const double* v, int64_t n, const double* group_edges,
+                       const mgrhd_opacity_params* op, double dt, double c_hat,
+                       const mgrhd_options* opt, const float* mean, const float* inv_std,
+                       float* X_fm, mgrhd_stream_t stream) {
+  PhysArgs p;
+  int rc = phys_args(p, E_g, F_g, rho, e_gas, v, n, group_edges, op, dt, c_hat, opt);
+  if (rc) return rc;
+  if (!mean || !inv_std || !X_fm) return MGRHD_E_NULL;
+  if (n == 0) return 0;
+  hipLaunchKernelGGL(k_features, grid1(n), dim3(256), 0, (hipStream_t)stream, p, mean, inv_std,
+                     X_fm);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : (int)e;
+}
+
+int mgrhd_mlp_targets(const double* E_g, const double* F_g, const double* rho, const double* e_gas,
+                      const double* v, int64_t n, const double* group_edges,
+                      const mgrhd_opacity_params* op, double dt, double c_hat,
+                      const mgrhd_options* opt, const double* E_new, const double* e_gas_new,
+                      const double* v_new, float* Y, mgrhd_stream_t stream) {
+  PhysArgs p;
+  int rc = phys_args(p, E_g, F_g, rho, e_gas, v, n, group_edges, op, dt, c_hat, opt);
+  if (rc) return rc;
+  if (!E_new || !e_gas_new || !v_new || !Y) return MGRHD_E_NULL;
+  if (n == 0) return 0;
+  hipLaunchKernelGGL(k_targets, grid1(n), dim3(256), 0, (hipStream_t)stream, p, E_new, e_gas_new,
+                     v_new, Y);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : (int)e;
+}
+
+int mgrhd_mlp_guess(const double* E_g, const double* F_g, const double* rho, const double* e_gas,
+                    const double* v, int64_t n, const double* group_edges,
+                    const mgrhd_opacity_params* op, double dt, double c_hat,
+                    const mgrhd_options* opt, const float* Y_norm, const float* y_mean,
+                    const float* y_std, double* guess, mgrhd_stream_t stream) {
+  PhysArgs p;
+  int rc = phys_args(p, E_g, F_g, rho, e_gas, v, n, group_edges, op, dt, c_hat, opt);
+  if (rc) return rc;
+  if (!Y_norm || !y_mean || !y_std || !guess) return MGRHD_E_NULL;
+  if (n == 0) return 0;
+  hipLaunchKernelGGL(k_guess, grid1(n), dim3(256), 0, (hipStream_t)stream, p, Y_norm, y_mean,
+                     y_std, opt ? opt->S_g : nullptr, guess);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : (int)e;
+}
+
+// plain product C = op(A) op(B) through the BF16 MFMA kernel (exposed for tests)
+int mgrhd_mlp_gemm(const float* A, int32_t lda, int32_t trans_a, const float* B, int32_t ldb,
+                   int32_t trans_b, float* C, int32_t ldc, int64_t M, int32_t N, int32_t K,
+                   mgrhd_stream_t stream) {
+  if (!A || !B || !C) return MGRHD_E_NULL;
+  if (M < 0 || N < 0 || K < 0) return MGRHD_E_SIZE;
+  if (M == 0 || N == 0) return 0;
+  hipStream_t s = (hipStream_t)stream;
+  if (trans_a && trans_b)
+    gemm<true, true, EPI_NONE>(s, A, lda, B, ldb, nullptr, C, ldc, nullptr, M, N, K);
+  else if (trans_a)
+    gemm<true, false, EPI_NONE>(s, A, lda, B, ldb, nullptr, C, ldc, nullptr, M, N, K);
+  else if (trans_b)
+    gemm<false, true, EPI_NONE>(s, A, lda, B, ldb, nullptr, C, ldc, nullptr, M, N, K);
+  else
+    gemm<false, false, EPI_NONE>(s, A, lda, B, ldb, nullptr, C, ldc, nullptr, M, N, K);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : (int)e;
+}
+
+void mgrhd_mlp_destroy(mgrhd_mlp* m) {
+  if (!m) return;
+  if (m->params) (void)hipFree(m->params);
+  if (m->grads) (void)hipFree(m->grads);
+  if (m->adam_m) (void)hipFree(m->adam_m);
+  if (m->adam_v) (void)hipFree(m->adam_v);
+  if (m->act) (void)hipFree(m->act);
+  if (m->loss) (void)hipFree(m->loss);
+  delete m;
+}
+
+}  // extern "C"

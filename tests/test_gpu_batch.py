@@ -52,23 +52,14 @@ def test_batch_matches_single_table_and_oracle(gpl):
     b.run()
     torch.cuda.synchronize()
     for L, w, d in zip(layouts, inputs, pd):
-        g = {k: d[k].cpu().numpy() for k in ("E_g", "F_g", "e_gas", "v")}
-        gs = d["status"].cpu().numpy()
-        assert (gs >= 0).all()
-        # the single-table entry point on the same patch
-        s, si, so, ss = U.run_gpu(w, 1)
-        same = (gs == ss) & (d["iters"].cpu().numpy() == si)
-        assert same.mean() > 0.99
-        err = U.field_errors(w, g, s, same & (ss == 0))
-        for k, e in err.items():
-            assert e < 1e-10, (L.index, k, e)
+        res = ({k: d[k].cpu().numpy() for k in ("E_g", "F_g", "e_gas", "v")},
+               d["iters"].cpu().numpy(), d["outer"].cpu().numpy(), d["status"].cpu().numpy())
+        assert (res[3] >= 0).all()
+        # the single-table entry point on the same patch (another lane split:
+        # the group sums round in another order)
+        U.compare(w, res, U.run_gpu(w, 1), label=f"patch {L.index} vs single table")
         # the oracle
-        o, oi, oo, os_ = U.run_oracle(w, 1)
-        ok = (os_ == 0) & (gs == 0) & (oi == d["iters"].cpu().numpy()) & \
-             (oo == d["outer"].cpu().numpy())
-        assert ok.mean() > 0.98
-        for k, e in U.field_errors(w, g, o, ok).items():
-            assert e < 1e-10, (L.index, k, e)
+        U.compare(w, res, U.run_oracle(w, 1), label=f"patch {L.index} vs oracle")
 
 
 def test_batch_graph_replay_matches_direct_run():
@@ -122,13 +113,9 @@ def test_batch_ragged_and_empty_patches():
     b.run()
     torch.cuda.synchronize()
     for w, d in zip(inputs, pd):
-        g = {k: d[k].cpu().numpy() for k in ("E_g", "F_g", "e_gas", "v")}
-        o, oi, oo, os_ = U.run_oracle(w, 2)
-        gs = d["status"].cpu().numpy()
-        ok = (os_ == 0) & (gs == 0) & (oi == d["iters"].cpu().numpy()) & \
-             (oo == d["outer"].cpu().numpy())
-        for k, e in U.field_errors(w, g, o, ok).items():
-            assert e < 1e-10, (k, e)
+        res = ({k: d[k].cpu().numpy() for k in ("E_g", "F_g", "e_gas", "v")},
+               d["iters"].cpu().numpy(), d["outer"].cpu().numpy(), d["status"].cpu().numpy())
+        U.compare(w, res, U.run_oracle(w, 2), label=f"ragged patch N_g={w.ng} n={w.n}")
 
 
 def test_batch_argument_errors():

@@ -1,0 +1,122 @@
+"""The warm-start network on the GPU: the BF16 matrix-core product (lane
+layout and all transpose forms), forward/backward against the FP64 numpy
+reference, training, and the warm-started solve.  GPU only."""
+import numpy as np
+import pytest
+import torch
+
+import mlp_ref
+from paper_2407_18304_amd import mgrhd, synth, warmstart
+from paper_2407_18304_amd import workloads as W
+
+import gpu_util as U
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+
+def bf16_round(x):
+    """Round float32 values to the nearest bfloat16 (ties to even)."""
+    b = np.ascontiguousarray(x, np.float32).view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+    return b.astype(np.uint32).view(np.float32)
+
+
+@pytest.mark.parametrize("ta,tb", [(False, False), (False, True), (True, False), (True, True)])
+@pytest.mark.parametrize("M,N,K", [(16, 16, 32), (100, 70, 45), (257, 130, 194)])
+def test_matrix_core_product(ta, tb, M, N, K):
+    rng = np.random.default_rng(M + N + K)
+    A = rng.normal(size=(K, M) if ta else (M, K)).astype(np.float32)
+    B = rng.normal(size=(N, K) if tb else (K, N)).astype(np.float32)
+    Cg = warmstart.gemm(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), ta, tb)
+    Ar = bf16_round(A).astype(np.float64)
+    Br = bf16_round(B).astype(np.float64)
+    ref = (Ar.T if ta else Ar) @ (Br.T if tb else Br)
+    err = np.abs(Cg.cpu().numpy() - ref).max() / np.abs(ref).max()
+    assert err < 1e-5, err
+
+
+def _small_net(ng=4, seed=3):
+    n_in, n_out = 2 + 3 * ng, 1 + ng
+    net = warmstart.MLP(n_in, n_out, 128, max_rows=4096, seed=seed)
+    return net
+
+
+def test_forward_and_gradients_match_fp64_reference():
+    rng = np.random.default_rng(5)
+    net = _small_net()
+    p = net.get_params()
+    Ws, bs = net.unpack(p.astype(np.float64))
+    rows = 512
+    X = rng.normal(size=(rows, net.n_in)).astype(np.float32)
+    T = rng.normal(size=(rows, net.n_out)).astype(np.float32)
+    Xd = torch.from_numpy(np.ascontiguousarray(X.T)).cuda()       # feature-major
+    Td = torch.from_numpy(T).cuda()
+    Y = net.forward(Xd).cpu().numpy()
+    yref, _ = mlp_ref.forward(Ws, bs, X.astype(np.float64))
+    assert np.abs(Y - yref).max() / np.abs(yref).max() < 2e-2     # BF16 operands
+    loss = float(net.gradients(Xd, Td).cpu())
+    g = net.get_params(which=1)
+    gW, gb = net.unpack(g.astype(np.float64))
+    lref, dW, db = mlp_ref.loss_and_grads(Ws, bs, X.astype(np.float64), T.astype(np.float64))
+    assert abs(loss - lref) < 2e-2 * lref
+    for l in range(4):
+        eW = np.linalg.norm(gW[l] - dW[l]) / np.linalg.norm(dW[l])
+        eb = np.linalg.norm(gb[l] - db[l]) / np.linalg.norm(db[l])
+        assert eW < 3e-2 and eb < 3e-2, (l, eW, eb)
+
+
+def test_training_reduces_loss_on_a_smooth_map():
+    rng = np.random.default_rng(7)
+    net = _small_net(seed=11)
+    n = 16384
+    X = rng.normal(size=(n, net.n_in)).astype(np.float32)
+    T = np.stack([np.sin(X[:, k % net.n_in]) + 0.3 * X[:, (k + 1) % net.n_in] ** 2
+                  for k in range(net.n_out)], 1).astype(np.float32)
+    Xd = torch.from_numpy(np.ascontiguousarray(X.T)).cuda()
+    Td = torch.from_numpy(T).cuda()
+    first = None
+    for step in range(300):
+        rows = torch.from_numpy(rng.choice(n, 1024, replace=False)).cuda()
+        loss = float(net.train_step(Xd[:, rows].contiguous(), Td[rows].contiguous(), 3e-3).cpu())
+        first = first or loss
+    final = float(((net.forward(Xd) - Td) ** 2).mean())
+    assert final < 0.1 * first, (first, final)
+
+
+def test_warm_start_same_result_fewer_iterations():
+    """Train on solver-generated pairs of the 64-group workload, then solve
+    fresh cells from the same distribution with and without the guess."""
+    consts = None
+    dw_train = synth.device_workload("config2", n=1 << 16, cell0=3 << 22)
+    consts = dw_train.consts()
+    Xr, Yr, ok = warmstart.make_training_data(dw_train, consts)
+    ws = warmstart.train(Xr, Yr, ok, epochs=6, batch=2048, holdout=4096)
+    assert ws.history[-1] < ws.history[0]
+    dw = synth.device_workload("config2", n=8192, cell0=0)
+    pristine = {k: v.clone() for k, v in dw.state.items()}
+    res = {}
+    for name in ("plain", "warm"):
+        for k in dw.state:
+            dw.state[k].copy_(pristine[k])
+        guess = ws.guess(dw.state, dw.tables, dw.kappa, consts) if name == "warm" else None
+        it = torch.zeros(dw.n, dtype=torch.int32, device="cuda")
+        stt = torch.zeros(dw.n, dtype=torch.int32, device="cuda")
+        st = dw.state
+        mgrhd.source_update(st["E_g"], st["F_g"], st["rho"], st["e_gas"], st["v"],
+                            dw.tables["edges"], dw.tables["chi_lo"], alpha_chi=dw.tables["alpha"],
+                            kappa_scale=dw.kappa, mean_mode=1, polish=1, guess=guess, iters=it,
+                            status=stt, **consts)
+        torch.cuda.synchronize()
+        res[name] = ({k: v.cpu().numpy() for k, v in st.items()}, it.cpu().numpy(),
+                     stt.cpu().numpy())
+    (gp, ip, sp), (gw, iw, sw) = res["plain"], res["warm"]
+    ok = (sp == 0) & ((sw & ~4) == 0)
+    assert ok.mean() > 0.99
+    host = synth.to_host(dw, np.arange(dw.n))
+    host.state = {k: v.cpu().numpy() for k, v in pristine.items()}
+    for k, e in U.field_errors(host, gw, gp, ok).items():
+        assert e < 1e-8, (k, e)
+    print(f"Newton iterations per cell: plain {ip[ok].mean():.3f}, warm {iw[ok].mean():.3f}; "
+          f"fallbacks {((sw & 4) != 0).mean():.4f}")
+    assert iw[ok].mean() < ip[ok].mean()

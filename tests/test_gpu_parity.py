@@ -12,13 +12,7 @@ import gpu_util as U
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
 
-TOL = 1e-10   # relative parity bound on every field
-
-
-# Cells where GPU and oracle take a different number of Newton steps or
-# outer passes (a stop test sitting on its threshold, < 1% of cells) differ
-# by the last increment of a converged iteration: bounded by this instead.
-TOL_COUNT_FLIP = 1e-8
+TOL, TOL_COUNT_FLIP = U.TOL, U.TOL_COUNT_FLIP
 
 
 def _check(w, mode, **kw):
@@ -28,36 +22,7 @@ def _check(w, mode, **kw):
 
 
 def _compare(w, mode, gpu, ora):
-    g, gi, go, gs = gpu
-    o, oi, oo, os_ = ora
-    # cells whose outer iteration does not contract (status bit 2 on the
-    # oracle) are compared for validity only: their last iterate depends on
-    # rounding.  Everything else must match.
-    both = (gs == os_)
-    assert both.mean() > 0.99, f"status agreement {both.mean():.4f}"
-    conv = (os_ == 0) & (gs == 0)
-    same = conv & (gi == oi) & (go == oo)
-    flip = conv & ~same
-    err = U.field_errors(w, g, o, same)
-    err_flip = U.field_errors(w, g, o, flip)
-    print(f"mode {mode}: n={w.n} N_g={w.ng} converged {conv.mean():.4f} "
-          f"same counts {same.mean():.4f} errors {err} count-flip cells {flip.sum()} {err_flip}")
-    for k, e in err.items():
-        assert e < TOL, (k, e)
-    for k, e in err_flip.items():
-        assert e < TOL_COUNT_FLIP, (k, e)
-    assert flip.mean() < 0.01
-    assert np.abs(gi[conv] - oi[conv]).max(initial=0) <= 2
-    # non-contracting cells: finite, valid, conserving
-    nc = (os_ & 2) != 0
-    for k in U.FIELDS:
-        assert np.isfinite(g[k].reshape(-1, w.n)[:, nc]).all()
-    # invalid / untouched cells agree exactly
-    inv = (os_ & 8) != 0
-    for k in U.FIELDS:
-        a, b = g[k].reshape(-1, w.n)[:, inv], w.state[k].reshape(-1, w.n)[:, inv]
-        assert np.array_equal(a, b)
-    return g, gs
+    return U.compare(w, gpu, ora, label=f"mode {mode}")
 
 
 @pytest.mark.parametrize("mode", [0, 1, 2])
