@@ -44,6 +44,7 @@ struct KArgs {
 
 constexpr int kBlock = 256;
 constexpr int kWave = 64;
+constexpr double kThird = 1.0 / 3.0;
 
 // LDS copy of the group tables with per-group constants (NGM = G * LPC).
 template <int NGM>
@@ -174,15 +175,16 @@ __device__ __forceinline__ void evaluate(const Tables<NGM>& t, int ng, int j, do
       const double ch = chiK[k];
       if (MODE == MGRHD_MEAN_PC) {
         c.chiF[k] = ch;
-        c.emit[k] = ch * (Bt - Dnu / 3.0);
+        c.emit[k] = ch * (Bt - Dnu * kThird);
       } else {
         const double ac = t.achi[g];
         const double dchib = rho_kappa * t.chit[g] * (t.rac[g] * p.ehi - p.elo);
-        const double num = (ch + ch / 3.0) * p.b + (ac * ch * p.b - dchib) / 3.0;
-        const double den = (4.0 * p.b - (p.ehi - p.elo)) / 3.0;
+        // eq. chiDiff with numerator and denominator both multiplied by 3
+        const double num = (4.0 + ac) * ch * p.b - dchib;
+        const double den = 4.0 * p.b - (p.ehi - p.elo);
         const double f = num / den;
         c.chiF[k] = (den > 0.0 && isfinite(f)) ? f : ch;
-        c.emit[k] = ch * Bt - aT4 * dchib * p.scale / 3.0;
+        c.emit[k] = ch * Bt - aT4 * dchib * p.scale * kThird;
       }
     }
   } else {
@@ -223,11 +225,11 @@ __device__ __forceinline__ void evaluate(const Tables<NGM>& t, int ng, int j, do
       c.chiB[k] = chB;
       c.chiE[k] = chE;
       const double dchib = chl * (t.rac[g] * ehi[k] - elo[k]);
-      const double num = (chB + chE / 3.0) * b[k] + (ac * chE * b[k] - dchib) / 3.0;
-      const double den = (4.0 * b[k] - (ehi[k] - elo[k])) / 3.0;
+      const double num = (3.0 * chB + (1.0 + ac) * chE) * b[k] - dchib;  // both times 3
+      const double den = 4.0 * b[k] - (ehi[k] - elo[k]);
       const double f = num / den;
       c.chiF[k] = (den > 0.0 && isfinite(f)) ? f : chE;
-      c.emit[k] = chB * Bt - aT4 * dchib * scale[k] / 3.0;
+      c.emit[k] = chB * Bt - aT4 * dchib * scale[k] * kThird;
     }
   }
 }
@@ -242,15 +244,17 @@ __device__ __forceinline__ void pressure_dot_v(int closure, double c, double E, 
   }
   const double fm = sqrt(F0 * F0 + F1 * F1 + F2 * F2);
   if (closure == MGRHD_CLOSURE_EDDINGTON || fm == 0.0) {
-    Pv[0] = E * v[0] / 3.0;
-    Pv[1] = E * v[1] / 3.0;
-    Pv[2] = E * v[2] / 3.0;
+    const double e3 = E * kThird;
+    Pv[0] = e3 * v[0];
+    Pv[1] = e3 * v[1];
+    Pv[2] = e3 * v[2];
     return;
   }
   double f = fm / (c * E);
   f = f > 1.0 ? 1.0 : f;
   const double chi = (3.0 + 4.0 * f * f) / (5.0 + 2.0 * sqrt(4.0 - 3.0 * f * f));
-  const double n0 = F0 / fm, n1 = F1 / fm, n2 = F2 / fm;
+  const double ifm = 1.0 / fm;
+  const double n0 = F0 * ifm, n1 = F1 * ifm, n2 = F2 * ifm;
   const double nv = n0 * v[0] + n1 * v[1] + n2 * v[2];
   const double p = 0.5 * (1.0 - chi), q = 0.5 * (3.0 * chi - 1.0);
   Pv[0] = E * (p * v[0] + q * n0 * nv);
@@ -511,22 +515,23 @@ __device__ __forceinline__ bool flux_step(const KArgs& a, const Tables<NGM>& t, 
     const double chE = (MODE == MGRHD_MEAN_PPL_FREE) ? c.chiE[k] : s.chiK[k];
     double Pv[3];
     pressure_dot_v(a.closure, a.c, Enew, s.Fk[0][k], s.Fk[1][k], s.Fk[2][k], s.v, Pv);
-    const double den = 1.0 + cdt * c.chiF[k];
+    const double iden = 1.0 / (1.0 + cdt * c.chiF[k]);
     const double q = (1.0 + t.achi[g]) * chE;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const double f0 = a.F[((int64_t)d * ng + g) * n + i];  // F_g^(t)
-      const double f = (f0 + cdt * (s.v[d] * c.emit[k] + q * Pv[d])) / den;
+      const double f = (f0 + cdt * (s.v[d] * c.emit[k] + q * Pv[d])) * iden;
       Fn[d][k] = f;
       dmom[d] += f - f0;
     }
   }
   const double ccc = 1.0 / (a.c * a.chat);
+  const double irho = 1.0 / s.rho;
   double vn[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     dmom[d] = cell_sum<LPC>(dmom[d], s.lpc);
-    vn[d] = (s.rho * a.v[(int64_t)d * n + i] - dmom[d] * ccc) / s.rho;  // momentum update
+    vn[d] = (s.rho * a.v[(int64_t)d * n + i] - dmom[d] * ccc) * irho;  // momentum update
   }
   double dW = 0.0;
 #pragma unroll
@@ -535,9 +540,9 @@ __device__ __forceinline__ bool flux_step(const KArgs& a, const Tables<NGM>& t, 
     if (g >= ng) continue;
     const double vf_new = vn[0] * Fn[0][k] + vn[1] * Fn[1][k] + vn[2] * Fn[2][k];
     const double vf_old = s.v[0] * s.Fk[0][k] + s.v[1] * s.Fk[1][k] + s.v[2] * s.Fk[2][k];
-    dW += fabs(cdt * (1.0 + t.achi[g]) * c.chiF[k] * (vf_new - vf_old)) / (a.c * a.c);
+    dW += fabs((1.0 + t.achi[g]) * c.chiF[k] * (vf_new - vf_old));
   }
-  dW = cell_sum<LPC>(dW, s.lpc);
+  dW = cell_sum<LPC>(dW, s.lpc) * (cdt / (a.c * a.c));
   const double ke_new = 0.5 * s.rho * (vn[0] * vn[0] + vn[1] * vn[1] + vn[2] * vn[2]);
   s.egv = s.egas_new + (ke_new - s.ke);
   s.ke = ke_new;

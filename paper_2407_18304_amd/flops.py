@@ -1,0 +1,189 @@
+"""FP64 operation count of the source update, for its ALU roofline.
+
+The source update does no dense contraction: its arithmetic runs on the FP64
+vector ALUs (peak 78.6 TFLOP/s on MI355X: 256 CUs x 2.4 GHz x 64 FP64 FMA
+lanes per CU per clock x 2).  The count below is the algorithmic work of the
+method as the kernels write it, per cell, in FLOP-equivalents:
+
+* +, -, x = 1 and fused multiply-add = 2; comparisons, selects, integer and
+  memory work = 0;
+* a call of exp, expm1, log, sqrt or a division costs the FLOP-equivalents of
+  the FP64 instruction sequence gfx950 code uses for it (FMA = 2, every other
+  FP64 arithmetic instruction = 1, compares 0), counted in the assembly of a
+  probe kernel built with the library's flags (``python -m
+  paper_2407_18304_amd.flops``, which prints the weights below).
+
+Per-unit counts come from the kernel source, operation by operation (the
+table in ``UNIT`` names each term).  The number of units per cell follows
+from the kernel's own per-cell counters: with ``iters`` Newton steps (polish
+steps not included) and ``outer`` passes, a cell takes ``iters + outer + 1``
+material evaluations, ``iters + outer`` Newton steps (one polish step per
+pass) and ``outer`` flux updates.  Which branch an edge's Planck evaluation
+takes depends on x = (h/k) nu / T; the count uses each cell's final
+temperature for every evaluation of that cell (the Newton iterates of a cell
+differ from it by the step, a small fraction of T).
+"""
+from __future__ import annotations
+
+import os
+import re
+import subprocess
+import sys
+import tempfile
+from collections import Counter
+
+import numpy as np
+
+# FLOP-equivalents of one call on gfx950 (measured by measure_weights())
+W = {"exp": 29, "expm1": 34, "log": 84, "div": 17, "sqrt": 19}
+
+PC, FIXED, FREE = 0, 1, 2
+
+
+def unit_costs(w=W):
+    """Per-unit FLOP-equivalents of the kernel source (see module doc)."""
+    e, m1, lg, dv, sq = w["exp"], w["expm1"], w["log"], w["div"], w["sqrt"]
+    # one Planck edge: x = hk/T * nu (1), x^2 and x^3 (2), then by branch
+    edge_common = 1 + 2
+    poly_P = 14 * 2 + 6              # degree-14 Horner in x^2 and the bracket
+    edge = {
+        "x<=2": edge_common + poly_P + (10 * 2 + 6),        # polynomial x/(e^x-1)
+        "2<x<=4": edge_common + e + poly_P + (4 + dv),      # x^4 u/(1-u)
+        "x>4": edge_common + e + 2 + (10 * 6 + 9 * 2) + 1 + (3 + dv),  # 10-term tail
+    }
+    # group data from its two edges (group_planck)
+    group = {"both<=4": 1, "straddle": 4, "wien": 3 + dv}
+    # per group and evaluation, after the Planck data: B~, Delta(nu B~), dB/dT (8)
+    ev_group = {
+        PC: 8 + 3,                                            # emit
+        FIXED: 8 + 4 + 4 + 3 + dv + 5,                        # dchib, chi_F num/den, emit
+        # logs of the two slope fits (B and E), two slope pairs, two group means
+        # (two expm1-brackets, a division and a rescaling exp each), chi_F, emit
+        FREE: 8 + 1 + (2 * lg + 3) + 2 * (2 * (2 + dv)) +
+              2 * (1 + 1 + 2 * (2 + m1 + dv) + 3 + dv + e) + 3 + 6 + 3 + dv + 5,
+    }
+    ev_cell = 19 + 3 + dv + 1          # T, a T^4, 1/T, hk/T
+    # Newton step per group: v.F (5), W (5), E_g (3), F_R (2), J_g0 (1), a_g b_g (2),
+    # four sums (4), update of R_g (4); PPL-free adds chi_B/chi_E, 1/tau, 1/J_gg
+    nt_group = {PC: 26, FIXED: 26, FREE: 26 + 1 + 3 * dv + 3}
+    nt_cell = 2 * (1 + dv) + 2 + (dv + 1) + (dv + 2) + (4 + dv) + 5   # 1/c^2, 1/(rho c_v),
+    #                                      F_G, two stop tests, dx_0, the step
+    # flux update per group: E_new (1), M1 closure P.v (|F|: 5+sqrt, f: 1+div, chi:
+    # 8+sqrt+div, 1/|F|: div, n: 3, n.v: 5, p q: 5, P.v: 15), 1/(1+cdt chi_F)
+    # (2+div), (1+a)chi_E (2), three components (3 x 8), dW terms (15)
+    fx_group = 1 + (42 + 2 * sq + 3 * dv) + (2 + dv) + 2 + 24 + 15
+    fx_cell = 2 * (1 + dv) + 12 + (2 + dv) + 7 + 2
+    # cell load: per group E0 (1), sum (1), chi (2), 1/tau and 1/J_gg (2 + 2 div)
+    ld_group = {PC: 5 + 2 * dv, FIXED: 6 + 2 * dv, FREE: 2}
+    ld_cell = 2 + 7 + 2 + dv
+    return dict(edge=edge, group=group, ev_group=ev_group, ev_cell=ev_cell,
+                nt_group=nt_group, nt_cell=nt_cell, fx_group=fx_group, fx_cell=fx_cell,
+                ld_group=ld_group, ld_cell=ld_cell)
+
+
+UNIT = unit_costs()
+
+
+def edge_mix(nu, hk, T):
+    """Per cell: numbers of edges with x <= 2, 2 < x <= 4, x > 4 and of groups
+    whose edges are both at x <= 4, straddle x = 4, or lie beyond it.
+    nu: ascending edges [N_g+1]; T: final temperatures [n] (numpy or torch)."""
+    xp = _xp(T)
+    ng = len(nu) - 1
+    nu_t = xp.asarray(nu) if xp is np else xp.as_tensor(nu, dtype=T.dtype, device=T.device)
+    n2 = _searchsorted(xp, nu_t, 2.0 * T / hk)
+    n4 = _searchsorted(xp, nu_t, 4.0 * T / hk)
+    e_le2 = n2
+    e_24 = n4 - n2
+    e_gt4 = (ng + 1) - n4
+    g_wien = xp.clip(ng - n4, 0, None) if xp is np else (ng - n4).clamp(min=0)
+    g_strad = ((n4 >= 1) & (n4 <= ng)) * 1
+    g_both = ng - g_wien - g_strad
+    return e_le2, e_24, e_gt4, g_both, g_strad, g_wien
+
+
+def _xp(a):
+    return np if isinstance(a, np.ndarray) else sys.modules["torch"]
+
+
+def _searchsorted(xp, sorted_seq, v):
+    if xp is np:
+        return np.searchsorted(sorted_seq, v, side="right")
+    return xp.searchsorted(sorted_seq, v.contiguous(), right=True)
+
+
+def flops_per_cell(ng, mode, iters, outer, mix, u=UNIT, valid=None):
+    """FLOP-equivalents per cell (array).  iters, outer: the kernel's per-cell
+    counters; mix: edge_mix(...) of the cell's final temperature."""
+    e_le2, e_24, e_gt4, g_both, g_strad, g_wien = mix
+    E = u["edge"]
+    G = u["group"]
+    per_eval = (e_le2 * E["x<=2"] + e_24 * E["2<x<=4"] + e_gt4 * E["x>4"] +
+                g_both * G["both<=4"] + g_strad * G["straddle"] + g_wien * G["wien"] +
+                ng * u["ev_group"][mode] + u["ev_cell"])
+    n_eval = iters + outer + 1
+    n_newton = iters + outer
+    f = (n_eval * per_eval + n_newton * (ng * u["nt_group"][mode] + u["nt_cell"]) +
+         outer * (ng * u["fx_group"] + u["fx_cell"]) + ng * u["ld_group"][mode] + u["ld_cell"])
+    if valid is not None:
+        f = f * valid
+    return f
+
+
+# ---------------------------------------------------------------------------
+PROBE = r"""
+#include <hip/hip_runtime.h>
+#include <cmath>
+#define K(name, expr) extern "C" __global__ void name(const double* __restrict__ a, \
+    double* __restrict__ o) { int i = threadIdx.x; double x = a[i]; o[i] = expr; }
+K(p_exp, exp(x))
+K(p_expm1, expm1(x))
+K(p_log, log(x))
+K(p_div, a[i + 64] / x)
+K(p_sqrt, sqrt(x))
+"""
+
+
+def _flop_weight(ins: str) -> int:
+    if "_cmp" in ins or "cvt" in ins or "class" in ins:
+        return 0
+    if ins.startswith(("v_fma_f64", "v_fmac_f64", "v_div_fmas_f64")):
+        return 2
+    return 1
+
+
+def measure_weights(hipcc="/opt/rocm/bin/hipcc", arch="gfx950"):
+    """Compile the probe with the library's FP64 flags and count the
+    FLOP-equivalents of each function's FP64 instructions."""
+    with tempfile.TemporaryDirectory() as d:
+        src, asm = os.path.join(d, "probe.hip"), os.path.join(d, "probe.s")
+        with open(src, "w") as f:
+            f.write(PROBE)
+        subprocess.run([hipcc, f"--offload-arch={arch}", "-O3", "-Xclang", "-target-feature",
+                        "-Xclang", "-packed-fp32-ops", "--cuda-device-only", "-S", "-o", asm,
+                        src], check=True, capture_output=True)
+        text = open(asm).read()
+    out, cur, body = {}, None, []
+    for line in text.splitlines():
+        m = re.match(r"^p_(\w+):", line)
+        if m:
+            cur, body = m.group(1), []
+            continue
+        if cur is None:
+            continue
+        tok = line.strip().split()
+        if tok and tok[0] == "s_endpgm":
+            c = Counter(t for t in body if t.startswith("v_") and "f64" in t)
+            out[cur] = sum(_flop_weight(k) * v for k, v in c.items())
+            cur = None
+        elif tok:
+            body.append(tok[0])
+    return out
+
+
+if __name__ == "__main__":
+    w = measure_weights()
+    print("FLOP-equivalents per call:", w)
+    u = unit_costs(w)
+    for k, v in u.items():
+        print(f"  {k}: {v}")

@@ -102,13 +102,18 @@ def compare(w, gpu, ref, label="", tol=TOL, tol_flip=TOL_COUNT_FLIP):
     err = field_errors(w, g, o, same)
     err_flip = field_errors(w, g, o, flip)
     print(f"{label}: n={w.n} N_g={w.ng} converged {conv.mean():.4f} non-contracting "
-          f"{chaotic.mean():.4f} same counts {same.mean():.4f} errors {err} "
-          f"count-flip cells {flip.sum()} {err_flip}")
+          f"{chaotic.mean():.4f} (gpu {((gs & 2) != 0).mean():.4f} ref {((os_ & 2) != 0).mean():.4f})"
+          f" same counts {same.mean():.4f} errors {err} count-flip cells {flip.sum()} "
+          f"(outer {(conv & (go != oo)).sum()}) {err_flip}")
     for k, e in err.items():
         assert e < tol, (label, k, e)
     for k, e in err_flip.items():
         assert e < tol_flip, (label, k, e)
-    assert flip.sum() <= max(0.01 * conv.sum(), 1), (label, int(flip.sum()))
+    # The outer stop test compares the change of the velocity terms with
+    # 1e-13 E_tot, a few hundred rounding errors: which pass meets it is
+    # decided by rounding in a few percent of the cells (the results of those
+    # cells still agree within tol_flip, checked above).
+    assert flip.sum() <= max(0.1 * conv.sum(), 1), (label, int(flip.sum()))
     assert np.abs(gi[conv] - oi[conv]).max(initial=0) <= 2
     # non-contracting cells: finite
     for k in FIELDS:
