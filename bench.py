@@ -46,7 +46,9 @@ def main():
     ap.add_argument("--cells", type=int, default=0, help="override the cell count")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline sample (0 = skip)")
-    ap.add_argument("--variant", default="", help="LPCxG kernel variant override, e.g. 8x8")
+    ap.add_argument("--variant", default="",
+                    help="kernel variant override LPCxG[xW] (lanes per cell, groups per lane, "
+                         "waves per SIMD), e.g. 16x4 or 16x4x3")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -68,8 +70,7 @@ def main():
     dw = synth.device_workload(name, n=n)
     ng = dw.ng
     if args.variant:
-        lpc, g = (int(x) for x in args.variant.split("x"))
-        mgrhd.set_variant(ng, lpc, g)
+        mgrhd.set_variant(ng, *(int(x) for x in args.variant.split("x")))
     pristine = {k: v.clone() for k, v in dw.state.items()}
     st = dw.state
     iters = torch.zeros(n, dtype=torch.int32, device=dev)

@@ -106,6 +106,13 @@ typedef struct {
   int32_t* iters;                 /* [n] out: Newton steps summed over passes, or NULL */
   int32_t* outer;                 /* [n] out: outer passes, or NULL                */
   int32_t* status;                /* [n] out: MGRHD_ST_* bits, or NULL             */
+  int32_t guess_kind;             /* 0: guess holds (E_gas, R_g) for every cell;
+                                     1: only row 0 (E_gas, [n]) is read, and each
+                                     R_g is taken from its own group balance at
+                                     that temperature (eq. Rnew inverted for E_g
+                                     with F_R,g = 0, eq. FGFR), so the first Newton
+                                     step corrects the temperature alone       */
+  int32_t reserved;
 } mgrhd_options;
 
 /* Fill *opt with the defaults: c = a_rad = h_over_k = 1, c_v = 3/2,
@@ -134,12 +141,21 @@ int mgrhd_source_update(double* E_g, double* F_g, const double* rho, double* e_g
                         const mgrhd_opacity_params* opacity, double dt, double c_hat,
                         mgrhd_stream_t stream, const mgrhd_options* opt);
 
-/* Kernel variant used for a given group count: lanes per cell and groups per
- * lane.  mgrhd_set_variant overrides the built-in choice for n_groups (0, 0
- * restores it); unknown variants return MGRHD_E_OPTION. */
+/* Kernel variant used for a given group count: lanes per cell, groups per
+ * lane and the register budget, given as the minimum resident waves per SIMD
+ * it is compiled for (more waves: fewer registers per lane).
+ * mgrhd_set_variant overrides the built-in choice for n_groups (0, 0, 0
+ * restores it; waves_per_simd = 0 takes the default budget of the pair);
+ * variants that are not compiled, or whose lanes x groups < n_groups, return
+ * MGRHD_E_OPTION.  Any pointer of mgrhd_get_variant may be NULL. */
 int mgrhd_get_variant(int32_t n_groups, int32_t mean_mode, int32_t* lanes_per_cell,
-                      int32_t* groups_per_lane);
-int mgrhd_set_variant(int32_t n_groups, int32_t lanes_per_cell, int32_t groups_per_lane);
+                      int32_t* groups_per_lane, int32_t* waves_per_simd);
+int mgrhd_set_variant(int32_t n_groups, int32_t lanes_per_cell, int32_t groups_per_lane,
+                      int32_t waves_per_simd);
+/* The compiled variants, k = 0 .. mgrhd_variant_count() - 1 (for autotuners). */
+int32_t mgrhd_variant_count(void);
+int mgrhd_variant_info(int32_t k, int32_t* lanes_per_cell, int32_t* groups_per_lane,
+                       int32_t* waves_per_simd);
 
 /* ---- Batched AMR-like patches: one persistent launch over many patches ----
  * Each patch holds its own SoA block (same layout as mgrhd_source_update,
@@ -242,12 +258,16 @@ int mgrhd_mlp_targets(const double* E_g, const double* F_g, const double* rho, c
                       const mgrhd_opacity_params* opacity, double dt, double c_hat,
                       const mgrhd_options* opt, const double* E_new, const double* e_gas_new,
                       const double* v_new, float* Y, mgrhd_stream_t stream);
-/* Newton guess [(N_g+1) x n] (E_gas, R_g) from a normalised prediction */
+/* Newton guess from a normalised prediction Y_norm [n x (1+N_g)] (row-major)
+ * de-normalised with y_mean, y_std [1+N_g]: guess_kind 0 writes
+ * [(N_g+1) x n] (E_gas, R_g); guess_kind 1 writes E_gas alone, [n], for
+ * mgrhd_options.guess_kind = 1. */
 int mgrhd_mlp_guess(const double* E_g, const double* F_g, const double* rho, const double* e_gas,
                     const double* v, int64_t n, const double* group_edges,
                     const mgrhd_opacity_params* opacity, double dt, double c_hat,
                     const mgrhd_options* opt, const float* Y_norm, const float* y_mean,
-                    const float* y_std, double* guess, mgrhd_stream_t stream);
+                    const float* y_std, int32_t guess_kind, double* guess,
+                    mgrhd_stream_t stream);
 /* C = op(A) op(B) with the BF16 matrix-core kernel (FP32 in and out) */
 int mgrhd_mlp_gemm(const float* A, int32_t lda, int32_t trans_a, const float* B, int32_t ldb,
                    int32_t trans_b, float* C, int32_t ldc, int64_t M, int32_t N, int32_t K,

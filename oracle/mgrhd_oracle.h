@@ -64,6 +64,9 @@ typedef struct {
   int32_t* iters;                 /* [n] out: Newton steps (all outer passes) */
   int32_t* outer;                 /* [n] out: outer passes, or NULL           */
   int32_t* status;                /* [n] out: ORA_ST_* bits, or NULL          */
+  int32_t guess_kind;             /* 0: guess holds (E_gas, R_g); 1: only row 0
+                                     (E_gas) is read and each R_g solves its own
+                                     group balance at that temperature        */
 } ora_options;
 
 /* Fill *o with the paper's defaults: eps 1e-11 / 1e-13, M1 closure,

@@ -52,7 +52,7 @@ class OraOptions(C.Structure):
                 ("closure", C.c_int32), ("polish", C.c_int32),
                 ("S_g", C.POINTER(C.c_double)), ("guess", C.POINTER(C.c_double)),
                 ("iters", C.POINTER(C.c_int32)), ("outer", C.POINTER(C.c_int32)),
-                ("status", C.POINTER(C.c_int32))]
+                ("status", C.POINTER(C.c_int32)), ("guess_kind", C.c_int32)]
 
 
 _lib = None
@@ -148,7 +148,7 @@ def source_update(state: dict, edges, chi_lo, *, mean_mode=MEAN_PPL_FIXED, alpha
                   chi_hi=None, kappa_scale=None, dt=1.0, c_hat=1.0, c=1.0, a_rad=1.0,
                   h_over_k=1.0, c_v=1.5, eps_newton=1e-11, eps_outer=1e-13,
                   max_newton=100, max_outer=10, closure=CLOSURE_M1, polish=0, S_g=None,
-                  guess=None, n_threads=0):
+                  guess=None, guess_kind=0, n_threads=0):
     """Run the oracle on a copy of ``state`` (dict of E_g [N_g,n], F_g [3,N_g,n],
     rho [n], e_gas [n], v [3,n]).  Returns (new_state, iters, outer, status)."""
     E = np.array(state["E_g"], dtype=np.float64, order="C", copy=True)
@@ -165,6 +165,8 @@ def source_update(state: dict, edges, chi_lo, *, mean_mode=MEAN_PPL_FIXED, alpha
     kappa_scale = None if kappa_scale is None else np.ascontiguousarray(kappa_scale, np.float64)
     S_g = None if S_g is None else np.ascontiguousarray(S_g, np.float64)
     guess = None if guess is None else np.ascontiguousarray(guess, np.float64)
+    if guess is not None and guess_kind == 1 and guess.ndim == 1:
+        guess = guess[None, :]                    # temperature-only: row 0 alone
     iters = np.zeros(n, np.int32)
     outer = np.zeros(n, np.int32)
     status = np.zeros(n, np.int32)
@@ -175,6 +177,7 @@ def source_update(state: dict, edges, chi_lo, *, mean_mode=MEAN_PPL_FIXED, alpha
     opt.eps_newton, opt.eps_outer = eps_newton, eps_outer
     opt.max_newton, opt.max_outer, opt.closure, opt.polish = max_newton, max_outer, closure, polish
     opt.S_g, opt.guess = _dp(S_g), _dp(guess)
+    opt.guess_kind = guess_kind
     opt.iters, opt.outer, opt.status = _ip(iters), _ip(outer), _ip(status)
     rc = lib().ora_source_update(_dp(E), _dp(F), _dp(rho), _dp(eg), _dp(v), n, _dp(edges),
                                  C.byref(op), float(dt), float(c_hat), C.byref(opt),

@@ -48,6 +48,7 @@ typedef struct {
   double dt, chat, c, a, hk, cv, eps, eps_out;
   double *E_g, *F_g, *e_gas, *v;
   const double *rho, *S, *guess;
+  int32_t guess_kind;
   int32_t *iters, *outer, *status;
 } problem;
 
@@ -138,7 +139,7 @@ static void pressure_dot_v(int closure, double c, double E, const double F[3],
 /* One inner stage.  Returns 0 converged, 1 hit max_newton, 2 T <= 0. */
 static int newton(const problem* p, work* w, double rho, double rho_kappa,
                   double egas0, double etot, const double v[3], double* egv,
-                  int32_t* steps) {
+                  int32_t* steps, int elim) {
   const int32_t ng = p->ng;
   const double cc = p->c / p->chat;
   const double ke = 0.5 * rho * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
@@ -148,6 +149,18 @@ static int newton(const problem* p, work* w, double rho, double rho_kappa,
     if (!(T > 0.0) || !isfinite(T)) return 2;
     for (int32_t g = 0; g < ng; ++g) w->Ecur[g] = w->E0[g] + w->R[g] + w->S[g];
     material(p, w, T, rho_kappa, w->Ecur);
+    if (elim) {
+      /* temperature-only start: at this T, eq. Rnew inverted for E_g and
+       * F_R,g = 0 (eq. FGFR) are linear in R_g alone; take that R_g */
+      for (int32_t g = 0; g < ng; ++g) {
+        double tauE = p->chat * p->dt * w->chiE[g];
+        double W = p->chat * p->dt * (1.0 + p->achi[g]) * w->chiF[g] * w->vF[g] /
+                   (p->c * p->c);
+        w->R[g] = (w->chiB[g] / w->chiE[g] * w->Bt[g] + W / tauE - w->E0[g] - w->S[g]) /
+                  (1.0 + 1.0 / tauE);
+      }
+      elim = 0;
+    }
 
     /* residuals of eq. FGFR with R_g from eq. Rnew inverted for E_g */
     double sumR = 0.0, sumabs = 0.0;
@@ -225,7 +238,8 @@ static void solve_cell(const problem* p, work* w, int64_t i) {
   int warm = p->guess != NULL;
   if (warm) {
     egv = p->guess[i];
-    for (int32_t g = 0; g < ng; ++g) w->R[g] = p->guess[(int64_t)(g + 1) * n + i];
+    for (int32_t g = 0; g < ng; ++g)
+      w->R[g] = p->guess_kind == 1 ? 0.0 : p->guess[(int64_t)(g + 1) * n + i];
   } else {
     egv = egas0; /* READING: plain Newton starts from the old state */
     for (int32_t g = 0; g < ng; ++g) w->R[g] = 0.0;
@@ -238,12 +252,13 @@ static void solve_cell(const problem* p, work* w, int64_t i) {
     ++passes;
     for (int32_t g = 0; g < ng; ++g)
       w->vF[g] = v[0] * w->Fk[3 * g] + v[1] * w->Fk[3 * g + 1] + v[2] * w->Fk[3 * g + 2];
-    int rc = newton(p, w, rho, rho_kappa, egas0, etot, v, &egv, &steps);
+    int rc = newton(p, w, rho, rho_kappa, egas0, etot, v, &egv, &steps,
+                    k == 0 && warm && p->guess_kind == 1);
     if (k == 0 && warm && rc != 0) {
       st |= ORA_ST_FALLBACK;
       egv = egas0;
       for (int32_t g = 0; g < ng; ++g) w->R[g] = 0.0;
-      rc = newton(p, w, rho, rho_kappa, egas0, etot, v, &egv, &steps);
+      rc = newton(p, w, rho, rho_kappa, egas0, etot, v, &egv, &steps, 0);
     }
     if (rc == 1) st |= ORA_ST_NEWTON_MAXIT;
     if (rc == 2) {
@@ -397,7 +412,8 @@ int ora_source_update(double* E_g, double* F_g, const double* rho, double* e_gas
   if (!(opt->c > 0.0) || !(opt->a_rad > 0.0) || !(opt->h_over_k > 0.0) || !(opt->c_v > 0.0))
     return -5;
   if (!(opt->eps_newton > 0.0) || !(opt->eps_outer > 0.0) || opt->max_newton < 1 ||
-      opt->max_outer < 1 || opt->polish < 0 || opt->closure < 0 || opt->closure > 1)
+      opt->max_outer < 1 || opt->polish < 0 || opt->closure < 0 || opt->closure > 1 ||
+      opt->guess_kind < 0 || opt->guess_kind > 1)
     return -6;
 
   problem p;
@@ -427,6 +443,7 @@ int ora_source_update(double* E_g, double* F_g, const double* rho, double* e_gas
   p.rho = rho;
   p.S = opt->S_g;
   p.guess = opt->guess;
+  p.guess_kind = opt->guess_kind;
   p.iters = opt->iters;
   p.outer = opt->outer;
   p.status = opt->status;

@@ -1,7 +1,7 @@
 """Autotuner for the source-update kernels.
 
-Single-table kernel: the compiled variants (lanes per cell x groups per lane)
-that cover N_g are timed on a sample of the workload (inputs restored before
+Single-table kernel: the compiled variants (lanes per cell x groups per lane
+x register budget) that cover N_g are timed on a sample of the workload (inputs restored before
 every timed launch, HIP events on the launch stream) and the fastest is
 installed with mgrhd_set_variant.  Batched launch: groups per lane, resident
 workgroups per CU and cells per work item are timed the same way.  Results are
@@ -17,9 +17,6 @@ import torch
 from . import mgrhd
 
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json")
-# compiled variants of the single-table kernel: (lanes per cell, groups per lane)
-VARIANTS = [(1, 4), (2, 4), (4, 4), (8, 4), (16, 4), (32, 4), (64, 4), (2, 2), (4, 2), (8, 2),
-            (16, 2), (32, 2), (4, 1), (8, 1), (16, 1)]
 
 
 def arch() -> str:
@@ -45,7 +42,8 @@ def apply_cache(path=CACHE) -> dict:
     for key, rec in cache.get("single", {}).items():
         ng = int(key.split(":")[0])
         try:
-            mgrhd.set_variant(ng, rec["lanes_per_cell"], rec["groups_per_lane"])
+            mgrhd.set_variant(ng, rec["lanes_per_cell"], rec["groups_per_lane"],
+                              rec.get("waves_per_simd", 0))
         except mgrhd.MgrhdError:
             pass
     return cache
@@ -80,23 +78,23 @@ def tune_single(dw, mode=mgrhd.MEAN_PPL_FIXED, reps=3, path=CACHE, log=print):
                             kappa_scale=dw.kappa, mean_mode=mode, polish=1, **dw.consts())
 
     results = []
-    for lpc, g in VARIANTS:
-        if lpc * g < dw.ng or lpc * g >= 4 * dw.ng:
+    for lpc, g, wps in mgrhd.variants():
+        if lpc * g < dw.ng or lpc * g >= 2 * dw.ng:
             continue
-        mgrhd.set_variant(dw.ng, lpc, g)
+        mgrhd.set_variant(dw.ng, lpc, g, wps)
         run()                    # warm up (first launch loads the code object)
         ms = _time(run, restore, reps)
-        results.append((ms, lpc, g))
-        log(f"  N_g={dw.ng} mode={mode}: {lpc} lanes x {g} groups -> {ms:.3f} ms")
+        results.append((ms, lpc, g, wps))
+        log(f"  N_g={dw.ng} mode={mode}: {lpc} lanes x {g} groups, {wps} waves/SIMD -> {ms:.3f} ms")
     restore()
-    ms, lpc, g = min(results)
-    mgrhd.set_variant(dw.ng, lpc, g)
+    ms, lpc, g, wps = min(results)
+    mgrhd.set_variant(dw.ng, lpc, g, wps)
     cache = load_cache(path)
     ent = cache.setdefault(arch(), {}).setdefault("single", {})
-    ent[f"{dw.ng}:{mode}"] = {"lanes_per_cell": lpc, "groups_per_lane": g, "ms": ms,
-                             "cells": dw.n, "all": [[m, l, gg] for m, l, gg in sorted(results)]}
+    ent[f"{dw.ng}:{mode}"] = {"lanes_per_cell": lpc, "groups_per_lane": g, "waves_per_simd": wps,
+                             "ms": ms, "cells": dw.n, "all": [list(r) for r in sorted(results)]}
     save_cache(cache, path)
-    return lpc, g, ms
+    return lpc, g, wps, ms
 
 
 def tune_batch(batch, restore, candidates=None, reps=2, path=CACHE, key="patches", log=print):

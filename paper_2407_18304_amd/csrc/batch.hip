@@ -185,6 +185,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_batch(BatchArgs b) {
     if (s.phase == P_FLUX) {
       if (!flux_step<G, 0, MODE, kBatchNGM>(a, tab, j, s, c)) continue;
     }
+    if (s.elim) group_balance<G, MODE, kBatchNGM>(a, tab, j, s, c);
     newton_step<G, 0, MODE, kBatchNGM>(a, tab, j, s, c);
   }
 }
@@ -270,7 +271,8 @@ int mgrhd_batch_create(const mgrhd_patch* patches, int32_t n_patches, int32_t me
   if (!pos(opt->c) || !pos(opt->a_rad) || !pos(opt->h_over_k) || !pos(opt->c_v))
     return MGRHD_E_SCALAR;
   if (!pos(opt->eps_newton) || !pos(opt->eps_outer) || opt->max_newton < 1 ||
-      opt->max_outer < 1 || opt->polish < 0 || opt->polish > 4)
+      opt->max_outer < 1 || opt->polish < 0 || opt->polish > 4 || opt->guess_kind < 0 ||
+      opt->guess_kind > 1)
     return MGRHD_E_OPTION;
   mgrhd_batch* bt = new (std::nothrow) mgrhd_batch();
   if (!bt) return MGRHD_E_DEVICE;
@@ -306,6 +308,7 @@ int mgrhd_batch_create(const mgrhd_patch* patches, int32_t n_patches, int32_t me
     a.kappa = q.kappa_scale;
     a.S = q.S_g;
     a.guess = q.guess;
+    a.guess_kind = opt->guess_kind;
     a.iters = q.iters;
     a.outer = q.outer;
     a.status = q.status;

@@ -273,10 +273,11 @@ __global__ void k_targets(PhysArgs p, const double* __restrict__ E_new,
   }
 }
 
-// Newton guess (E_gas, R_g) from the de-normalised prediction.
+// Newton guess from the de-normalised prediction: (E_gas, R_g), or E_gas alone
+// (kind 1; the solver then takes each R_g from its group balance).
 __global__ void k_guess(PhysArgs p, const float* __restrict__ Yn, const float* __restrict__ ymean,
                         const float* __restrict__ ystd, const double* __restrict__ S,
-                        double* __restrict__ guess) {
+                        int kind, double* __restrict__ guess) {
   const int64_t n = p.n;
   const int ng = p.ng, no = ng + 1;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -288,6 +289,7 @@ __global__ void k_guess(PhysArgs p, const float* __restrict__ Yn, const float* _
     const double yT = (double)Yn[i * no] * ystd[0] + ymean[0];
     const double Tg = T * exp(fmin(fmax(yT, -5.0), 5.0));
     guess[i] = rho * p.cv * Tg + 0.5 * rho * (v0 * v0 + v1 * v1 + v2 * v2);
+    if (kind == 1) continue;
     for (int g = 0; g < ng; ++g) {
       const double yE = (double)Yn[i * no + 1 + g] * ystd[1 + g] + ymean[1 + g];
       const double Eg = aT4 * exp(fmin(fmax(yE, -60.0), 60.0));
@@ -606,14 +608,16 @@ int mgrhd_mlp_guess(const double* E_g, const double* F_g, const double* rho, con
                     const double* v, int64_t n, const double* group_edges,
                     const mgrhd_opacity_params* op, double dt, double c_hat,
                     const mgrhd_options* opt, const float* Y_norm, const float* y_mean,
-                    const float* y_std, double* guess, mgrhd_stream_t stream) {
+                    const float* y_std, int32_t guess_kind, double* guess,
+                    mgrhd_stream_t stream) {
   PhysArgs p;
   int rc = phys_args(p, E_g, F_g, rho, e_gas, v, n, group_edges, op, dt, c_hat, opt);
   if (rc) return rc;
   if (!Y_norm || !y_mean || !y_std || !guess) return MGRHD_E_NULL;
+  if (guess_kind < 0 || guess_kind > 1) return MGRHD_E_OPTION;
   if (n == 0) return 0;
   hipLaunchKernelGGL(k_guess, grid1(n), dim3(256), 0, (hipStream_t)stream, p, Y_norm, y_mean,
-                     y_std, opt ? opt->S_g : nullptr, guess);
+                     y_std, opt ? opt->S_g : nullptr, (int)guess_kind, guess);
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? 0 : (int)e;
 }

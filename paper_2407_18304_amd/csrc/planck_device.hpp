@@ -11,8 +11,9 @@
 //   x >  4  e^x Q(x) = (15/pi^4) sum_{k=1..10} e^{-(k-1)x} (x^3/k + 3x^2/k^2
 //           + 6x/k^3 + 6/k^4), the geometric series of 1/(e^t - 1), whose
 //           11th term is below 2e-18 of the first for x > 4;
-//   x <= 2  x/(e^x - 1) = 1 - x/2 + y Ep(y), no transcendental;
-//   x >  2  x/(e^x - 1) from u = e^{-x}.
+//   x <= 4  x/(e^x - 1) = 1 - x/2 + y Ep(y) (no exponential: an edge below the
+//           Wien side costs two polynomials, the same instructions in every lane);
+//   x >  4  x/(e^x - 1) from u = e^{-x}.
 // A group whose lower edge is beyond x = 4 (the Wien side) is returned scaled
 // by e^{x_lo}, so that nothing underflows for x up to ~1e300.
 #pragma once
@@ -32,7 +33,7 @@ __host__ __device__ __forceinline__ bool is_pinf(double x) { return x > 1.797693
 // Per-edge data at temperature T.
 struct Edge {
   double x;     // (h/k) nu / T
-  double u;     // e^{-x} for x > 2, else 1
+  double u;     // e^{-x} on the Wien side, else 1
   double val;   // P(x), or e^x Q(x) on the Wien side
   double eps;   // (15/pi^4) x^4/(e^x - 1), times e^x on the Wien side
   bool wien;    // x > kPlanckSplit
@@ -44,8 +45,9 @@ __host__ __device__ __forceinline__ Edge planck_edge(double x) {
   e.x = x;
   e.inf = is_pinf(x);
   e.wien = x > kPlanckSplit;
+  static_assert(kEdgeSplit == kPlanckSplit, "one polynomial branch below the Wien side");
   double u = 1.0;
-  if (x > kEdgeSplit) u = exp(-x);
+  if (e.wien) u = exp(-x);
   e.u = u;
   const double y = x * x;
   const double x3 = y * x;
@@ -54,14 +56,10 @@ __host__ __device__ __forceinline__ Edge planck_edge(double x) {
 #pragma unroll
     for (int k = kApDeg - 1; k >= 0; --k) ap = fma(ap, y, planck_ap(k));
     e.val = kC15 * x3 * ((1.0 / 3.0 - 0.125 * x) + ap * y);
-    if (x <= kEdgeSplit) {
-      double ep = planck_ep(kEpDeg);
+    double ep = planck_ep(kEpDeg);
 #pragma unroll
-      for (int k = kEpDeg - 1; k >= 0; --k) ep = fma(ep, y, planck_ep(k));
-      e.eps = kC15 * x3 * ((1.0 - 0.5 * x) + ep * y);
-    } else {
-      e.eps = kC15 * x3 * x * u / (1.0 - u);
-    }
+    for (int k = kEpDeg - 1; k >= 0; --k) ep = fma(ep, y, planck_ep(k));
+    e.eps = kC15 * x3 * ((1.0 - 0.5 * x) + ep * y);
   } else if (e.inf) {
     e.val = 0.0;
     e.eps = 0.0;

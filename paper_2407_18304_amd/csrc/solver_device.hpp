@@ -39,7 +39,7 @@ struct KArgs {
   int32_t ng;
   int32_t closure;
   double dt, chat, c, a, hk, cv, eps, eps_out;
-  int32_t max_newton, max_outer, polish, pad;
+  int32_t max_newton, max_outer, polish, guess_kind;
 };
 
 constexpr int kBlock = 256;
@@ -60,16 +60,42 @@ struct Tables {
   int bad;
 };
 
+// Lane exchange inside a row of 16 lanes through the DPP crossbar (no LDS
+// round trip).  All lanes of one cell group are active together, so the
+// source lane is always active.
+template <int CTRL>
+__device__ __forceinline__ double dpp_swap(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// One butterfly level of the group sum: partner lane at distance m.  Levels
+// 1 and 2 pair lanes i and i^m (quad permutations); levels 4 and 8 pair lane
+// i with the mirror image of i in its 8- or 16-lane block, which holds the
+// same partial sum as lane i^m after the lower levels, so every lane adds the
+// same two partial sums as the xor butterfly.  Levels 16 and 32 use the LDS
+// crossbar.
+template <int M>
+__device__ __forceinline__ double butterfly(double v) {
+  if (M == 1) return v + dpp_swap<0xB1>(v);   // quad_perm [1,0,3,2]
+  if (M == 2) return v + dpp_swap<0x4E>(v);   // quad_perm [2,3,0,1]
+  if (M == 4) return v + dpp_swap<0x141>(v);  // row_half_mirror
+  if (M == 8) return v + dpp_swap<0x140>(v);  // row_mirror
+  return v + __shfl_xor(v, M, kWave);
+}
+
 // Sum over the lanes of one cell group (bit-identical in every lane).  LPC = 0:
 // the group size lpc is a run-time value, uniform over the wave.
 template <int LPC>
 __device__ __forceinline__ double cell_sum(double v, int lpc) {
-  if (LPC > 0) {
-#pragma unroll
-    for (int m = 1; m < LPC; m <<= 1) v += __shfl_xor(v, m, kWave);
-  } else {
-    for (int m = 1; m < lpc; m <<= 1) v += __shfl_xor(v, m, kWave);
-  }
+  const int n = LPC > 0 ? LPC : lpc;
+  if (n >= 2) v = butterfly<1>(v);
+  if (n >= 4) v = butterfly<2>(v);
+  if (n >= 8) v = butterfly<4>(v);
+  if (n >= 16) v = butterfly<8>(v);
+  if (n >= 32) v = butterfly<16>(v);
+  if (n >= 64) v = butterfly<32>(v);
   return v;
 }
 
@@ -270,7 +296,7 @@ struct CellState {
   int64_t i;
   int lpc;  // lanes per cell (run-time copy of the template value)
   int phase, st, steps, passes, k_out, polish_left;
-  bool warm, fell_back;
+  bool warm, fell_back, elim;
   double rho, rho_kappa, egas0, etot, ke, egv, egas_new;
   double v[3];
   double R[G], E0[G], Fk[3][G];      // F_g^(t) and v^(t) stay in global memory
@@ -336,14 +362,19 @@ __device__ __forceinline__ void load_cell(const KArgs& a, const Tables<NGM>& t, 
   s.etot = s.egas0 + (a.chat / a.c) * sumE;  // E_tot of Sec. 3
   ok = bad == 0.0 && (s.egas0 - s.ke) > 0.0 && s.etot > 0.0;
   s.warm = a.guess != nullptr;
+  s.elim = false;
   s.egv = s.egas0;
   s.egas_new = s.egas0;
   if (ok && s.warm) {
     s.egv = a.guess[i];
+    if (a.guess_kind == 1) {
+      s.elim = true;  // R_g from the group balances at the first evaluation
+    } else {
 #pragma unroll
-    for (int k = 0; k < G; ++k) {
-      const int g = j * G + k;
-      if (g < ng) s.R[k] = a.guess[(int64_t)(g + 1) * n + i];
+      for (int k = 0; k < G; ++k) {
+        const int g = j * G + k;
+        if (g < ng) s.R[k] = a.guess[(int64_t)(g + 1) * n + i];
+      }
     }
   }
   if (ok) {
@@ -404,6 +435,7 @@ __device__ __forceinline__ void newton_done(const KArgs& a, int j, CellState<G>&
     // warm start failed: plain Newton from the old state (status bit 4)
     s.st |= MGRHD_ST_FALLBACK;
     s.fell_back = true;
+    s.elim = false;
     s.egv = s.egas0;
 #pragma unroll
     for (int k = 0; k < G; ++k) s.R[k] = 0.0;
@@ -423,6 +455,30 @@ __device__ __forceinline__ void newton_done(const KArgs& a, int j, CellState<G>&
   sumR = cell_sum<LPC>(sumR, s.lpc);
   s.egas_new = s.egas0 - (a.c / a.chat) * sumR;
   s.phase = P_FLUX;
+}
+
+// Temperature-only start: at the cached material state, eq. Rnew inverted for
+// E_g and F_R,g = 0 (eq. FGFR) are linear in R_g alone; take that R_g.
+template <int G, int MODE, int NGM>
+__device__ __forceinline__ void group_balance(const KArgs& a, const Tables<NGM>& t, int j,
+                                              CellState<G>& s, const Cache<G>& c) {
+  const int ng = a.ng;
+  const double cdt = a.chat * a.dt;
+  const double ic2 = 1.0 / (a.c * a.c);
+#pragma unroll
+  for (int k = 0; k < G; ++k) {
+    const int g = j * G + k;
+    if (g >= ng) continue;
+    double ratio = 1.0, itau = s.itau[k];
+    if (MODE == MGRHD_MEAN_PPL_FREE) {
+      ratio = c.chiB[k] / c.chiE[k];
+      itau = 1.0 / (cdt * c.chiE[k]);
+    }
+    const double vF = s.v[0] * s.Fk[0][k] + s.v[1] * s.Fk[1][k] + s.v[2] * s.Fk[2][k];
+    const double W = cdt * (1.0 + t.achi[g]) * c.chiF[k] * vF * ic2;
+    s.R[k] = (ratio * c.Bt[k] + W * itau - s.E0[k]) / (1.0 + itau);
+  }
+  s.elim = false;
 }
 
 // Newton consumer: residual of eq. FGFR at the cached material state, the

@@ -110,6 +110,7 @@ __global__ __launch_bounds__(kBlock, WPE) void k_source_update(KArgs a) {
       if (!flux_step<G, LPC, MODE, NGM>(a, tab, j, s, c)) continue;
       // the next inner pass starts at this temperature: fall through
     }
+    if (s.elim) group_balance<G, MODE, NGM>(a, tab, j, s, c);
     newton_step<G, LPC, MODE, NGM>(a, tab, j, s, c);
   }
 }
@@ -119,14 +120,14 @@ __global__ __launch_bounds__(kBlock, WPE) void k_source_update(KArgs a) {
 using KernelFn = void (*)(KArgs);
 
 struct Variant {
-  int lpc, g;
+  int lpc, g, wpe;  // lanes per cell, groups per lane, minimum waves per SIMD
   KernelFn fn[3];
   int blocks_per_cu[3];
 };
 
 #define MGRHD_VARIANT(G_, LPC_, WPE_)                                             \
   {                                                                               \
-    LPC_, G_,                                                                     \
+    LPC_, G_, WPE_,                                                               \
         {k_source_update<G_, LPC_, MGRHD_MEAN_PC, WPE_>,                          \
          k_source_update<G_, LPC_, MGRHD_MEAN_PPL_FIXED, WPE_>,                   \
          k_source_update<G_, LPC_, MGRHD_MEAN_PPL_FREE, WPE_>},                   \
@@ -135,34 +136,41 @@ struct Variant {
     }                                                                             \
   }
 
+// The first entry of each (lanes per cell, groups per lane) pair is its
+// default register budget; the others trade registers (spills) for waves.
 static Variant kVariants[] = {
     MGRHD_VARIANT(4, 1, 2),  MGRHD_VARIANT(4, 2, 2),  MGRHD_VARIANT(4, 4, 2),
     MGRHD_VARIANT(4, 8, 2),  MGRHD_VARIANT(4, 16, 2), MGRHD_VARIANT(4, 32, 2),
     MGRHD_VARIANT(4, 64, 2), MGRHD_VARIANT(2, 2, 3),  MGRHD_VARIANT(2, 4, 3),
     MGRHD_VARIANT(2, 8, 3),  MGRHD_VARIANT(2, 16, 3), MGRHD_VARIANT(2, 32, 3),
     MGRHD_VARIANT(1, 4, 4),  MGRHD_VARIANT(1, 8, 4),  MGRHD_VARIANT(1, 16, 4),
+    MGRHD_VARIANT(1, 32, 4), MGRHD_VARIANT(1, 64, 4), MGRHD_VARIANT(4, 4, 3),
+    MGRHD_VARIANT(4, 4, 4),  MGRHD_VARIANT(4, 16, 3), MGRHD_VARIANT(4, 16, 4),
+    MGRHD_VARIANT(2, 8, 4),  MGRHD_VARIANT(2, 32, 4),
 };
 
 // user overrides per group count (0 = built-in choice)
 static int g_override_lpc[MGRHD_MAX_GROUPS + 1];
 static int g_override_g[MGRHD_MAX_GROUPS + 1];
+static int g_override_wpe[MGRHD_MAX_GROUPS + 1];
 static std::mutex g_mutex;
 
-static Variant* find_variant(int lpc, int g) {
+// wpe = 0: the default register budget of (lpc, g)
+static Variant* find_variant(int lpc, int g, int wpe) {
   for (Variant& v : kVariants)
-    if (v.lpc == lpc && v.g == g) return &v;
+    if (v.lpc == lpc && v.g == g && (wpe == 0 || v.wpe == wpe)) return &v;
   return nullptr;
 }
 
 static Variant* choose_variant(int ng) {
   if (g_override_lpc[ng]) {
-    Variant* v = find_variant(g_override_lpc[ng], g_override_g[ng]);
+    Variant* v = find_variant(g_override_lpc[ng], g_override_g[ng], g_override_wpe[ng]);
     if (v && v->lpc * v->g >= ng) return v;
   }
   // default: 4 groups per lane, enough lanes to cover N_g
   int lpc = 1;
   while (lpc * 4 < ng) lpc <<= 1;
-  return find_variant(lpc, 4);
+  return find_variant(lpc, 4, 0);
 }
 
 // resident workgroups per CU of a variant (queried once)
@@ -214,26 +222,39 @@ void mgrhd_default_options(mgrhd_options* o) {
   o->polish = 0;
 }
 
-int mgrhd_get_variant(int32_t n_groups, int32_t mean_mode, int32_t* lpc, int32_t* gpl) {
+int mgrhd_get_variant(int32_t n_groups, int32_t mean_mode, int32_t* lpc, int32_t* gpl,
+                      int32_t* waves_per_simd) {
   (void)mean_mode;
   if (n_groups < 1 || n_groups > MGRHD_MAX_GROUPS) return MGRHD_E_SIZE;
   const Variant* v = choose_variant(n_groups);
   if (!v) return MGRHD_E_OPTION;
   if (lpc) *lpc = v->lpc;
   if (gpl) *gpl = v->g;
+  if (waves_per_simd) *waves_per_simd = v->wpe;
   return 0;
 }
 
-int mgrhd_set_variant(int32_t n_groups, int32_t lpc, int32_t gpl) {
+int32_t mgrhd_variant_count(void) { return (int32_t)(sizeof(kVariants) / sizeof(kVariants[0])); }
+
+int mgrhd_variant_info(int32_t k, int32_t* lpc, int32_t* gpl, int32_t* waves_per_simd) {
+  if (k < 0 || k >= mgrhd_variant_count()) return MGRHD_E_OPTION;
+  if (lpc) *lpc = kVariants[k].lpc;
+  if (gpl) *gpl = kVariants[k].g;
+  if (waves_per_simd) *waves_per_simd = kVariants[k].wpe;
+  return 0;
+}
+
+int mgrhd_set_variant(int32_t n_groups, int32_t lpc, int32_t gpl, int32_t waves_per_simd) {
   if (n_groups < 1 || n_groups > MGRHD_MAX_GROUPS) return MGRHD_E_SIZE;
   if (lpc == 0 && gpl == 0) {
-    g_override_lpc[n_groups] = g_override_g[n_groups] = 0;
+    g_override_lpc[n_groups] = g_override_g[n_groups] = g_override_wpe[n_groups] = 0;
     return 0;
   }
-  const Variant* v = find_variant(lpc, gpl);
+  const Variant* v = find_variant(lpc, gpl, waves_per_simd);
   if (!v || v->lpc * v->g < n_groups) return MGRHD_E_OPTION;
   g_override_lpc[n_groups] = lpc;
   g_override_g[n_groups] = gpl;
+  g_override_wpe[n_groups] = v->wpe;
   return 0;
 }
 
@@ -258,7 +279,8 @@ int mgrhd_source_update(double* E_g, double* F_g, const double* rho, double* e_g
       !pos(opt->c_v))
     return MGRHD_E_SCALAR;
   if (!pos(opt->eps_newton) || !pos(opt->eps_outer) || opt->max_newton < 1 ||
-      opt->max_outer < 1 || opt->polish < 0 || opt->polish > 4)
+      opt->max_outer < 1 || opt->polish < 0 || opt->polish > 4 || opt->guess_kind < 0 ||
+      opt->guess_kind > 1)
     return MGRHD_E_OPTION;
 
   Variant* var = choose_variant(ng);
@@ -274,6 +296,7 @@ int mgrhd_source_update(double* E_g, double* F_g, const double* rho, double* e_g
   a.kappa = op->kappa_scale;
   a.S = opt->S_g;
   a.guess = opt->guess;
+  a.guess_kind = opt->guess_kind;
   a.iters = opt->iters;
   a.outer = opt->outer;
   a.status = opt->status;

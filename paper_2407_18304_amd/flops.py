@@ -46,9 +46,10 @@ def unit_costs(w=W):
     # one Planck edge: x = hk/T * nu (1), x^2 and x^3 (2), then by branch
     edge_common = 1 + 2
     poly_P = 14 * 2 + 6              # degree-14 Horner in x^2 and the bracket
+    poly_E = 16 * 2 + 6              # degree-16 Horner in x^2 for x/(e^x-1) and the bracket
     edge = {
-        "x<=2": edge_common + poly_P + (10 * 2 + 6),        # polynomial x/(e^x-1)
-        "2<x<=4": edge_common + e + poly_P + (4 + dv),      # x^4 u/(1-u)
+        "x<=2": edge_common + poly_P + poly_E,
+        "2<x<=4": edge_common + poly_P + poly_E,
         "x>4": edge_common + e + 2 + (10 * 6 + 9 * 2) + 1 + (3 + dv),  # 10-term tail
     }
     # group data from its two edges (group_planck)

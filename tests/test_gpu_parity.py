@@ -119,6 +119,22 @@ def test_warm_start_matches_plain_and_falls_back():
         assert e < 1e-13, (k, e)
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_temperature_only_guess_matches_oracle(mode):
+    """Guess kind 1 (E_gas alone; R_g from the group balances) on the GPU and
+    on the oracle with the same rough guess: same counts, same results."""
+    w = W.config1(cells=np.arange(3000))
+    plain, it0, _, st0 = U.run_gpu(w, mode)
+    rough = plain["e_gas"] * (1.0 + 1e-3 * np.cos(np.arange(w.n)))
+    g = U.run_gpu(w, mode, guess=rough, guess_kind=1)
+    o = U.run_oracle(w, mode, guess=rough, guess_kind=1)
+    _compare(w, mode, g, o)
+    ok = (st0 == 0) & (g[3] == 0)
+    assert g[1][ok].mean() < it0[ok].mean()
+    for k, e in U.field_errors(w, g[0], plain, ok).items():
+        assert e < TOL_COUNT_FLIP, (k, e)
+
+
 def test_bad_device_table_is_reported_per_cell():
     w = W.config0(cells=np.arange(100))
     w.edges = w.edges[::-1].copy()          # descending: rejected on the device
@@ -146,8 +162,8 @@ def test_deterministic_and_variant_independent():
     default = mgrhd.get_variant(w.ng)
     try:
         ref = U.run_gpu(w, 1)
-        for lpc, gpl in [(8, 2), (16, 1), (8, 4)]:
-            mgrhd.set_variant(w.ng, lpc, gpl)
+        for lpc, gpl, wps in [(8, 2, 0), (16, 1, 0), (8, 4, 0), (4, 4, 4), (8, 2, 4)]:
+            mgrhd.set_variant(w.ng, lpc, gpl, wps)
             # another lane split changes only the order of the group sums
             _compare(w, 1, U.run_gpu(w, 1), ref)
     finally:

@@ -302,6 +302,34 @@ def test_warm_start_same_result_and_fallback(ora, mode):
         assert np.array_equal(fb[k], plain[k])
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_temperature_only_warm_start(ora, mode):
+    """Guess kind 1 reads only E_gas; each R_g then solves its own group
+    balance (eq. Rnew inverted, F_R,g = 0) at that temperature.  From the
+    converged E_gas of a plain solve, that R_g is the plain solution itself:
+    the pass converges with no Newton step and returns the same state.
+    (PPL-free is left out: its slopes lag the iterate and it may have several
+    fixed points, so plain and warm results need not coincide.)"""
+    w = W.config0(cells=np.arange(300))
+    kw = dict(kappa_scale=w.kappa, alpha_chi=w.alpha_chi, mean_mode=mode, polish=1,
+              max_outer=1, **w.consts())
+    plain, it0, _, st0 = ora.source_update(w.state, w.edges, w.chi_lo, **kw)
+    warm, it1, _, st1 = ora.source_update(w.state, w.edges, w.chi_lo, guess=plain["e_gas"],
+                                          guess_kind=1, **kw)
+    assert ((st1 & ~2) == 0).all() and it0.mean() > 2
+    assert (it1 == 0).all()
+    for k in ("E_g", "e_gas"):
+        assert np.allclose(warm[k], plain[k], rtol=1e-12, atol=1e-300)
+    # a rough temperature still converges to the same root, in fewer steps
+    rough = plain["e_gas"] * (1 + 1e-3)
+    r, it2, _, st2 = ora.source_update(w.state, w.edges, w.chi_lo, guess=rough, guess_kind=1, **kw)
+    assert ((st2 & ~2) == 0).all() and it2.mean() < it0.mean()
+    for k in ("E_g", "e_gas"):
+        assert np.allclose(r[k], plain[k], rtol=1e-11, atol=1e-300)
+    with pytest.raises(ValueError):
+        ora.source_update(w.state, w.edges, w.chi_lo, guess=rough, guess_kind=2, **kw)
+
+
 def test_invalid_cells_untouched_and_bad_arguments(ora):
     w = W.config0(cells=np.arange(4))
     st = {k: v.copy() for k, v in w.state.items()}
