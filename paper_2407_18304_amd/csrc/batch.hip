@@ -60,43 +60,11 @@ __device__ __forceinline__ bool stage_tables_wave(const KArgs& a, Tables<kBatchN
     wave_sync();
     return false;
   }
-  for (int g = lane; g <= ng; g += kWave) {
-    const double nu = a.edges[g];
-    t.nu[g] = nu;
-    bool ok = nu >= 0.0;
-    if (MODE != MGRHD_MEAN_PC) ok = ok && nu > 0.0 && !is_pinf(nu);
-    if (!ok) atomicOr(&t.bad, 1);
-  }
+  for (int g = lane; g <= ng; g += kWave)
+    if (!table_edge<kBatchNGM, MODE>(a, t, g)) atomicOr(&t.bad, 1);
   wave_sync();
-  for (int g = lane; g < ng; g += kWave) {
-    const double lo = t.nu[g], hi = t.nu[g + 1];
-    const double chl = a.chi_lo[g];
-    bool ok = hi > lo && chl > 0.0 && !is_pinf(chl);
-    double L = 0.0, ac = 0.0, mf = 1.0, rac = 1.0, ldn = 0.0, lc = 0.0;
-    if (MODE != MGRHD_MEAN_PC) {
-      L = log(hi / lo);
-      if (a.alpha) {
-        ac = a.alpha[g];
-      } else {
-        const double chh = a.chi_hi[g];
-        ok = ok && chh > 0.0 && !is_pinf(chh);
-        ac = log(chh / chl) / L;
-      }
-      ok = ok && isfinite(ac);
-      mf = mean_ratio(ac, -1.0, L);
-      rac = exp(ac * L);
-      ldn = log(hi - lo);
-      lc = 0.5 * (log(lo) + log(hi));
-    }
-    t.lnr[g] = L;
-    t.achi[g] = ac;
-    t.chit[g] = chl;
-    t.mfix[g] = mf;
-    t.rac[g] = rac;
-    t.lndnu[g] = ldn;
-    t.lnc[g] = lc;
-    if (!ok) atomicOr(&t.bad, 1);
-  }
+  for (int g = lane; g < ng; g += kWave)
+    if (!table_group<kBatchNGM, MODE>(a, t, g)) atomicOr(&t.bad, 1);
   wave_sync();
   return t.bad == 0;
 }
@@ -104,6 +72,8 @@ __device__ __forceinline__ bool stage_tables_wave(const KArgs& a, Tables<kBatchN
 template <int G, int MODE>
 __global__ __launch_bounds__(kBlock, 2) void k_batch(BatchArgs b) {
   __shared__ Tables<kBatchNGM> tabs[kBlock / kWave];
+  __shared__ double lane_lds[LaneStore<G>::kSlots * kBlock];
+  const LaneStore<G> ls{lane_lds + threadIdx.x};
   const int lane = threadIdx.x % kWave;
   Tables<kBatchNGM>& tab = tabs[threadIdx.x / kWave];
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
@@ -158,8 +128,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_batch(BatchArgs b) {
       mine = __shfl(mine, lane - j, kWave);
       if (need) {
         if (mine < hi) {
-          load_cell<G, 0, MODE, kBatchNGM>(a, tab, j, mine, s);
-          if (s.phase == P_EMPTY) finish_cell<G, 0>(a, j, s, false);
+          load_cell<G, 0, MODE, kBatchNGM>(a, tab, j, mine, s, ls);
+          if (s.phase == P_EMPTY) finish_cell<G, 0>(a, j, s, ls, false);
         } else {
           s.phase = P_IDLE;
         }
@@ -170,10 +140,10 @@ __global__ __launch_bounds__(kBlock, 2) void k_batch(BatchArgs b) {
     const double T = ((s.phase == P_FLUX ? s.egas_new : s.egv) - s.ke) / (s.rho * a.cv);
     if (!(T > 0.0) || !isfinite(T)) {
       if (s.phase == P_NEWTON)
-        newton_done<G, 0>(a, j, s, 2);
+        newton_done<G, 0>(a, j, s, ls, 2);
       else {
         s.st |= MGRHD_ST_INVALID;
-        finish_cell<G, 0>(a, j, s, false);
+        finish_cell<G, 0>(a, j, s, ls, false);
       }
       continue;
     }
@@ -181,12 +151,12 @@ __global__ __launch_bounds__(kBlock, 2) void k_batch(BatchArgs b) {
 #pragma unroll
     for (int k = 0; k < G; ++k) Ecur[k] = s.E0[k] + s.R[k];
     const double aT4 = a.a * (T * T) * (T * T);
-    evaluate<G, 0, MODE, kBatchNGM>(tab, a.ng, j, T, aT4, a.hk, s.rho_kappa, Ecur, s.chiK, c);
+    evaluate<G, 0, MODE, kBatchNGM>(tab, a.ng, j, T, aT4, a.hk, s.rho_kappa, Ecur, c);
     if (s.phase == P_FLUX) {
-      if (!flux_step<G, 0, MODE, kBatchNGM>(a, tab, j, s, c)) continue;
+      if (!flux_step<G, 0, MODE, kBatchNGM>(a, tab, j, s, ls, c)) continue;
     }
-    if (s.elim) group_balance<G, MODE, kBatchNGM>(a, tab, j, s, c);
-    newton_step<G, 0, MODE, kBatchNGM>(a, tab, j, s, c);
+    if (s.elim) group_balance<G, MODE, kBatchNGM>(a, tab, j, s, ls, c);
+    newton_step<G, 0, MODE, kBatchNGM>(a, tab, j, s, ls, c);
   }
 }
 

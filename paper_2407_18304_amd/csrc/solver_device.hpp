@@ -54,6 +54,7 @@ struct Tables {
   double achi[NGM];   // opacity powerlaw index (0 in PC)
   double chit[NGM];   // chi_lo table entry (per unit rho * kappa)
   double mfix[NGM];   // PPL-fixed mean ratio chi_0B/chi_0,g- = chi_0E/chi_0,g-
+  double chk[NGM];    // PC / PPL-fixed group mean per unit rho * kappa (chit, or chit * mfix)
   double rac[NGM];    // r_g^alpha_chi
   double lndnu[NGM];  // ln(nu_g+ - nu_g-)
   double lnc[NGM];    // (ln nu_g- + ln nu_g+)/2
@@ -99,51 +100,77 @@ __device__ __forceinline__ double cell_sum(double v, int lpc) {
   return v;
 }
 
+// Table entries of group g (edges already staged in t.nu); false if the
+// group's table is unusable.
+template <int NGM, int MODE>
+__device__ __forceinline__ bool table_group(const KArgs& a, Tables<NGM>& t, int g) {
+  const double lo = t.nu[g], hi = t.nu[g + 1];
+  const double chl = a.chi_lo[g];
+  bool ok = hi > lo && chl > 0.0 && !is_pinf(chl);
+  double L = 0.0, ac = 0.0, mf = 1.0, rac = 1.0, ldn = 0.0, lc = 0.0;
+  if (MODE != MGRHD_MEAN_PC) {
+    L = log(hi / lo);
+    if (a.alpha) {
+      ac = a.alpha[g];
+    } else {
+      const double chh = a.chi_hi[g];
+      ok = ok && chh > 0.0 && !is_pinf(chh);
+      ac = log(chh / chl) / L;  // tabulated opacity: index from the edge values
+    }
+    ok = ok && isfinite(ac);
+    mf = mean_ratio(ac, -1.0, L);
+    rac = exp(ac * L);
+    ldn = log(hi - lo);
+    lc = 0.5 * (log(lo) + log(hi));
+  }
+  t.lnr[g] = L;
+  t.achi[g] = ac;
+  t.chit[g] = chl;
+  t.mfix[g] = mf;
+  t.chk[g] = (MODE == MGRHD_MEAN_PC) ? chl : chl * mf;
+  t.rac[g] = rac;
+  t.lndnu[g] = ldn;
+  t.lnc[g] = lc;
+  return ok;
+}
+
+// Edge g of the table; false if unusable.
+template <int NGM, int MODE>
+__device__ __forceinline__ bool table_edge(const KArgs& a, Tables<NGM>& t, int g) {
+  const double nu = a.edges[g];
+  t.nu[g] = nu;
+  bool ok = nu >= 0.0;
+  if (MODE != MGRHD_MEAN_PC) ok = ok && nu > 0.0 && !is_pinf(nu);
+  return ok;
+}
+
+// Stage the tables in LDS (whole workgroup).
 template <int NGM, int MODE>
 __device__ __forceinline__ bool stage_tables(const KArgs& a, Tables<NGM>& t) {
   if (threadIdx.x == 0) t.bad = 0;
   __syncthreads();
-  const int ng = a.ng;
-  for (int g = threadIdx.x; g <= ng; g += blockDim.x) {
-    const double nu = a.edges[g];
-    t.nu[g] = nu;
-    bool ok = nu >= 0.0;
-    if (MODE != MGRHD_MEAN_PC) ok = ok && nu > 0.0 && !is_pinf(nu);
-    if (!ok) atomicOr(&t.bad, 1);
-  }
+  for (int g = threadIdx.x; g <= a.ng; g += blockDim.x)
+    if (!table_edge<NGM, MODE>(a, t, g)) atomicOr(&t.bad, 1);
   __syncthreads();
-  for (int g = threadIdx.x; g < ng; g += blockDim.x) {
-    const double lo = t.nu[g], hi = t.nu[g + 1];
-    const double chl = a.chi_lo[g];
-    bool ok = hi > lo && chl > 0.0 && !is_pinf(chl);
-    double L = 0.0, ac = 0.0, mf = 1.0, rac = 1.0, ldn = 0.0, lc = 0.0;
-    if (MODE != MGRHD_MEAN_PC) {
-      L = log(hi / lo);
-      if (a.alpha) {
-        ac = a.alpha[g];
-      } else {
-        const double chh = a.chi_hi[g];
-        ok = ok && chh > 0.0 && !is_pinf(chh);
-        ac = log(chh / chl) / L;  // tabulated opacity: index from the edge values
-      }
-      ok = ok && isfinite(ac);
-      mf = mean_ratio(ac, -1.0, L);
-      rac = exp(ac * L);
-      ldn = log(hi - lo);
-      lc = 0.5 * (log(lo) + log(hi));
-    }
-    t.lnr[g] = L;
-    t.achi[g] = ac;
-    t.chit[g] = chl;
-    t.mfix[g] = mf;
-    t.rac[g] = rac;
-    t.lndnu[g] = ldn;
-    t.lnc[g] = lc;
-    if (!ok) atomicOr(&t.bad, 1);
-  }
+  for (int g = threadIdx.x; g < a.ng; g += blockDim.x)
+    if (!table_group<NGM, MODE>(a, t, g)) atomicOr(&t.bad, 1);
   __syncthreads();
   return t.bad == 0;
 }
+
+// Per-lane values held in LDS instead of registers: the fluxes F_k of the
+// lane's groups during the outer iteration (3G) and, in PC and PPL-fixed, the
+// per-cell constants 1/tau_g = 1/(c_hat dt chi_0E,g) and 1/J_gg of eq. matrix
+// (2G).  Slot s of thread t lives at lds[s * kBlock + t]: the 64 lanes of a
+// wave touch 64 consecutive words, free of bank conflicts.
+template <int G>
+struct LaneStore {
+  static constexpr int kSlots = 5 * G;
+  double* base;  // &lds[threadIdx.x]
+  __device__ __forceinline__ double& F(int d, int k) const { return base[(d * G + k) * kBlock]; }
+  __device__ __forceinline__ double& itau(int k) const { return base[(3 * G + k) * kBlock]; }
+  __device__ __forceinline__ double& iJgg(int k) const { return base[(4 * G + k) * kBlock]; }
+};
 
 // Material data of this lane's groups at one temperature.
 template <int G>
@@ -178,11 +205,11 @@ __device__ __forceinline__ void slopes_free(const Tables<NGM>& t, int ng, int j,
 }
 
 // One material evaluation: Planck data, slopes (PPL-free), group means.
-// chiK holds the per-cell constant chi_0E (= chi_0B) of PC and PPL-fixed.
+// In PC and PPL-fixed chi_0E = chi_0B = rho kappa chk_g is fixed per cell.
 template <int G, int LPC, int MODE, int NGM>
 __device__ __forceinline__ void evaluate(const Tables<NGM>& t, int ng, int j, double T, double aT4,
                                          double hk, double rho_kappa, const double* Ecur,
-                                         const double* chiK, Cache<G>& c) {
+                                         Cache<G>& c) {
   const double invT = 1.0 / T;
   const double hkT = hk * invT;
   Edge lo = planck_edge(hkT * t.nu[min(j * G, ng)]);
@@ -198,7 +225,7 @@ __device__ __forceinline__ void evaluate(const Tables<NGM>& t, int ng, int j, do
       const double Dnu = aT4 * (p.ehi - p.elo) * p.scale;
       c.Bt[k] = Bt;
       c.dBdT[k] = (4.0 * Bt - Dnu) * invT;
-      const double ch = chiK[k];
+      const double ch = rho_kappa * t.chk[g];
       if (MODE == MGRHD_MEAN_PC) {
         c.chiF[k] = ch;
         c.emit[k] = ch * (Bt - Dnu * kThird);
@@ -299,13 +326,13 @@ struct CellState {
   bool warm, fell_back, elim;
   double rho, rho_kappa, egas0, etot, ke, egv, egas_new;
   double v[3];
-  double R[G], E0[G], Fk[3][G];      // F_g^(t) and v^(t) stay in global memory
-  double chiK[G], itau[G], iJgg[G];  // PC / PPL-fixed constants
+  double R[G], E0[G];  // F_g^(t) and v^(t) stay in global memory, F_k in LDS
+  double vF[G];        // v_k . F_g,k of the current outer pass
 };
 
 template <int G, int LPC, int MODE, int NGM>
 __device__ __forceinline__ void load_cell(const KArgs& a, const Tables<NGM>& t, int j, int64_t i,
-                          CellState<G>& s) {
+                                          CellState<G>& s, const LaneStore<G>& ls) {
   const int64_t n = a.n;
   const int ng = a.ng;
   s.i = i;
@@ -330,11 +357,9 @@ __device__ __forceinline__ void load_cell(const KArgs& a, const Tables<NGM>& t, 
     const int g = j * G + k;
     s.R[k] = 0.0;
     s.E0[k] = 0.0;
-    s.chiK[k] = 1.0;
-    s.itau[k] = 0.0;
-    s.iJgg[k] = -1.0;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) s.Fk[d][k] = 0.0;
+    s.vF[k] = 0.0;
+    double f[3] = {0.0, 0.0, 0.0};
+    double it = 0.0, ij = -1.0;
     if (g < ng) {
       const double e = a.E[(int64_t)g * n + i];
       const double sg = a.S ? a.S[(int64_t)g * n + i] : 0.0;
@@ -343,17 +368,20 @@ __device__ __forceinline__ void load_cell(const KArgs& a, const Tables<NGM>& t, 
       sumE += e + sg;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        const double f = a.F[((int64_t)d * ng + g) * n + i];
-        ok = ok && isfinite(f);
-        s.Fk[d][k] = f;
+        f[d] = a.F[((int64_t)d * ng + g) * n + i];
+        ok = ok && isfinite(f[d]);
       }
+      s.vF[k] = s.v[0] * f[0] + s.v[1] * f[1] + s.v[2] * f[2];
       if (MODE != MGRHD_MEAN_PPL_FREE) {
-        const double chl = s.rho_kappa * t.chit[g];
-        const double ch = (MODE == MGRHD_MEAN_PC) ? chl : chl * t.mfix[g];
-        s.chiK[k] = ch;
-        s.itau[k] = 1.0 / (cdt * ch);
-        s.iJgg[k] = 1.0 / (-s.itau[k] - 1.0);
+        it = 1.0 / (cdt * s.rho_kappa * t.chk[g]);
+        ij = 1.0 / (-it - 1.0);
       }
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) ls.F(d, k) = f[d];
+    if (MODE != MGRHD_MEAN_PPL_FREE) {
+      ls.itau(k) = it;
+      ls.iJgg(k) = ij;
     }
   }
   sumE = cell_sum<LPC>(sumE, s.lpc);
@@ -386,7 +414,8 @@ __device__ __forceinline__ void load_cell(const KArgs& a, const Tables<NGM>& t, 
 }
 
 template <int G, int LPC>
-__device__ __forceinline__ void finish_cell(const KArgs& a, int j, CellState<G>& s, bool store) {
+__device__ __forceinline__ void finish_cell(const KArgs& a, int j, CellState<G>& s,
+                                            const LaneStore<G>& ls, bool store) {
   const int64_t n = a.n, i = s.i;
   const int ng = a.ng;
   if (store) {
@@ -398,7 +427,7 @@ __device__ __forceinline__ void finish_cell(const KArgs& a, int j, CellState<G>&
       if (!isfinite(s.E0[k] + s.R[k])) bad = 1.0;
 #pragma unroll
       for (int d = 0; d < 3; ++d)
-        if (!isfinite(s.Fk[d][k])) bad = 1.0;
+        if (!isfinite(ls.F(d, k))) bad = 1.0;
     }
     bad = cell_sum<LPC>(bad, s.lpc);
     if (bad != 0.0) {
@@ -410,7 +439,7 @@ __device__ __forceinline__ void finish_cell(const KArgs& a, int j, CellState<G>&
         if (g >= ng) continue;
         a.E[(int64_t)g * n + i] = s.E0[k] + s.R[k];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) a.F[((int64_t)d * ng + g) * n + i] = s.Fk[d][k];
+        for (int d = 0; d < 3; ++d) a.F[((int64_t)d * ng + g) * n + i] = ls.F(d, k);
       }
       if (j == 0) {
         a.egas[i] = s.egas_new;
@@ -430,7 +459,8 @@ __device__ __forceinline__ void finish_cell(const KArgs& a, int j, CellState<G>&
 
 // End of an inner pass with result rc (0 converged, 1 max_newton, 2 T <= 0).
 template <int G, int LPC>
-__device__ __forceinline__ void newton_done(const KArgs& a, int j, CellState<G>& s, int rc) {
+__device__ __forceinline__ void newton_done(const KArgs& a, int j, CellState<G>& s,
+                                            const LaneStore<G>& ls, int rc) {
   if (s.k_out == 0 && s.warm && rc != 0 && !s.fell_back) {
     // warm start failed: plain Newton from the old state (status bit 4)
     s.st |= MGRHD_ST_FALLBACK;
@@ -445,7 +475,7 @@ __device__ __forceinline__ void newton_done(const KArgs& a, int j, CellState<G>&
   if (rc == 1) s.st |= MGRHD_ST_NEWTON_MAXIT;
   if (rc == 2) {
     s.st |= MGRHD_ST_INVALID;
-    finish_cell<G, LPC>(a, j, s, false);
+    finish_cell<G, LPC>(a, j, s, ls, false);
     return;
   }
   // conservative energy update (Sec. 3)
@@ -461,7 +491,8 @@ __device__ __forceinline__ void newton_done(const KArgs& a, int j, CellState<G>&
 // E_g and F_R,g = 0 (eq. FGFR) are linear in R_g alone; take that R_g.
 template <int G, int MODE, int NGM>
 __device__ __forceinline__ void group_balance(const KArgs& a, const Tables<NGM>& t, int j,
-                                              CellState<G>& s, const Cache<G>& c) {
+                                              CellState<G>& s, const LaneStore<G>& ls,
+                                              const Cache<G>& c) {
   const int ng = a.ng;
   const double cdt = a.chat * a.dt;
   const double ic2 = 1.0 / (a.c * a.c);
@@ -469,13 +500,14 @@ __device__ __forceinline__ void group_balance(const KArgs& a, const Tables<NGM>&
   for (int k = 0; k < G; ++k) {
     const int g = j * G + k;
     if (g >= ng) continue;
-    double ratio = 1.0, itau = s.itau[k];
+    double ratio = 1.0, itau;
     if (MODE == MGRHD_MEAN_PPL_FREE) {
       ratio = c.chiB[k] / c.chiE[k];
       itau = 1.0 / (cdt * c.chiE[k]);
+    } else {
+      itau = ls.itau(k);
     }
-    const double vF = s.v[0] * s.Fk[0][k] + s.v[1] * s.Fk[1][k] + s.v[2] * s.Fk[2][k];
-    const double W = cdt * (1.0 + t.achi[g]) * c.chiF[k] * vF * ic2;
+    const double W = cdt * (1.0 + t.achi[g]) * c.chiF[k] * s.vF[k] * ic2;
     s.R[k] = (ratio * c.Bt[k] + W * itau - s.E0[k]) / (1.0 + itau);
   }
   s.elim = false;
@@ -484,8 +516,9 @@ __device__ __forceinline__ void group_balance(const KArgs& a, const Tables<NGM>&
 // Newton consumer: residual of eq. FGFR at the cached material state, the
 // elimination of eq. matrix, and the step.
 template <int G, int LPC, int MODE, int NGM>
-__device__ __forceinline__ void newton_step(const KArgs& a, const Tables<NGM>& t, int j, CellState<G>& s,
-                            const Cache<G>& c) {
+__device__ __forceinline__ void newton_step(const KArgs& a, const Tables<NGM>& t, int j,
+                                            CellState<G>& s, const LaneStore<G>& ls,
+                                            const Cache<G>& c) {
   const int ng = a.ng;
   const double cc = a.c / a.chat;
   const double cdt = a.chat * a.dt;
@@ -499,14 +532,16 @@ __device__ __forceinline__ void newton_step(const KArgs& a, const Tables<NGM>& t
     bg[k] = 0.0;
     const int g = j * G + k;
     if (g >= ng) continue;
-    double ratio = 1.0, itau = s.itau[k], iJgg = s.iJgg[k];
+    double ratio = 1.0, itau, iJgg;
     if (MODE == MGRHD_MEAN_PPL_FREE) {
       ratio = c.chiB[k] / c.chiE[k];
       itau = 1.0 / (cdt * c.chiE[k]);
       iJgg = 1.0 / (-itau - 1.0);
+    } else {
+      itau = ls.itau(k);
+      iJgg = ls.iJgg(k);
     }
-    const double vF = s.v[0] * s.Fk[0][k] + s.v[1] * s.Fk[1][k] + s.v[2] * s.Fk[2][k];
-    const double W = cdt * (1.0 + t.achi[g]) * c.chiF[k] * vF * ic2;  // eq. Rnew
+    const double W = cdt * (1.0 + t.achi[g]) * c.chiF[k] * s.vF[k] * ic2;  // eq. Rnew
     const double Eg = ratio * c.Bt[k] + (W - s.R[k]) * itau;  // eq. Rnew solved for E_g
     const double FR = Eg - s.E0[k] - s.R[k];
     const double Jg0 = ratio * c.dBdT[k] * ircv;               // eq. linear
@@ -525,11 +560,11 @@ __device__ __forceinline__ void newton_step(const KArgs& a, const Tables<NGM>& t
   const bool conv = fabs(FG) / s.etot < a.eps && cc * sumAbs / s.etot < a.eps;
   if (s.polish_left < 0 && conv) s.polish_left = a.polish;
   if (s.polish_left == 0) {
-    newton_done<G, LPC>(a, j, s, 0);
+    newton_done<G, LPC>(a, j, s, ls, 0);
     return;
   }
   if (s.polish_left < 0 && s.steps >= a.max_newton) {
-    newton_done<G, LPC>(a, j, s, 1);
+    newton_done<G, LPC>(a, j, s, ls, 1);
     return;
   }
   // eq. matrix eliminated: dx0, then dx_g = -a_g - b_g dx0
@@ -537,7 +572,7 @@ __device__ __forceinline__ void newton_step(const KArgs& a, const Tables<NGM>& t
   double lam = 1.0;
   for (int h = 0; h < 30 && !(s.egv + lam * dx0 - s.ke > 0.0); ++h) lam *= 0.5;
   if (!(s.egv + lam * dx0 - s.ke > 0.0)) {
-    newton_done<G, LPC>(a, j, s, 2);
+    newton_done<G, LPC>(a, j, s, ls, 2);
     return;
   }
   s.egv += lam * dx0;
@@ -547,37 +582,35 @@ __device__ __forceinline__ void newton_step(const KArgs& a, const Tables<NGM>& t
     --s.polish_left;
   else
     ++s.steps;
-  if (s.polish_left == 0) newton_done<G, LPC>(a, j, s, 0);
+  if (s.polish_left == 0) newton_done<G, LPC>(a, j, s, ls, 0);
 }
 
 // Outer-stage consumer: flux update eq. numF1 with the outdated velocity,
 // momentum update, outer test.  Returns true when the next inner pass starts
 // (at the same temperature, so the caller reuses this evaluation).
 template <int G, int LPC, int MODE, int NGM>
-__device__ __forceinline__ bool flux_step(const KArgs& a, const Tables<NGM>& t, int j, CellState<G>& s,
-                          const Cache<G>& c) {
+__device__ __forceinline__ bool flux_step(const KArgs& a, const Tables<NGM>& t, int j,
+                                          CellState<G>& s, const LaneStore<G>& ls,
+                                          const Cache<G>& c) {
   const int ng = a.ng;
   const int64_t n = a.n, i = s.i;
   const double cdt = a.chat * a.dt;
   double dmom[3] = {0.0, 0.0, 0.0};
-  double Fn[3][G];
 #pragma unroll
   for (int k = 0; k < G; ++k) {
-#pragma unroll
-    for (int d = 0; d < 3; ++d) Fn[d][k] = 0.0;
     const int g = j * G + k;
     if (g >= ng) continue;
     const double Enew = s.E0[k] + s.R[k];
-    const double chE = (MODE == MGRHD_MEAN_PPL_FREE) ? c.chiE[k] : s.chiK[k];
+    const double chE = (MODE == MGRHD_MEAN_PPL_FREE) ? c.chiE[k] : s.rho_kappa * t.chk[g];
     double Pv[3];
-    pressure_dot_v(a.closure, a.c, Enew, s.Fk[0][k], s.Fk[1][k], s.Fk[2][k], s.v, Pv);
+    pressure_dot_v(a.closure, a.c, Enew, ls.F(0, k), ls.F(1, k), ls.F(2, k), s.v, Pv);
     const double iden = 1.0 / (1.0 + cdt * c.chiF[k]);
     const double q = (1.0 + t.achi[g]) * chE;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const double f0 = a.F[((int64_t)d * ng + g) * n + i];  // F_g^(t)
       const double f = (f0 + cdt * (s.v[d] * c.emit[k] + q * Pv[d])) * iden;
-      Fn[d][k] = f;
+      ls.F(d, k) = f;  // F_k+1 replaces F_k (v_k . F_k stays in s.vF)
       dmom[d] += f - f0;
     }
   }
@@ -594,9 +627,9 @@ __device__ __forceinline__ bool flux_step(const KArgs& a, const Tables<NGM>& t, 
   for (int k = 0; k < G; ++k) {
     const int g = j * G + k;
     if (g >= ng) continue;
-    const double vf_new = vn[0] * Fn[0][k] + vn[1] * Fn[1][k] + vn[2] * Fn[2][k];
-    const double vf_old = s.v[0] * s.Fk[0][k] + s.v[1] * s.Fk[1][k] + s.v[2] * s.Fk[2][k];
-    dW += fabs((1.0 + t.achi[g]) * c.chiF[k] * (vf_new - vf_old));
+    const double vf_new = vn[0] * ls.F(0, k) + vn[1] * ls.F(1, k) + vn[2] * ls.F(2, k);
+    dW += fabs((1.0 + t.achi[g]) * c.chiF[k] * (vf_new - s.vF[k]));
+    s.vF[k] = vf_new;
   }
   dW = cell_sum<LPC>(dW, s.lpc) * (cdt / (a.c * a.c));
   const double ke_new = 0.5 * s.rho * (vn[0] * vn[0] + vn[1] * vn[1] + vn[2] * vn[2]);
@@ -604,17 +637,13 @@ __device__ __forceinline__ bool flux_step(const KArgs& a, const Tables<NGM>& t, 
   s.ke = ke_new;
 #pragma unroll
   for (int d = 0; d < 3; ++d) s.v[d] = vn[d];
-#pragma unroll
-  for (int k = 0; k < G; ++k)
-#pragma unroll
-    for (int d = 0; d < 3; ++d) s.Fk[d][k] = Fn[d][k];
   if (dW < a.eps_out * s.etot) {
-    finish_cell<G, LPC>(a, j, s, true);
+    finish_cell<G, LPC>(a, j, s, ls, true);
     return false;
   }
   if (s.k_out + 1 >= a.max_outer) {
     s.st |= MGRHD_ST_OUTER_MAXIT;
-    finish_cell<G, LPC>(a, j, s, true);
+    finish_cell<G, LPC>(a, j, s, ls, true);
     return false;
   }
   ++s.k_out;

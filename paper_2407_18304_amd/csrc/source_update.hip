@@ -39,6 +39,8 @@ __global__ __launch_bounds__(kBlock, WPE) void k_source_update(KArgs a) {
   constexpr int NGM = G * LPC;
   constexpr int kGroupsPerWave = kWave / LPC;
   __shared__ Tables<NGM> tab;
+  __shared__ double lane_lds[LaneStore<G>::kSlots * kBlock];
+  const LaneStore<G> ls{lane_lds + threadIdx.x};
   const bool table_ok = stage_tables<NGM, MODE>(a, tab);
 
   const int lane = threadIdx.x % kWave;
@@ -76,8 +78,8 @@ __global__ __launch_bounds__(kBlock, WPE) void k_source_update(KArgs a) {
       mine = __shfl(mine, lane - j, kWave);
       if (need) {
         if (mine < hi) {
-          load_cell<G, LPC, MODE, NGM>(a, tab, j, mine, s);
-          if (s.phase == P_EMPTY) finish_cell<G, LPC>(a, j, s, false);
+          load_cell<G, LPC, MODE, NGM>(a, tab, j, mine, s, ls);
+          if (s.phase == P_EMPTY) finish_cell<G, LPC>(a, j, s, ls, false);
         } else {
           s.phase = P_IDLE;
         }
@@ -93,10 +95,10 @@ __global__ __launch_bounds__(kBlock, WPE) void k_source_update(KArgs a) {
     const double T = ((s.phase == P_FLUX ? s.egas_new : s.egv) - s.ke) / (s.rho * a.cv);
     if (!(T > 0.0) || !isfinite(T)) {
       if (s.phase == P_NEWTON)
-        newton_done<G, LPC>(a, j, s, 2);
+        newton_done<G, LPC>(a, j, s, ls, 2);
       else {
         s.st |= MGRHD_ST_INVALID;
-        finish_cell<G, LPC>(a, j, s, false);
+        finish_cell<G, LPC>(a, j, s, ls, false);
       }
       continue;
     }
@@ -104,14 +106,14 @@ __global__ __launch_bounds__(kBlock, WPE) void k_source_update(KArgs a) {
 #pragma unroll
     for (int k = 0; k < G; ++k) Ecur[k] = s.E0[k] + s.R[k];
     const double aT4 = a.a * (T * T) * (T * T);
-    evaluate<G, LPC, MODE, NGM>(tab, a.ng, j, T, aT4, a.hk, s.rho_kappa, Ecur, s.chiK, c);
+    evaluate<G, LPC, MODE, NGM>(tab, a.ng, j, T, aT4, a.hk, s.rho_kappa, Ecur, c);
 
     if (s.phase == P_FLUX) {
-      if (!flux_step<G, LPC, MODE, NGM>(a, tab, j, s, c)) continue;
+      if (!flux_step<G, LPC, MODE, NGM>(a, tab, j, s, ls, c)) continue;
       // the next inner pass starts at this temperature: fall through
     }
-    if (s.elim) group_balance<G, MODE, NGM>(a, tab, j, s, c);
-    newton_step<G, LPC, MODE, NGM>(a, tab, j, s, c);
+    if (s.elim) group_balance<G, MODE, NGM>(a, tab, j, s, ls, c);
+    newton_step<G, LPC, MODE, NGM>(a, tab, j, s, ls, c);
   }
 }
 
