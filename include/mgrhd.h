@@ -36,6 +36,7 @@
 #ifndef MGRHD_H
 #define MGRHD_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -156,6 +157,23 @@ int mgrhd_set_variant(int32_t n_groups, int32_t lanes_per_cell, int32_t groups_p
 int32_t mgrhd_variant_count(void);
 int mgrhd_variant_info(int32_t k, int32_t* lanes_per_cell, int32_t* groups_per_lane,
                        int32_t* waves_per_simd);
+
+/* ---- Two-stage IMEX step of the source terms (Sec. 2.3, eqs. imex1, imex2) ----
+ * With no transport term, one step of the paper's IMEX integrator is
+ *   U^(n+1/2) = U^(n) + dt S(U^(n+1/2))            (source update, theta dt = dt)
+ *   U^(n+1)   = (U^(n) + U^(n+1/2))/2 + (dt/2) S(U^(n+1))   (theta dt = dt/2).
+ * mgrhd_imex_step performs both stages in place on the state of
+ * mgrhd_source_update (same arguments and layout), keeping U^(n) in the
+ * caller's DEVICE workspace `work` of at least mgrhd_imex_workspace_bytes()
+ * bytes (8 n (4 N_g + 4)); nothing is allocated.  opt->iters/outer/status
+ * report the second stage.  Returns as mgrhd_source_update; MGRHD_E_SIZE if
+ * the workspace is too small. */
+size_t mgrhd_imex_workspace_bytes(int64_t n_cells, int32_t n_groups);
+int mgrhd_imex_step(double* E_g, double* F_g, const double* rho, double* e_gas, double* v,
+                    int64_t n_cells, const double* group_edges,
+                    const mgrhd_opacity_params* opacity, double dt, double c_hat,
+                    mgrhd_stream_t stream, const mgrhd_options* opt, void* work,
+                    size_t work_bytes);
 
 /* ---- Batched AMR-like patches: one persistent launch over many patches ----
  * Each patch holds its own SoA block (same layout as mgrhd_source_update,

@@ -25,7 +25,7 @@ HIPCC_FLAGS = [
 ]
 
 LIBS = {
-    "libmgrhd.so": ["source_update.hip", "batch.hip", "mlp.hip"],
+    "libmgrhd.so": ["source_update.hip", "batch.hip", "mlp.hip", "imex.hip"],
     "libmgrhd_synth.so": ["synth.hip"],
 }
 

@@ -56,26 +56,28 @@ def unit_costs(w=W):
     group = {"both<=4": 1, "straddle": 4, "wien": 3 + dv}
     # per group and evaluation, after the Planck data: B~, Delta(nu B~), dB/dT (8)
     ev_group = {
-        PC: 8 + 3,                                            # emit
-        FIXED: 8 + 4 + 4 + 3 + dv + 5,                        # dchib, chi_F num/den, emit
+        PC: 1 + 8 + 3,                                        # chi (1), emit
+        FIXED: 1 + 8 + 4 + 4 + 3 + dv + 5,                    # chi, dchib, chi_F num/den, emit
         # logs of the two slope fits (B and E), two slope pairs, two group means
         # (two expm1-brackets, a division and a rescaling exp each), chi_F, emit
         FREE: 8 + 1 + (2 * lg + 3) + 2 * (2 * (2 + dv)) +
               2 * (1 + 1 + 2 * (2 + m1 + dv) + 3 + dv + e) + 3 + 6 + 3 + dv + 5,
     }
     ev_cell = 19 + 3 + dv + 1          # T, a T^4, 1/T, hk/T
-    # Newton step per group: v.F (5), W (5), E_g (3), F_R (2), J_g0 (1), a_g b_g (2),
-    # four sums (4), update of R_g (4); PPL-free adds chi_B/chi_E, 1/tau, 1/J_gg
-    nt_group = {PC: 26, FIXED: 26, FREE: 26 + 1 + 3 * dv + 3}
+    # Newton step per group: W (5, with v.F cached per pass), E_g (3), F_R (2),
+    # J_g0 (1), a_g b_g (2), four sums (4), update of R_g (4); PPL-free adds
+    # chi_B/chi_E, 1/tau, 1/J_gg
+    nt_group = {PC: 21, FIXED: 21, FREE: 21 + 1 + 3 * dv + 3}
     nt_cell = 2 * (1 + dv) + 2 + (dv + 1) + (dv + 2) + (4 + dv) + 5   # 1/c^2, 1/(rho c_v),
     #                                      F_G, two stop tests, dx_0, the step
     # flux update per group: E_new (1), M1 closure P.v (|F|: 5+sqrt, f: 1+div, chi:
     # 8+sqrt+div, 1/|F|: div, n: 3, n.v: 5, p q: 5, P.v: 15), 1/(1+cdt chi_F)
-    # (2+div), (1+a)chi_E (2), three components (3 x 8), dW terms (15)
-    fx_group = 1 + (42 + 2 * sq + 3 * dv) + (2 + dv) + 2 + 24 + 15
+    # (2+div), chi_E and (1+a)chi_E (3), three components (3 x 8), the new v.F (5)
+    # and the dW term (5)
+    fx_group = 1 + (42 + 2 * sq + 3 * dv) + (2 + dv) + 3 + 24 + 10
     fx_cell = 2 * (1 + dv) + 12 + (2 + dv) + 7 + 2
-    # cell load: per group E0 (1), sum (1), chi (2), 1/tau and 1/J_gg (2 + 2 div)
-    ld_group = {PC: 5 + 2 * dv, FIXED: 6 + 2 * dv, FREE: 2}
+    # cell load: per group E0 (1), sum (1), v.F (5), 1/tau and 1/J_gg (3 + 2 div)
+    ld_group = {PC: 10 + 2 * dv, FIXED: 10 + 2 * dv, FREE: 7}
     ld_cell = 2 + 7 + 2 + dv
     return dict(edge=edge, group=group, ev_group=ev_group, ev_cell=ev_cell,
                 nt_group=nt_group, nt_cell=nt_cell, fx_group=fx_group, fx_cell=fx_cell,

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(PKG, "libmgrhd.so")
 
 MEAN_PC, MEAN_PPL_FIXED, MEAN_PPL_FREE = 0, 1, 2
 CLOSURE_M1, CLOSURE_EDDINGTON = 0, 1
+E_NULL, E_SIZE, E_MODE, E_TABLE, E_SCALAR, E_OPTION, E_DEVICE = -1, -2, -3, -4, -5, -6, -7
 ST_OK, ST_NEWTON_MAXIT, ST_OUTER_MAXIT, ST_FALLBACK, ST_INVALID, ST_NONFINITE, ST_BAD_TABLE = (
     0, 1, 2, 4, 8, 16, 32)
 MAX_GROUPS = 256
@@ -51,7 +52,8 @@ _lib = None
 
 # exported symbols of include/mgrhd.h
 SYMBOLS = ["mgrhd_source_update", "mgrhd_default_options", "mgrhd_get_variant",
-           "mgrhd_set_variant", "mgrhd_variant_count", "mgrhd_variant_info", "mgrhd_version"]
+           "mgrhd_set_variant", "mgrhd_variant_count", "mgrhd_variant_info",
+           "mgrhd_imex_workspace_bytes", "mgrhd_imex_step", "mgrhd_version"]
 
 
 def lib():
@@ -77,6 +79,11 @@ def lib():
         L.mgrhd_variant_count.argtypes = []
         L.mgrhd_variant_info.restype = C.c_int
         L.mgrhd_variant_info.argtypes = [C.c_int32] + [C.POINTER(C.c_int32)] * 3
+        L.mgrhd_imex_workspace_bytes.restype = C.c_size_t
+        L.mgrhd_imex_workspace_bytes.argtypes = [C.c_int64, C.c_int32]
+        L.mgrhd_imex_step.restype = C.c_int
+        L.mgrhd_imex_step.argtypes = (L.mgrhd_source_update.argtypes +
+                                      [C.c_void_p, C.c_size_t])
         L.mgrhd_version.restype = C.c_char_p
         L.mgrhd_version.argtypes = []
         _lib = L
@@ -112,6 +119,10 @@ def get_variant(n_groups: int, mean_mode: int = MEAN_PPL_FIXED):
     return lpc.value, gpl.value, wps.value
 
 
+def imex_workspace_bytes(n_cells: int, n_groups: int) -> int:
+    return int(lib().mgrhd_imex_workspace_bytes(n_cells, n_groups))
+
+
 def variants():
     """Compiled variants: list of (lanes per cell, groups per lane, waves per SIMD)."""
     out = []
@@ -133,9 +144,12 @@ def source_update(E_g, F_g, rho, e_gas, v, group_edges, chi_lo, *, dt, c_hat,
                   mean_mode=MEAN_PPL_FIXED, alpha_chi=None, chi_hi=None, kappa_scale=None,
                   c=1.0, a_rad=1.0, h_over_k=1.0, c_v=1.5, eps_newton=1e-11, eps_outer=1e-13,
                   max_newton=100, max_outer=10, closure=CLOSURE_M1, polish=0, S_g=None,
-                  guess=None, guess_kind=0, iters=None, outer=None, status=None, stream=None):
+                  guess=None, guess_kind=0, iters=None, outer=None, status=None, stream=None,
+                  imex_work=None):
     """In-place source update of the device state (see include/mgrhd.h).
-    guess_kind 0: guess is [N_g+1, n] (E_gas, R_g); 1: guess is [n] (E_gas)."""
+    guess_kind 0: guess is [N_g+1, n] (E_gas, R_g); 1: guess is [n] (E_gas).
+    imex_work: a device tensor of at least imex_workspace_bytes(n, N_g) bytes
+    turns the call into one two-stage IMEX step (mgrhd_imex_step)."""
     ng, n = E_g.shape
     o = default_options()
     o.c, o.a_rad, o.h_over_k, o.c_v = c, a_rad, h_over_k, c_v
@@ -153,11 +167,18 @@ def source_update(E_g, F_g, rho, e_gas, v, group_edges, chi_lo, *, dt, c_hat,
                        _ptr(kappa_scale, (n,), name="kappa_scale"))
     if stream is None:
         stream = torch.cuda.current_stream(E_g.device).cuda_stream
-    rc = lib().mgrhd_source_update(
-        _ptr(E_g, (ng, n), name="E_g"), _ptr(F_g, (3, ng, n), name="F_g"),
-        _ptr(rho, (n,), name="rho"), _ptr(e_gas, (n,), name="e_gas"), _ptr(v, (3, n), name="v"),
-        n, _ptr(group_edges, (ng + 1,), name="group_edges"), C.byref(op), float(dt),
-        float(c_hat), stream, C.byref(o))
+    args = (_ptr(E_g, (ng, n), name="E_g"), _ptr(F_g, (3, ng, n), name="F_g"),
+            _ptr(rho, (n,), name="rho"), _ptr(e_gas, (n,), name="e_gas"),
+            _ptr(v, (3, n), name="v"), n, _ptr(group_edges, (ng + 1,), name="group_edges"),
+            C.byref(op), float(dt), float(c_hat), stream, C.byref(o))
+    if imex_work is None:
+        rc = lib().mgrhd_source_update(*args)
+    else:
+        if not (isinstance(imex_work, torch.Tensor) and imex_work.is_cuda and
+                imex_work.is_contiguous()):
+            raise TypeError("imex_work must be a contiguous device tensor")
+        rc = lib().mgrhd_imex_step(*args, imex_work.data_ptr(),
+                                   imex_work.numel() * imex_work.element_size())
     if rc != 0:
         raise MgrhdError(rc)
 

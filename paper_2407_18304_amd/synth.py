@@ -132,14 +132,10 @@ class DevicePatch:
 def device_patches(layouts, dev="cuda", stream=None):
     """Allocate and fill every patch of ``layouts`` in HBM (state as config2,
     units of the patch family); cell numbers are the layouts' global ones."""
-    sp = W.SPECS["config2"]
     u = W.UNITS["patches"]
     dt = 1.0 / u["c"]
-    gl = torch.from_numpy(np.concatenate([W._GL_X, W._GL_W])).to(dev)
     f64 = dict(dtype=torch.float64, device=dev)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
-    if stream is None:
-        stream = torch.cuda.current_stream(torch.device(dev)).cuda_stream
     out = []
     for L in layouts:
         n, ng = L.n, L.ng
@@ -148,18 +144,35 @@ def device_patches(layouts, dev="cuda", stream=None):
               "v": torch.empty((3, n), **f64)}
         kap, T = torch.empty(n, **f64), torch.empty(n, **f64)
         tabs = {"edges": t(L.edges), "chi_lo": t(L.chi_lo), "alpha": t(L.alpha_chi)}
+        out.append(DevicePatch(L, st, kap, T, tabs, dt, u["c"]))
+    fill_patches(out, stream)
+    return out
+
+
+def fill_patches(dps, stream=None):
+    """(Re)generate the state of every device patch in place."""
+    if not dps:
+        return
+    sp = W.SPECS["config2"]
+    u = W.UNITS["patches"]
+    dev = dps[0].kappa.device
+    gl = torch.from_numpy(np.concatenate([W._GL_X, W._GL_W])).to(dev)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev).cuda_stream
+    for dp in dps:
+        L, st = dp.layout, dp.state
         rc = lib().mgrhd_synth_state(
             st["E_g"].data_ptr(), st["F_g"].data_ptr(), st["rho"].data_ptr(),
-            st["e_gas"].data_ptr(), st["v"].data_ptr(), kap.data_ptr(), T.data_ptr(),
-            tabs["edges"].data_ptr(), gl.data_ptr(), n, L.cell0,
-            np.uint64(W.PATCH_SPEC["seed"]).item(), ng, len(W._GL_X), sp["t_kind"], sp["t_p"][0],
-            sp["t_p"][1], sp["k_kind"], sp["k_p"][0], sp["k_p"][1], 1.0 / (dt * u["c"]),
-            W.TRAD_RANGE[0], W.TRAD_RANGE[1], sp["vmax"], u["c"], u["a_rad"], 1.5, stream)
+            st["e_gas"].data_ptr(), st["v"].data_ptr(), dp.kappa.data_ptr(), dp.T.data_ptr(),
+            dp.tables["edges"].data_ptr(), gl.data_ptr(), L.n, L.cell0,
+            np.uint64(W.PATCH_SPEC["seed"]).item(), L.ng, len(W._GL_X), sp["t_kind"],
+            sp["t_p"][0], sp["t_p"][1], sp["k_kind"], sp["k_p"][0], sp["k_p"][1],
+            1.0 / (dp.dt * u["c"]), W.TRAD_RANGE[0], W.TRAD_RANGE[1], sp["vmax"], u["c"],
+            u["a_rad"], 1.5, stream)
         if rc != 0:
             raise RuntimeError(f"mgrhd_synth_state failed ({rc})")
-        out.append(DevicePatch(L, st, kap, T, tabs, dt, u["c"]))
     torch.cuda.synchronize()
-    return out
+    del gl
 
 
 def patch_to_host(dp: DevicePatch, idx=None) -> W.Workload:

@@ -1,0 +1,78 @@
+"""The C ABI without a GPU: the built library loads, exports every function
+include/mgrhd.h declares, and its host-only entry points (defaults, version,
+variant table, workspace size, host-side argument checks that return before
+any device call) behave as documented."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2407_18304_amd import mgrhd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mgrhd.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mgrhd_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(mgrhd.LIB_PATH):
+        pytest.skip("libmgrhd.so is not built")
+    return mgrhd.lib()
+
+
+def test_every_declared_function_is_exported(lib):
+    names = declared_functions()
+    assert len(names) > 25
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_symbols_are_declared():
+    declared = set(declared_functions())
+    assert set(mgrhd.SYMBOLS) <= declared
+
+
+def test_defaults_version_and_variants(lib):
+    o = mgrhd.default_options()
+    assert (o.c, o.a_rad, o.h_over_k, o.c_v) == (1.0, 1.0, 1.0, 1.5)
+    assert (o.eps_newton, o.eps_outer, o.max_newton, o.max_outer) == (1e-11, 1e-13, 100, 10)
+    assert o.polish == 0 and o.guess_kind == 0 and not o.guess and not o.S_g
+    assert b"gfx950" in lib.mgrhd_version()
+    vs = mgrhd.variants()
+    assert (16, 4, 2) in vs and (8, 2, 3) in vs and (64, 1, 4) in vs
+    for ng in (1, 4, 16, 64, 100, 256):
+        lpc, g, w = mgrhd.get_variant(ng)
+        assert lpc * g >= ng and (lpc, g, w) in vs
+    with pytest.raises(mgrhd.MgrhdError):
+        mgrhd.set_variant(64, 4, 4)          # 16 lanes-groups < 64 groups
+    with pytest.raises(mgrhd.MgrhdError):
+        mgrhd.set_variant(16, 3, 4)          # not compiled
+    assert lib.mgrhd_get_variant(0, 1, None, None, None) == mgrhd.E_SIZE
+
+
+def test_imex_workspace_size(lib):
+    assert mgrhd.imex_workspace_bytes(1000, 16) == 8 * 1000 * (4 * 16 + 4)
+    assert mgrhd.imex_workspace_bytes(-1, 16) == 0
+
+
+def test_host_argument_errors_need_no_device(lib):
+    # rejected before anything touches the device
+    o = mgrhd.default_options()
+    assert lib.mgrhd_source_update(None, None, None, None, None, 10, None, None, 1.0, 1.0,
+                                   None, C.byref(o)) == mgrhd.E_NULL
+    op = mgrhd.OpacityParams(0, 1, None, None, None, None)
+    assert lib.mgrhd_source_update(None, None, None, None, None, 10, None, C.byref(op), 1.0,
+                                   1.0, None, C.byref(o)) == mgrhd.E_SIZE
+    op = mgrhd.OpacityParams(4, 7, None, None, None, None)
+    assert lib.mgrhd_source_update(None, None, None, None, None, 10, None, C.byref(op), 1.0,
+                                   1.0, None, C.byref(o)) == mgrhd.E_MODE
+    op = mgrhd.OpacityParams(4, 1, None, None, None, None)
+    assert lib.mgrhd_imex_step(None, None, None, None, None, 10, None, C.byref(op), 1.0, 1.0,
+                               None, C.byref(o), None, 0) == mgrhd.E_NULL
