@@ -137,7 +137,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_batch(BatchArgs b) {
     }
     if (s.phase != P_NEWTON && s.phase != P_FLUX) continue;
 
-    const double T = ((s.phase == P_FLUX ? s.egas_new : s.egv) - s.ke) / (s.rho * a.cv);
+    const double T = ((s.phase == P_FLUX ? s.egas_new : s.egv) - s.ke) * s.ircv;
     if (!(T > 0.0) || !isfinite(T)) {
       if (s.phase == P_NEWTON)
         newton_done<G, 0>(a, j, s, ls, 2);
@@ -300,6 +300,7 @@ int mgrhd_batch_create(const mgrhd_patch* patches, int32_t n_patches, int32_t me
     a.max_newton = opt->max_newton;
     a.max_outer = opt->max_outer;
     a.polish = opt->polish;
+    set_derived(a);
     bt->n_cells += q.n_cells;
     bt->max_groups = std::max(bt->max_groups, q.n_groups);
   }

@@ -121,7 +121,7 @@ __global__ __launch_bounds__(256) void k_gemm(const float* __restrict__ A, int l
         if (m >= M) continue;
         float z = acc[a][b][i] + bv;
         if (EPI == EPI_BIAS_SILU) {
-          Z[m * ldc + n] = z;
+          if (Z) Z[m * ldc + n] = z;  // pre-activation, kept for the backward pass
           z = z / (1.f + expf(-z));
         }
         C[m * ldc + n] = z;
@@ -224,6 +224,15 @@ __device__ __forceinline__ double cell_T(const PhysArgs& p, int64_t i) {
 
 __global__ void k_features(PhysArgs p, const float* __restrict__ mean,
                            const float* __restrict__ istd, float* __restrict__ X) {
+  // ln(chi_0E,g per unit rho kappa) of the PPL-fixed group mean, per group
+  __shared__ double lchi[MGRHD_MAX_GROUPS];
+  const int ng = p.ng;
+  for (int g = threadIdx.x; g < ng; g += blockDim.x) {
+    const double L = log(p.edges[g + 1] / p.edges[g]);
+    const double ac = p.alpha ? p.alpha[g] : 0.0;
+    lchi[g] = log(p.chi_lo[g] * mean_ratio(ac, -1.0, L));
+  }
+  __syncthreads();
   const int64_t n = p.n;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -231,7 +240,7 @@ __global__ void k_features(PhysArgs p, const float* __restrict__ mean,
     const double rho = p.rho[i];
     const double aT4 = p.a * (T * T) * (T * T);
     const double kap = p.kappa ? p.kappa[i] : 1.0;
-    const int ng = p.ng;
+    const double lcell = log(p.chat * p.dt * rho * kap);
     auto put = [&](int f, double x) { X[(int64_t)f * n + i] = (float)((x - mean[f]) * istd[f]); };
     put(0, log(T));
     put(1, log(rho));
@@ -242,12 +251,9 @@ __global__ void k_features(PhysArgs p, const float* __restrict__ mean,
       const double f2 = p.F[((int64_t)2 * ng + g) * n + i];
       const double le = E > 0.0 ? fmin(fmax(log(E / aT4), -50.0), 50.0) : -50.0;
       const double fr = E > 0.0 ? fmin(sqrt(f0 * f0 + f1 * f1 + f2 * f2) / (p.c * E), 2.0) : 0.0;
-      const double L = log(p.edges[g + 1] / p.edges[g]);
-      const double ac = p.alpha ? p.alpha[g] : 0.0;
-      const double chiE = rho * kap * p.chi_lo[g] * mean_ratio(ac, -1.0, L);
       put(2 + g, le);
       put(2 + ng + g, fr);
-      put(2 + 2 * ng + g, log(p.chat * p.dt * chiE));
+      put(2 + 2 * ng + g, lcell + lchi[g]);
     }
   }
 }
@@ -347,18 +353,19 @@ static void gemm(hipStream_t s, const float* A, int lda, const float* B, int ldb
 // forward of `rows` rows.  X_fm: features feature-major [n_in x ld_x]; the
 // rows are X_fm[:, 0:rows].  Output Y row-major [rows x n_out].
 static void forward(mgrhd_mlp* m, hipStream_t s, const float* X_fm, int64_t ld_x, int64_t rows,
-                    float* Y) {
+                    float* Y, bool keep_z) {
   const float* in = X_fm;
   for (int l = 0; l < 3; ++l) {
     const float* W = m->params + m->w_off[l];
     const float* b = m->params + m->b_off[l];
     if (l == 0)
       gemm<true, true, EPI_BIAS_SILU>(s, in, (int)ld_x, W, m->in_dim[l], b, m->H[l],
-                                      m->out_dim[l], m->Zs[l], rows, m->out_dim[l], m->in_dim[l]);
+                                      m->out_dim[l], keep_z ? m->Zs[l] : nullptr, rows,
+                                      m->out_dim[l], m->in_dim[l]);
     else
       gemm<false, true, EPI_BIAS_SILU>(s, in, m->in_dim[l], W, m->in_dim[l], b, m->H[l],
-                                       m->out_dim[l], m->Zs[l], rows, m->out_dim[l],
-                                       m->in_dim[l]);
+                                       m->out_dim[l], keep_z ? m->Zs[l] : nullptr, rows,
+                                       m->out_dim[l], m->in_dim[l]);
     in = m->H[l];
   }
   gemm<false, true, EPI_BIAS>(s, in, m->in_dim[3], m->params + m->w_off[3], m->in_dim[3],
@@ -505,7 +512,7 @@ int mgrhd_mlp_forward(mgrhd_mlp* m, const float* X_fm, int64_t ld_x, int64_t row
   hipStream_t s = (hipStream_t)stream;
   for (int64_t r0 = 0; r0 < rows; r0 += m->max_rows) {
     const int64_t r = std::min(m->max_rows, rows - r0);
-    forward(m, s, X_fm + r0, ld_x, r, Y + r0 * m->n_out);
+    forward(m, s, X_fm + r0, ld_x, r, Y + r0 * m->n_out, false);
   }
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? 0 : (int)e;
@@ -516,7 +523,7 @@ int mgrhd_mlp_gradients(mgrhd_mlp* m, const float* X_fm, int64_t ld_x, int64_t r
   if (!m || !X_fm || !Y_target) return MGRHD_E_NULL;
   if (rows < 1 || rows > m->max_rows || ld_x < rows) return MGRHD_E_SIZE;
   hipStream_t s = (hipStream_t)stream;
-  forward(m, s, X_fm, ld_x, rows, m->Y);
+  forward(m, s, X_fm, ld_x, rows, m->Y, true);
   backward(m, s, X_fm, ld_x, rows, Y_target);
   if (loss_out)
     (void)hipMemcpyAsync(loss_out, m->loss, sizeof(float), hipMemcpyDeviceToDevice, s);

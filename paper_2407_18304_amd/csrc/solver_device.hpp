@@ -40,7 +40,20 @@ struct KArgs {
   int32_t closure;
   double dt, chat, c, a, hk, cv, eps, eps_out;
   int32_t max_newton, max_outer, polish, guess_kind;
+  // derived on the host (set_derived): c/c_hat, c_hat/c, c_hat dt, 1/c^2,
+  // 1/(c c_hat), c_hat dt / c^2
+  double cc, icc, cdt, ic2, iccc, cdt_ic2;
 };
+
+// Fill the derived constants of a (host side).
+inline void set_derived(KArgs& a) {
+  a.cc = a.c / a.chat;
+  a.icc = a.chat / a.c;
+  a.cdt = a.chat * a.dt;
+  a.ic2 = 1.0 / (a.c * a.c);
+  a.iccc = 1.0 / (a.c * a.chat);
+  a.cdt_ic2 = a.cdt * a.ic2;
+}
 
 constexpr int kBlock = 256;
 constexpr int kWave = 64;
@@ -325,6 +338,7 @@ struct CellState {
   int phase, st, steps, passes, k_out, polish_left;
   bool warm, fell_back, elim;
   double rho, rho_kappa, egas0, etot, ke, egv, egas_new;
+  double ircv, ietot;  // 1/(rho c_v), 1/E_tot
   double v[3];
   double R[G], E0[G];  // F_g^(t) and v^(t) stay in global memory, F_k in LDS
   double vF[G];        // v_k . F_g,k of the current outer pass
@@ -350,7 +364,8 @@ __device__ __forceinline__ void load_cell(const KArgs& a, const Tables<NGM>& t, 
   bool ok = s.rho > 0.0 && isfinite(s.rho) && kap > 0.0 && isfinite(kap) && isfinite(s.egas0) &&
             isfinite(s.v[0]) && isfinite(s.v[1]) && isfinite(s.v[2]);
   s.rho_kappa = s.rho * kap;
-  const double cdt = a.chat * a.dt;
+  s.ircv = 1.0 / (s.rho * a.cv);
+  const double cdt = a.cdt;
   double sumE = 0.0;
 #pragma unroll
   for (int k = 0; k < G; ++k) {
@@ -387,7 +402,8 @@ __device__ __forceinline__ void load_cell(const KArgs& a, const Tables<NGM>& t, 
   sumE = cell_sum<LPC>(sumE, s.lpc);
   const double bad = cell_sum<LPC>(ok ? 0.0 : 1.0, s.lpc);
   s.ke = 0.5 * s.rho * (s.v[0] * s.v[0] + s.v[1] * s.v[1] + s.v[2] * s.v[2]);
-  s.etot = s.egas0 + (a.chat / a.c) * sumE;  // E_tot of Sec. 3
+  s.etot = s.egas0 + a.icc * sumE;  // E_tot of Sec. 3
+  s.ietot = 1.0 / s.etot;
   ok = bad == 0.0 && (s.egas0 - s.ke) > 0.0 && s.etot > 0.0;
   s.warm = a.guess != nullptr;
   s.elim = false;
@@ -483,7 +499,7 @@ __device__ __forceinline__ void newton_done(const KArgs& a, int j, CellState<G>&
 #pragma unroll
   for (int k = 0; k < G; ++k) sumR += s.R[k];
   sumR = cell_sum<LPC>(sumR, s.lpc);
-  s.egas_new = s.egas0 - (a.c / a.chat) * sumR;
+  s.egas_new = s.egas0 - a.cc * sumR;
   s.phase = P_FLUX;
 }
 
@@ -494,8 +510,8 @@ __device__ __forceinline__ void group_balance(const KArgs& a, const Tables<NGM>&
                                               CellState<G>& s, const LaneStore<G>& ls,
                                               const Cache<G>& c) {
   const int ng = a.ng;
-  const double cdt = a.chat * a.dt;
-  const double ic2 = 1.0 / (a.c * a.c);
+  const double cdt = a.cdt;
+  const double ic2 = a.ic2;
 #pragma unroll
   for (int k = 0; k < G; ++k) {
     const int g = j * G + k;
@@ -520,10 +536,10 @@ __device__ __forceinline__ void newton_step(const KArgs& a, const Tables<NGM>& t
                                             CellState<G>& s, const LaneStore<G>& ls,
                                             const Cache<G>& c) {
   const int ng = a.ng;
-  const double cc = a.c / a.chat;
-  const double cdt = a.chat * a.dt;
-  const double ic2 = 1.0 / (a.c * a.c);
-  const double ircv = 1.0 / (s.rho * a.cv);
+  const double cc = a.cc;
+  const double cdt = a.cdt;
+  const double ic2 = a.ic2;
+  const double ircv = s.ircv;
   double sumR = 0.0, sumAbs = 0.0, sumA = 0.0, sumB = 0.0;
   double ag[G], bg[G];
 #pragma unroll
@@ -557,7 +573,7 @@ __device__ __forceinline__ void newton_step(const KArgs& a, const Tables<NGM>& t
   sumA = cell_sum<LPC>(sumA, s.lpc);
   sumB = cell_sum<LPC>(sumB, s.lpc);
   const double FG = s.egv - s.egas0 + cc * sumR;
-  const bool conv = fabs(FG) / s.etot < a.eps && cc * sumAbs / s.etot < a.eps;
+  const bool conv = fabs(FG) * s.ietot < a.eps && cc * sumAbs * s.ietot < a.eps;
   if (s.polish_left < 0 && conv) s.polish_left = a.polish;
   if (s.polish_left == 0) {
     newton_done<G, LPC>(a, j, s, ls, 0);
@@ -594,7 +610,7 @@ __device__ __forceinline__ bool flux_step(const KArgs& a, const Tables<NGM>& t, 
                                           const Cache<G>& c) {
   const int ng = a.ng;
   const int64_t n = a.n, i = s.i;
-  const double cdt = a.chat * a.dt;
+  const double cdt = a.cdt;
   double dmom[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int k = 0; k < G; ++k) {
@@ -614,8 +630,8 @@ __device__ __forceinline__ bool flux_step(const KArgs& a, const Tables<NGM>& t, 
       dmom[d] += f - f0;
     }
   }
-  const double ccc = 1.0 / (a.c * a.chat);
-  const double irho = 1.0 / s.rho;
+  const double ccc = a.iccc;
+  const double irho = s.ircv * a.cv;
   double vn[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
@@ -631,7 +647,7 @@ __device__ __forceinline__ bool flux_step(const KArgs& a, const Tables<NGM>& t, 
     dW += fabs((1.0 + t.achi[g]) * c.chiF[k] * (vf_new - s.vF[k]));
     s.vF[k] = vf_new;
   }
-  dW = cell_sum<LPC>(dW, s.lpc) * (cdt / (a.c * a.c));
+  dW = cell_sum<LPC>(dW, s.lpc) * a.cdt_ic2;
   const double ke_new = 0.5 * s.rho * (vn[0] * vn[0] + vn[1] * vn[1] + vn[2] * vn[2]);
   s.egv = s.egas_new + (ke_new - s.ke);
   s.ke = ke_new;

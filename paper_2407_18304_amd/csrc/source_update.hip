@@ -92,7 +92,7 @@ __global__ __launch_bounds__(kBlock, WPE) void k_source_update(KArgs a) {
     if (s.phase != P_NEWTON && s.phase != P_FLUX) continue;
 
     // one material evaluation at this cell's current temperature
-    const double T = ((s.phase == P_FLUX ? s.egas_new : s.egv) - s.ke) / (s.rho * a.cv);
+    const double T = ((s.phase == P_FLUX ? s.egas_new : s.egv) - s.ke) * s.ircv;
     if (!(T > 0.0) || !isfinite(T)) {
       if (s.phase == P_NEWTON)
         newton_done<G, LPC>(a, j, s, ls, 2);
@@ -146,9 +146,8 @@ static Variant kVariants[] = {
     MGRHD_VARIANT(4, 64, 2), MGRHD_VARIANT(2, 2, 3),  MGRHD_VARIANT(2, 4, 3),
     MGRHD_VARIANT(2, 8, 3),  MGRHD_VARIANT(2, 16, 3), MGRHD_VARIANT(2, 32, 3),
     MGRHD_VARIANT(1, 4, 4),  MGRHD_VARIANT(1, 8, 4),  MGRHD_VARIANT(1, 16, 4),
-    MGRHD_VARIANT(1, 32, 4), MGRHD_VARIANT(1, 64, 4), MGRHD_VARIANT(4, 4, 3),
-    MGRHD_VARIANT(4, 4, 4),  MGRHD_VARIANT(4, 16, 3), MGRHD_VARIANT(4, 16, 4),
-    MGRHD_VARIANT(2, 8, 4),  MGRHD_VARIANT(2, 32, 4),
+    MGRHD_VARIANT(1, 32, 4), MGRHD_VARIANT(1, 64, 4), MGRHD_VARIANT(2, 8, 4),
+    MGRHD_VARIANT(2, 32, 4),
 };
 
 // user overrides per group count (0 = built-in choice)
@@ -320,6 +319,7 @@ int mgrhd_source_update(double* E_g, double* F_g, const double* rho, double* e_g
   a.max_newton = opt->max_newton;
   a.max_outer = opt->max_outer;
   a.polish = opt->polish;
+  set_derived(a);
 
   // persistent grid: one resident wave of workgroups, never more workgroups
   // than there are cell groups to fill them

@@ -282,7 +282,8 @@ def train(Xraw, Yraw, ok, *, epochs=8, batch=4096, lr=2e-3, n_hidden=128, seed=2
     x_istd = (1.0 / x_std).contiguous()
     X = ((Xraw - x_mean[:, None]) * x_istd[:, None]).contiguous()
     Y = ((Yraw - y_mean[None, :]) / y_std[None, :]).contiguous()
-    net = MLP(X.shape[0], Y.shape[1], n_hidden, max_rows=max(batch, 1 << 16), seed=seed)
+    # rows per forward chunk: the activations of 2^20 rows take ~3 GB
+    net = MLP(X.shape[0], Y.shape[1], n_hidden, max_rows=max(batch, 1 << 20), seed=seed)
     Xh, Yh = X[:, hold].contiguous(), Y[hold].contiguous()
     history = []
     steps_per_epoch = max(1, tr.numel() // batch)
