@@ -300,7 +300,10 @@ __device__ __forceinline__ void evaluate(const Tables<NGM>& t, int ng, int j, do
   }
 }
 
-// P_g . v of the group closure (Sec. 2.1: M1 per group, or Eddington)
+// P_g . v of the group closure (Sec. 2.1: M1 per group, or Eddington).  M1:
+// P = E [(1 - chi)/2 I + (3 chi - 1)/2 n n] with n = F/|F| and the Levermore
+// Eddington factor chi(f), f = min(|F|/(cE), 1); n (n . v) = F (F . v)/|F|^2,
+// and chi needs only f^2, so one square root serves.
 __device__ __forceinline__ void pressure_dot_v(int closure, double c, double E, double F0,
                                                double F1, double F2, const double* v,
                                                double* Pv) {
@@ -308,24 +311,23 @@ __device__ __forceinline__ void pressure_dot_v(int closure, double c, double E, 
     Pv[0] = Pv[1] = Pv[2] = 0.0;
     return;
   }
-  const double fm = sqrt(F0 * F0 + F1 * F1 + F2 * F2);
-  if (closure == MGRHD_CLOSURE_EDDINGTON || fm == 0.0) {
+  const double FF = F0 * F0 + F1 * F1 + F2 * F2;
+  if (closure == MGRHD_CLOSURE_EDDINGTON || FF == 0.0) {
     const double e3 = E * kThird;
     Pv[0] = e3 * v[0];
     Pv[1] = e3 * v[1];
     Pv[2] = e3 * v[2];
     return;
   }
-  double f = fm / (c * E);
-  f = f > 1.0 ? 1.0 : f;
-  const double chi = (3.0 + 4.0 * f * f) / (5.0 + 2.0 * sqrt(4.0 - 3.0 * f * f));
-  const double ifm = 1.0 / fm;
-  const double n0 = F0 * ifm, n1 = F1 * ifm, n2 = F2 * ifm;
-  const double nv = n0 * v[0] + n1 * v[1] + n2 * v[2];
-  const double p = 0.5 * (1.0 - chi), q = 0.5 * (3.0 * chi - 1.0);
-  Pv[0] = E * (p * v[0] + q * n0 * nv);
-  Pv[1] = E * (p * v[1] + q * n1 * nv);
-  Pv[2] = E * (p * v[2] + q * n2 * nv);
+  const double icE = 1.0 / (c * E);
+  double f2 = FF * icE * icE;
+  f2 = f2 > 1.0 ? 1.0 : f2;
+  const double chi = (3.0 + 4.0 * f2) / (5.0 + 2.0 * sqrt(4.0 - 3.0 * f2));
+  const double p = 0.5 * (1.0 - chi);
+  const double q = 0.5 * (3.0 * chi - 1.0) * (F0 * v[0] + F1 * v[1] + F2 * v[2]) / FF;
+  Pv[0] = E * (p * v[0] + q * F0);
+  Pv[1] = E * (p * v[1] + q * F1);
+  Pv[2] = E * (p * v[2] + q * F2);
 }
 
 enum Phase : int { P_EMPTY = 0, P_NEWTON = 1, P_FLUX = 2, P_IDLE = 3 };

@@ -70,11 +70,11 @@ def unit_costs(w=W):
     nt_group = {PC: 21, FIXED: 21, FREE: 21 + 1 + 3 * dv + 3}
     nt_cell = 2 * (1 + dv) + 2 + (dv + 1) + (dv + 2) + (4 + dv) + 5   # 1/c^2, 1/(rho c_v),
     #                                      F_G, two stop tests, dx_0, the step
-    # flux update per group: E_new (1), M1 closure P.v (|F|: 5+sqrt, f: 1+div, chi:
-    # 8+sqrt+div, 1/|F|: div, n: 3, n.v: 5, p q: 5, P.v: 15), 1/(1+cdt chi_F)
+    # flux update per group: E_new (1), M1 closure P.v (F.F: 5, 1/(cE): 1+div,
+    # f^2: 2, chi: 6+sqrt+div, p: 2, F.v: 5, q: 4+div, P.v: 12), 1/(1+cdt chi_F)
     # (2+div), chi_E and (1+a)chi_E (3), three components (3 x 8), the new v.F (5)
     # and the dW term (5)
-    fx_group = 1 + (42 + 2 * sq + 3 * dv) + (2 + dv) + 3 + 24 + 10
+    fx_group = 1 + (37 + sq + 3 * dv) + (2 + dv) + 3 + 24 + 10
     fx_cell = 2 * (1 + dv) + 12 + (2 + dv) + 7 + 2
     # cell load: per group E0 (1), sum (1), v.F (5), 1/tau and 1/J_gg (3 + 2 div)
     ld_group = {PC: 10 + 2 * dv, FIXED: 10 + 2 * dv, FREE: 7}
