@@ -151,11 +151,11 @@ __global__ __launch_bounds__(kBlock, 2) void k_batch(BatchArgs b) {
 #pragma unroll
     for (int k = 0; k < G; ++k) Ecur[k] = s.E0[k] + s.R[k];
     const double aT4 = a.a * (T * T) * (T * T);
-    evaluate<G, 0, MODE, kBatchNGM>(tab, a.ng, j, T, aT4, a.hk, s.rho_kappa, Ecur, c);
+    evaluate<G, 0, MODE, kBatchNGM>(tab, a.ng, j, s.lpc, T, aT4, a.hk, s.rho_kappa, Ecur, c);
     if (s.phase == P_FLUX) {
       if (!flux_step<G, 0, MODE, kBatchNGM>(a, tab, j, s, ls, c)) continue;
     }
-    if (s.elim) group_balance<G, MODE, kBatchNGM>(a, tab, j, s, ls, c);
+    if (s.elim) group_balance<G, 0, MODE, kBatchNGM>(a, tab, j, s, ls, c);
     newton_step<G, 0, MODE, kBatchNGM>(a, tab, j, s, ls, c);
   }
 }

@@ -3,8 +3,9 @@
 // (batch.hip): group tables in LDS, material evaluation, the Newton and
 // outer-stage consumers, and the per-cell state machine.
 //
-// A "cell group" of LPC consecutive lanes owns one cell; lane j of the group
-// owns groups j*G .. j*G+G-1.  The lane count per cell is a template
+// A "cell group" of LPC consecutive lanes owns one cell; its groups are dealt
+// to the lanes in turn, slot k of lane j holding group k*LPC + j (see gidx).
+// The lane count per cell is a template
 // parameter in the single-table kernel and a run-time value (uniform over the
 // wave) in the batched kernel: LPC = 0 in the templates below means "read
 // lpc at run time".
@@ -113,6 +114,43 @@ __device__ __forceinline__ double cell_sum(double v, int lpc) {
   return v;
 }
 
+// Group held by slot k of lane j.  Dealing the groups to the lanes in turn
+// puts adjacent groups on adjacent lanes at every slot, so at one slot the
+// cells of a wave evaluate their Planck edges in a narrow band of
+// x = h nu / kT and mostly take the same branch (all below the Wien side at
+// the first slots, all on it at the last ones).
+template <int LPC>
+__device__ __forceinline__ int gidx(int j, int k, int lpc) {
+  return k * (LPC > 0 ? LPC : lpc) + j;
+}
+
+// Value held by lane (j - 1) mod lpc, resp. (j + 1) mod lpc, of this lane's
+// cell group.  Every lane of the group must execute it (all are active
+// together).  DPP quad permutations and row rotations where they fit the
+// group, the LDS crossbar otherwise.
+template <int LPC>
+__device__ __forceinline__ double from_left(double v, int lpc) {
+  const int n = LPC > 0 ? LPC : lpc;
+  if (n == 1) return v;
+  if (n == 2) return dpp_swap<0xB1>(v);   // quad_perm [1,0,3,2]
+  if (n == 4) return dpp_swap<0x93>(v);   // quad_perm [3,0,1,2]
+  if (n == 16) return dpp_swap<0x121>(v); // row_ror:1
+  const int lane = __lane_id();
+  const int base = lane & ~(n - 1);
+  return __shfl(v, base + ((lane - base + n - 1) & (n - 1)), kWave);
+}
+template <int LPC>
+__device__ __forceinline__ double from_right(double v, int lpc) {
+  const int n = LPC > 0 ? LPC : lpc;
+  if (n == 1) return v;
+  if (n == 2) return dpp_swap<0xB1>(v);   // quad_perm [1,0,3,2]
+  if (n == 4) return dpp_swap<0x39>(v);   // quad_perm [1,2,3,0]
+  if (n == 16) return dpp_swap<0x12F>(v); // row_ror:15
+  const int lane = __lane_id();
+  const int base = lane & ~(n - 1);
+  return __shfl(v, base + ((lane - base + 1) & (n - 1)), kWave);
+}
+
 // Table entries of group g (edges already staged in t.nu); false if the
 // group's table is unusable.
 template <int NGM, int MODE>
@@ -196,19 +234,20 @@ struct Cache {
   double chiE[G];
 };
 
+// Appendix A slopes of the lane's groups from ln Qbar (lq, per slot).  The
+// neighbours of group g = k lpc + j are on lanes j -+ 1 at the same slot, or
+// on the last (first) lane at the previous (next) slot.
 template <int G, int LPC, int NGM>
-__device__ __forceinline__ void slopes_free(const Tables<NGM>& t, int ng, int j, const double* lq,
-                                            double* alpha) {
-  const int lane = __lane_id();
-  const double left = __shfl(lq[G - 1], lane > 0 ? lane - 1 : 0, kWave);
-  const double right = __shfl(lq[0], lane < kWave - 1 ? lane + 1 : kWave - 1, kWave);
+__device__ __forceinline__ void slopes_free(const Tables<NGM>& t, int ng, int j, int lpc,
+                                            const double* lq, double* alpha) {
+  const int n = LPC > 0 ? LPC : lpc;
 #pragma unroll
   for (int k = 0; k < G; ++k) {
-    const int g = j * G + k;
+    const double lm = from_left<LPC>((j == n - 1) ? (k > 0 ? lq[k - 1] : -INFINITY) : lq[k], lpc);
+    const double lp = from_right<LPC>((j == 0) ? (k < G - 1 ? lq[k + 1] : -INFINITY) : lq[k], lpc);
+    const int g = gidx<LPC>(j, k, lpc);
     alpha[k] = -1.0;
     if (g <= 0 || g >= ng - 1) continue;
-    const double lm = (k == 0) ? left : lq[k - 1];
-    const double lp = (k == G - 1) ? right : lq[k + 1];
     const double sl = (lq[k] - lm) / (t.lnc[g] - t.lnc[g - 1]);
     const double sr = (lp - lq[k]) / (t.lnc[g + 1] - t.lnc[g]);
     if (isnan(sl) || isnan(sr)) continue;
@@ -217,23 +256,44 @@ __device__ __forceinline__ void slopes_free(const Tables<NGM>& t, int ng, int j,
   }
 }
 
+// Low edge of slot k's group: the high edge of lane j - 1 at this slot, or,
+// on lane 0, the high edge of the last lane at the previous slot (kept in
+// `prev`; edge 0 before slot 0).  The wien/inf flags follow from x.
+template <int LPC>
+__device__ __forceinline__ Edge low_edge(const Edge& hi, const Edge& prev, int j, int lpc) {
+  const int n = LPC > 0 ? LPC : lpc;
+  const bool last = j == n - 1;
+  Edge lo;
+  lo.x = from_left<LPC>(last ? prev.x : hi.x, lpc);
+  lo.u = from_left<LPC>(last ? prev.u : hi.u, lpc);
+  lo.val = from_left<LPC>(last ? prev.val : hi.val, lpc);
+  lo.eps = from_left<LPC>(last ? prev.eps : hi.eps, lpc);
+  lo.wien = lo.x > kPlanckSplit;
+  lo.inf = is_pinf(lo.x);
+  return lo;
+}
+
 // One material evaluation: Planck data, slopes (PPL-free), group means.
 // In PC and PPL-fixed chi_0E = chi_0B = rho kappa chk_g is fixed per cell.
 template <int G, int LPC, int MODE, int NGM>
-__device__ __forceinline__ void evaluate(const Tables<NGM>& t, int ng, int j, double T, double aT4,
-                                         double hk, double rho_kappa, const double* Ecur,
-                                         Cache<G>& c) {
+__device__ __forceinline__ void evaluate(const Tables<NGM>& t, int ng, int j, int lpc, double T,
+                                         double aT4, double hk, double rho_kappa,
+                                         const double* Ecur, Cache<G>& c) {
+  const int n = LPC > 0 ? LPC : lpc;
   const double invT = 1.0 / T;
   const double hkT = hk * invT;
-  Edge lo = planck_edge(hkT * t.nu[min(j * G, ng)]);
+  Edge prev;
+  prev.x = prev.u = prev.val = prev.eps = 0.0;
+  if (j == n - 1) prev = planck_edge(hkT * t.nu[0]);  // edge 0, handed to lane 0
   if (MODE != MGRHD_MEAN_PPL_FREE) {
 #pragma unroll
     for (int k = 0; k < G; ++k) {
-      const int g = j * G + k;
-      if (g >= ng) break;
-      const Edge hi = planck_edge(hkT * t.nu[g + 1]);
+      const int g = gidx<LPC>(j, k, lpc);
+      const Edge hi = planck_edge(hkT * t.nu[min(g + 1, ng)]);
+      const Edge lo = low_edge<LPC>(hi, prev, j, lpc);
+      prev = hi;
+      if (g >= ng) continue;
       const GroupPlanck p = group_planck(lo, hi);
-      lo = hi;
       const double Bt = aT4 * p.b * p.scale;
       const double Dnu = aT4 * (p.ehi - p.elo) * p.scale;
       c.Bt[k] = Bt;
@@ -257,15 +317,16 @@ __device__ __forceinline__ void evaluate(const Tables<NGM>& t, int ng, int j, do
     double b[G], elo[G], ehi[G], sig[G], scale[G], lqB[G], lqE[G], aB[G], aE[G];
 #pragma unroll
     for (int k = 0; k < G; ++k) {
-      const int g = j * G + k;
+      const int g = gidx<LPC>(j, k, lpc);
+      const Edge hi = planck_edge(hkT * t.nu[min(g + 1, ng)]);
+      const Edge lo = low_edge<LPC>(hi, prev, j, lpc);
+      prev = hi;
       lqB[k] = -INFINITY;
       lqE[k] = -INFINITY;
       b[k] = elo[k] = ehi[k] = sig[k] = 0.0;
       scale[k] = 1.0;
       if (g >= ng) continue;
-      const Edge hi = planck_edge(hkT * t.nu[g + 1]);
       const GroupPlanck p = group_planck(lo, hi);
-      lo = hi;
       b[k] = p.b;
       elo[k] = p.elo;
       ehi[k] = p.ehi;
@@ -274,12 +335,12 @@ __device__ __forceinline__ void evaluate(const Tables<NGM>& t, int ng, int j, do
       if (p.b > 0.0) lqB[k] = log(p.b) - p.sigma - t.lndnu[g];
       if (Ecur[k] > 0.0) lqE[k] = log(Ecur[k]) - t.lndnu[g];
     }
-    slopes_free<G, LPC, NGM>(t, ng, j, lqB, aB);
-    slopes_free<G, LPC, NGM>(t, ng, j, lqE, aE);
+    slopes_free<G, LPC, NGM>(t, ng, j, lpc, lqB, aB);
+    slopes_free<G, LPC, NGM>(t, ng, j, lpc, lqE, aE);
 #pragma unroll
     for (int k = 0; k < G; ++k) {
-      const int g = j * G + k;
-      if (g >= ng) break;
+      const int g = gidx<LPC>(j, k, lpc);
+      if (g >= ng) continue;
       const double ac = t.achi[g], L = t.lnr[g];
       const double chl = rho_kappa * t.chit[g];
       const double Bt = aT4 * b[k] * scale[k];
@@ -371,7 +432,7 @@ __device__ __forceinline__ void load_cell(const KArgs& a, const Tables<NGM>& t, 
   double sumE = 0.0;
 #pragma unroll
   for (int k = 0; k < G; ++k) {
-    const int g = j * G + k;
+    const int g = gidx<LPC>(j, k, s.lpc);
     s.R[k] = 0.0;
     s.E0[k] = 0.0;
     s.vF[k] = 0.0;
@@ -418,7 +479,7 @@ __device__ __forceinline__ void load_cell(const KArgs& a, const Tables<NGM>& t, 
     } else {
 #pragma unroll
       for (int k = 0; k < G; ++k) {
-        const int g = j * G + k;
+        const int g = gidx<LPC>(j, k, s.lpc);
         if (g < ng) s.R[k] = a.guess[(int64_t)(g + 1) * n + i];
       }
     }
@@ -441,7 +502,7 @@ __device__ __forceinline__ void finish_cell(const KArgs& a, int j, CellState<G>&
                      ? 0.0 : 1.0;
 #pragma unroll
     for (int k = 0; k < G; ++k) {
-      if (j * G + k >= ng) continue;
+      if (gidx<LPC>(j, k, s.lpc) >= ng) continue;
       if (!isfinite(s.E0[k] + s.R[k])) bad = 1.0;
 #pragma unroll
       for (int d = 0; d < 3; ++d)
@@ -453,7 +514,7 @@ __device__ __forceinline__ void finish_cell(const KArgs& a, int j, CellState<G>&
     } else {
 #pragma unroll
       for (int k = 0; k < G; ++k) {
-        const int g = j * G + k;
+        const int g = gidx<LPC>(j, k, s.lpc);
         if (g >= ng) continue;
         a.E[(int64_t)g * n + i] = s.E0[k] + s.R[k];
 #pragma unroll
@@ -507,7 +568,7 @@ __device__ __forceinline__ void newton_done(const KArgs& a, int j, CellState<G>&
 
 // Temperature-only start: at the cached material state, eq. Rnew inverted for
 // E_g and F_R,g = 0 (eq. FGFR) are linear in R_g alone; take that R_g.
-template <int G, int MODE, int NGM>
+template <int G, int LPC, int MODE, int NGM>
 __device__ __forceinline__ void group_balance(const KArgs& a, const Tables<NGM>& t, int j,
                                               CellState<G>& s, const LaneStore<G>& ls,
                                               const Cache<G>& c) {
@@ -516,7 +577,7 @@ __device__ __forceinline__ void group_balance(const KArgs& a, const Tables<NGM>&
   const double ic2 = a.ic2;
 #pragma unroll
   for (int k = 0; k < G; ++k) {
-    const int g = j * G + k;
+    const int g = gidx<LPC>(j, k, s.lpc);
     if (g >= ng) continue;
     double ratio = 1.0, itau;
     if (MODE == MGRHD_MEAN_PPL_FREE) {
@@ -548,7 +609,7 @@ __device__ __forceinline__ void newton_step(const KArgs& a, const Tables<NGM>& t
   for (int k = 0; k < G; ++k) {
     ag[k] = 0.0;
     bg[k] = 0.0;
-    const int g = j * G + k;
+    const int g = gidx<LPC>(j, k, s.lpc);
     if (g >= ng) continue;
     double ratio = 1.0, itau, iJgg;
     if (MODE == MGRHD_MEAN_PPL_FREE) {
@@ -616,7 +677,7 @@ __device__ __forceinline__ bool flux_step(const KArgs& a, const Tables<NGM>& t, 
   double dmom[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int k = 0; k < G; ++k) {
-    const int g = j * G + k;
+    const int g = gidx<LPC>(j, k, s.lpc);
     if (g >= ng) continue;
     const double Enew = s.E0[k] + s.R[k];
     const double chE = (MODE == MGRHD_MEAN_PPL_FREE) ? c.chiE[k] : s.rho_kappa * t.chk[g];
@@ -643,7 +704,7 @@ __device__ __forceinline__ bool flux_step(const KArgs& a, const Tables<NGM>& t, 
   double dW = 0.0;
 #pragma unroll
   for (int k = 0; k < G; ++k) {
-    const int g = j * G + k;
+    const int g = gidx<LPC>(j, k, s.lpc);
     if (g >= ng) continue;
     const double vf_new = vn[0] * ls.F(0, k) + vn[1] * ls.F(1, k) + vn[2] * ls.F(2, k);
     dW += fabs((1.0 + t.achi[g]) * c.chiF[k] * (vf_new - s.vF[k]));

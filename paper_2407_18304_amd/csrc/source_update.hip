@@ -2,18 +2,21 @@
 // matter-radiation source update (He, Wibking & Krumholz 2024, Sec. 3).
 //
 // Work decomposition.  LPC consecutive lanes of a wavefront own one cell (a
-// "cell group"); lane j of the group owns the G consecutive groups
-// j*G .. j*G+G-1 and keeps their state in registers: the Newton unknowns R_g,
-// E_g^(t)+S_g, F_g^(t), F_g of the current outer pass, the temperature-
-// independent opacity constants, and the material data of the last
-// evaluation.  Group sums (sum R_g, sum |F_R,g|, the two sums of the
-// arrowhead elimination, the momentum change, the outer test) are
-// xor-butterfly shuffles inside the LPC lanes, so every lane of a cell holds
-// bit-identical scalars and takes the same branches.
+// "cell group"); its N_g groups are dealt to the lanes in turn, slot k of lane
+// j holding group k*LPC + j (G slots per lane), so that at each slot a wave
+// evaluates Planck edges in a narrow band of x and mostly takes one branch.
+// Registers hold the Newton unknowns R_g, E_g^(t)+S_g and v.F_g of the
+// current outer pass; the fluxes F_g of the pass and the per-cell constants
+// 1/tau_g, 1/J_gg sit in per-lane LDS slots; F_g^(t) and v^(t) stay in HBM.
+// Group sums (sum R_g, sum |F_R,g|, the two sums of the arrowhead
+// elimination, the momentum change, the outer test) are butterflies inside
+// the LPC lanes (DPP where the distance fits a row), so every lane of a cell
+// holds bit-identical scalars and takes the same branches.
 //
 // Persistent state machine.  Each wave owns a contiguous chunk of cells.  One
-// trip of the main loop performs exactly one material evaluation (G+1 Planck
-// edges and G group means per lane) for every active cell group, followed by
+// trip of the main loop performs exactly one material evaluation (G Planck
+// edges, one edge handed over from a neighbour lane, and G group means per
+// lane) for every active cell group, followed by
 // the consumer of the cell's phase: a Newton step, or the flux/momentum
 // update of the outer stage.  The flux-stage evaluation is also the first
 // evaluation of the next inner pass (the pass restarts at the same
@@ -106,13 +109,13 @@ __global__ __launch_bounds__(kBlock, WPE) void k_source_update(KArgs a) {
 #pragma unroll
     for (int k = 0; k < G; ++k) Ecur[k] = s.E0[k] + s.R[k];
     const double aT4 = a.a * (T * T) * (T * T);
-    evaluate<G, LPC, MODE, NGM>(tab, a.ng, j, T, aT4, a.hk, s.rho_kappa, Ecur, c);
+    evaluate<G, LPC, MODE, NGM>(tab, a.ng, j, s.lpc, T, aT4, a.hk, s.rho_kappa, Ecur, c);
 
     if (s.phase == P_FLUX) {
       if (!flux_step<G, LPC, MODE, NGM>(a, tab, j, s, ls, c)) continue;
       // the next inner pass starts at this temperature: fall through
     }
-    if (s.elim) group_balance<G, MODE, NGM>(a, tab, j, s, ls, c);
+    if (s.elim) group_balance<G, LPC, MODE, NGM>(a, tab, j, s, ls, c);
     newton_step<G, LPC, MODE, NGM>(a, tab, j, s, ls, c);
   }
 }
