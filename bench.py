@@ -85,6 +85,9 @@ def main():
     ng = dw.ng
     if args.variant:
         mgrhd.set_variant(ng, *(int(x) for x in args.variant.split("x")))
+    else:
+        from paper_2407_18304_amd import autotune
+        autotune.apply_cache(mode=args.mode)   # the autotuner's choices for this GPU
     pristine = {k: v.clone() for k, v in dw.state.items()}
     st = dw.state
     iters = torch.zeros(n, dtype=torch.int32, device=dev)

@@ -36,11 +36,14 @@ def save_cache(cache, path=CACHE):
         json.dump(cache, f, indent=1, sort_keys=True)
 
 
-def apply_cache(path=CACHE) -> dict:
-    """Install the cached single-table choices for this GPU; returns them."""
+def apply_cache(path=CACHE, mode=None) -> dict:
+    """Install the cached single-table choices for this GPU (for mean mode
+    `mode`, or all); returns them."""
     cache = load_cache(path).get(arch(), {})
     for key, rec in cache.get("single", {}).items():
-        ng = int(key.split(":")[0])
+        ng, m = (int(x) for x in key.split(":"))
+        if mode is not None and m != mode:
+            continue
         try:
             mgrhd.set_variant(ng, rec["lanes_per_cell"], rec["groups_per_lane"],
                               rec.get("waves_per_simd", 0))
