@@ -286,6 +286,20 @@ int mgrhd_mlp_guess(const double* E_g, const double* F_g, const double* rho, con
                     const mgrhd_options* opt, const float* Y_norm, const float* y_mean,
                     const float* y_std, int32_t guess_kind, double* guess,
                     mgrhd_stream_t stream);
+/* Fused inference: features, the three hidden layers, the output layer and
+ * the Newton guess in one kernel, activations kept in LDS (BF16 matrix-core
+ * products, FP32 accumulation; features formed in FP32).  Requires
+ * n_hidden = 128, n_in = 2 + 3 N_g, n_out = 1 + N_g and N_g <= 138.  x_mean,
+ * x_istd [n_in], y_mean, y_std [n_out]: the training normalisation (DEVICE).
+ * guess_kind 1 computes the temperature output only and writes E_gas [n];
+ * guess_kind 0 writes [(N_g+1) x n] (E_gas, R_g).  State arguments as
+ * mgrhd_source_update.  Returns MGRHD_E_SIZE if the network does not fit. */
+int mgrhd_mlp_infer(mgrhd_mlp* m, const double* E_g, const double* F_g, const double* rho,
+                    const double* e_gas, const double* v, int64_t n_cells,
+                    const double* group_edges, const mgrhd_opacity_params* opacity, double dt,
+                    double c_hat, const mgrhd_options* opt, const float* x_mean,
+                    const float* x_istd, const float* y_mean, const float* y_std,
+                    int32_t guess_kind, double* guess, mgrhd_stream_t stream);
 /* C = op(A) op(B) with the BF16 matrix-core kernel (FP32 in and out) */
 int mgrhd_mlp_gemm(const float* A, int32_t lda, int32_t trans_a, const float* B, int32_t ldb,
                    int32_t trans_b, float* C, int32_t ldc, int64_t M, int32_t N, int32_t K,

@@ -305,6 +305,195 @@ __global__ void k_guess(PhysArgs p, const float* __restrict__ Yn, const float* _
   }
 }
 
+// ---------------------------------------------------------------------------
+// Fused inference: features -> 3 SiLU layers -> output -> Newton guess, one
+// tile of kTile cells per block iteration, activations kept in LDS as BF16.
+// Weights are BF16 copies [N_pad x K_pad] (zero padded) read straight from
+// L2 as matrix-core B fragments; wave w computes n-tiles w, w+4, ... for all
+// four 16-row tiles, so every weight element is read once per cell tile.
+// Features are formed in FP32 (they are rounded to BF16 for the products).
+constexpr int kTile = 64;
+constexpr int kHidden = 128;               // hidden width of the fused path
+constexpr int kHPad = kHidden + 8;         // LDS row pitch of a hidden tile
+constexpr int kMaxKin = 416;               // padded input width (N_g <= 138)
+
+struct InferArgs {
+  PhysArgs p;
+  const float* xmean;
+  const float* xistd;
+  const float* ymean;
+  const float* ystd;
+  const __bf16* W[4];  // [N_pad x K_pad] each
+  const float* b[4];   // [N_pad] each (zero padded)
+  int K_pad[4], N_pad[4];
+  int n_in, n_out, kind;
+  const double* S;
+  double* guess;
+};
+
+// one layer: out = act(in W^T + b) on a kTile-row tile; in: LDS bf16 rows of
+// pitch ldi; hidden layers write bf16 to `hout` (pitch kHPad), the output
+// layer writes fp32 to `fout` (pitch ldo).
+template <bool HIDDEN>
+__device__ __forceinline__ void tile_layer(const __bf16* in, int ldi, const __bf16* __restrict__ W,
+                                           const float* __restrict__ bias, int K_pad, int n_tiles,
+                                           __bf16* hout, float* fout, int ldo) {
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  const int r16 = lane % 16, kq = 8 * (lane / 16);
+  for (int nt0 = wave; nt0 < n_tiles; nt0 += 8) {
+    // this wave's n-tiles: nt0 and nt0 + 4 (when present)
+    const int nts[2] = {nt0, nt0 + 4};
+    const bool two = nt0 + 4 < n_tiles;
+    floatx4 acc[4][2];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int t = 0; t < 2; ++t) acc[a][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K_pad; k0 += 32) {
+      bf16x8 bfr[2];
+      bfr[0] = *(const bf16x8*)(W + (int64_t)(16 * nts[0] + r16) * K_pad + k0 + kq);
+      bfr[1] = two ? *(const bf16x8*)(W + (int64_t)(16 * nts[1] + r16) * K_pad + k0 + kq)
+                   : bfr[0];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const bf16x8 af = *(const bf16x8*)(in + (16 * a + r16) * ldi + k0 + kq);
+        acc[a][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfr[0], acc[a][0], 0, 0, 0);
+        if (two)
+          acc[a][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfr[1], acc[a][1], 0, 0, 0);
+      }
+    }
+    const int col16 = lane % 16, row4 = 4 * (lane / 16);
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      if (t == 1 && !two) break;
+      const int n = 16 * nts[t] + col16;
+      const float bv = bias[n];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int r = 16 * a + row4 + i;
+          float z = acc[a][t][i] + bv;
+          if (HIDDEN) {
+            z = z / (1.f + __expf(-z));
+            hout[r * kHPad + n] = (__bf16)z;
+          } else {
+            fout[r * ldo + n] = z;
+          }
+        }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_infer(InferArgs q) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const PhysArgs& p = q.p;
+  const int ng = p.ng;
+  const int64_t n = p.n;
+  const int ldx = q.K_pad[0] + 8;
+  __bf16* X = (__bf16*)smem;                                  // [kTile][ldx]; later H_b / out
+  __bf16* Ha = X + kTile * (ldx > kHPad ? ldx : kHPad);       // [kTile][kHPad]
+  float* lchi = (float*)(Ha + kTile * kHPad);                  // [ng]
+  for (int g = threadIdx.x; g < ng; g += blockDim.x) {
+    const double L = log(p.edges[g + 1] / p.edges[g]);
+    const double ac = p.alpha ? p.alpha[g] : 0.0;
+    lchi[g] = (float)log(p.chi_lo[g] * mean_ratio(ac, -1.0, L));
+  }
+  __syncthreads();
+  const int r = threadIdx.x / 4, qd = threadIdx.x % 4;
+  const int64_t tiles = (n + kTile - 1) / kTile;
+  for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const int64_t i = tile * kTile + r;
+    const bool live = i < n;
+    // ---- features (normalised, bf16) ----
+    {
+      float T = 1.f, rho = 1.f, lcell = 0.f, aT4 = 1.f;
+      if (live) {
+        const double v0 = p.v[i], v1 = p.v[n + i], v2 = p.v[2 * n + i];
+        const double rh = p.rho[i];
+        const double Td = fmax((p.egas[i] - 0.5 * rh * (v0 * v0 + v1 * v1 + v2 * v2)) / (rh * p.cv),
+                               1e-300);
+        const double kap = p.kappa ? p.kappa[i] : 1.0;
+        T = (float)Td;
+        rho = (float)rh;
+        aT4 = (float)(p.a * (Td * Td) * (Td * Td));
+        lcell = (float)log(p.chat * p.dt * rh * kap);
+      }
+      __bf16* xr = X + r * ldx;
+      auto put = [&](int f, float x) { xr[f] = (__bf16)((x - q.xmean[f]) * q.xistd[f]); };
+      if (qd == 0) {
+        put(0, live ? __logf(T) : 0.f);
+        put(1, live ? __logf(rho) : 0.f);
+      }
+      for (int g = qd; g < ng; g += 4) {
+        float le = -50.f, fr = 0.f;
+        if (live) {
+          const double E = p.E[(int64_t)g * n + i];
+          const double f0 = p.F[((int64_t)0 * ng + g) * n + i];
+          const double f1 = p.F[((int64_t)1 * ng + g) * n + i];
+          const double f2 = p.F[((int64_t)2 * ng + g) * n + i];
+          if (E > 0.0) {
+            le = fminf(fmaxf(__logf((float)(E / (double)aT4)), -50.f), 50.f);
+            fr = fminf((float)(sqrt(f0 * f0 + f1 * f1 + f2 * f2) / (p.c * E)), 2.f);
+          }
+        }
+        put(2 + g, le);
+        put(2 + ng + g, fr);
+        put(2 + 2 * ng + g, lcell + lchi[g]);
+      }
+      for (int f = q.n_in + qd; f < q.K_pad[0]; f += 4) xr[f] = (__bf16)0.f;
+    }
+    __syncthreads();
+    // ---- layers: X -> Ha -> Hb (in X's space) -> Ha -> out (fp32 in X's space) ----
+    __bf16* Hb = X;
+    tile_layer<true>(X, ldx, q.W[0], q.b[0], q.K_pad[0], q.N_pad[0] / 16, Ha, nullptr, 0);
+    __syncthreads();
+    tile_layer<true>(Ha, kHPad, q.W[1], q.b[1], q.K_pad[1], q.N_pad[1] / 16, Hb, nullptr, 0);
+    __syncthreads();
+    tile_layer<true>(Hb, kHPad, q.W[2], q.b[2], q.K_pad[2], q.N_pad[2] / 16, Ha, nullptr, 0);
+    __syncthreads();
+    float* out = (float*)X;
+    const int ldo = q.N_pad[3];
+    const int out_tiles = q.kind == 1 ? 1 : q.N_pad[3] / 16;
+    tile_layer<false>(Ha, kHPad, q.W[3], q.b[3], q.K_pad[3], out_tiles, nullptr, out, ldo);
+    __syncthreads();
+    // ---- Newton guess ----
+    if (live) {
+      const double v0 = p.v[i], v1 = p.v[n + i], v2 = p.v[2 * n + i];
+      const double rh = p.rho[i];
+      const double ke = 0.5 * rh * (v0 * v0 + v1 * v1 + v2 * v2);
+      const double Tc = fmax((p.egas[i] - ke) / (rh * p.cv), 1e-300);
+      const float* o = out + r * ldo;
+      if (qd == 0) {
+        const double yT = (double)o[0] * q.ystd[0] + q.ymean[0];
+        q.guess[i] = rh * p.cv * Tc * exp(fmin(fmax(yT, -5.0), 5.0)) + ke;
+      }
+      if (q.kind == 0) {
+        const double aT4 = p.a * (Tc * Tc) * (Tc * Tc);
+        for (int g = qd; g < ng; g += 4) {
+          const double yE = (double)o[1 + g] * q.ystd[1 + g] + q.ymean[1 + g];
+          const double sg = q.S ? q.S[(int64_t)g * n + i] : 0.0;
+          q.guess[(int64_t)(g + 1) * n + i] =
+              aT4 * exp(fmin(fmax(yE, -60.0), 60.0)) - p.E[(int64_t)g * n + i] - sg;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// fp32 weights [N x K] -> bf16 [N_pad x K_pad] (zero padded); biases -> fp32 [N_pad]
+__global__ void k_pack(const float* __restrict__ W, const float* __restrict__ b, int N, int K,
+                       int N_pad, int K_pad, __bf16* __restrict__ Wp, float* __restrict__ bp) {
+  const int64_t total = (int64_t)N_pad * K_pad;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int nn = (int)(e / K_pad), kk = (int)(e % K_pad);
+    Wp[e] = (__bf16)((nn < N && kk < K) ? W[(int64_t)nn * K + kk] : 0.f);
+    if (kk == 0) bp[nn] = nn < N ? b[nn] : 0.f;
+  }
+}
+
 }  // namespace mlp
 }  // namespace mgrhd
 
@@ -333,6 +522,12 @@ struct mgrhd_mlp {
   float* dY = nullptr;
   float* dA = nullptr;
   float* dB = nullptr;
+  // BF16 copies for the fused inference (repacked when the weights change)
+  __bf16* wpack = nullptr;
+  float* bpack = nullptr;
+  int k_pad[kLayers], n_pad[kLayers];
+  int64_t wp_off[kLayers], bp_off[kLayers];
+  bool dirty = true;
 };
 
 static inline dim3 grid1(int64_t n) {
@@ -449,7 +644,18 @@ int mgrhd_mlp_create(int32_t n_in, int32_t n_hidden, int32_t n_out, int64_t max_
       h[m->w_off[l] + k] = (float)((2.0 * next() - 1.0) * lim);
   }
   const int64_t act = (int64_t)max_rows * (6 * n_hidden + 2 * n_out + 2 * std::max(n_hidden, n_out));
-  bool ok = hipMalloc(&m->params, sizeof(float) * off) == hipSuccess &&
+  int64_t wtot = 0, btot = 0;
+  for (int l = 0; l < 4; ++l) {
+    m->k_pad[l] = (dims[l] + 31) / 32 * 32;
+    m->n_pad[l] = (dims[l + 1] + 15) / 16 * 16;
+    m->wp_off[l] = wtot;
+    m->bp_off[l] = btot;
+    wtot += (int64_t)m->k_pad[l] * m->n_pad[l];
+    btot += m->n_pad[l];
+  }
+  bool ok = hipMalloc(&m->wpack, sizeof(__bf16) * wtot) == hipSuccess &&
+            hipMalloc(&m->bpack, sizeof(float) * btot) == hipSuccess &&
+            hipMalloc(&m->params, sizeof(float) * off) == hipSuccess &&
             hipMalloc(&m->grads, sizeof(float) * off) == hipSuccess &&
             hipMalloc(&m->adam_m, sizeof(float) * off) == hipSuccess &&
             hipMalloc(&m->adam_v, sizeof(float) * off) == hipSuccess &&
@@ -500,6 +706,7 @@ int mgrhd_mlp_get_params(const mgrhd_mlp* m, float* host, int32_t which) {
 
 int mgrhd_mlp_set_params(mgrhd_mlp* m, const float* host) {
   if (!m || !host) return MGRHD_E_NULL;
+  m->dirty = true;
   return hipMemcpy(m->params, host, sizeof(float) * m->n_params, hipMemcpyHostToDevice) ==
                  hipSuccess
              ? 0 : MGRHD_E_DEVICE;
@@ -535,6 +742,7 @@ int mgrhd_mlp_adam_step(mgrhd_mlp* m, float lr, mgrhd_stream_t stream) {
   if (!m) return MGRHD_E_NULL;
   hipStream_t s = (hipStream_t)stream;
   m->step += 1;
+  m->dirty = true;
   const float b1 = 0.9f, b2 = 0.999f;
   const float c1 = 1.f - std::pow(b1, (float)m->step), c2 = 1.f - std::pow(b2, (float)m->step);
   hipLaunchKernelGGL(k_adam, grid1(m->n_params), dim3(256), 0, s, m->params, m->grads, m->adam_m,
@@ -629,6 +837,69 @@ int mgrhd_mlp_guess(const double* E_g, const double* F_g, const double* rho, con
   return e == hipSuccess ? 0 : (int)e;
 }
 
+int mgrhd_mlp_infer(mgrhd_mlp* m, const double* E_g, const double* F_g, const double* rho,
+                    const double* e_gas, const double* v, int64_t n, const double* group_edges,
+                    const mgrhd_opacity_params* op, double dt, double c_hat,
+                    const mgrhd_options* opt, const float* x_mean, const float* x_istd,
+                    const float* y_mean, const float* y_std, int32_t guess_kind, double* guess,
+                    mgrhd_stream_t stream) {
+  if (!m) return MGRHD_E_NULL;
+  PhysArgs p;
+  int rc = phys_args(p, E_g, F_g, rho, e_gas, v, n, group_edges, op, dt, c_hat, opt);
+  if (rc) return rc;
+  if (!x_mean || !x_istd || !y_mean || !y_std || !guess) return MGRHD_E_NULL;
+  if (guess_kind < 0 || guess_kind > 1) return MGRHD_E_OPTION;
+  if (m->n_hidden != kHidden || m->n_in != 2 + 3 * p.ng || m->n_out != 1 + p.ng ||
+      m->k_pad[0] > kMaxKin)
+    return MGRHD_E_SIZE;
+  if (n == 0) return 0;
+  hipStream_t s = (hipStream_t)stream;
+  if (m->dirty) {
+    for (int l = 0; l < 4; ++l)
+      hipLaunchKernelGGL(k_pack, grid1((int64_t)m->n_pad[l] * m->k_pad[l]), dim3(256), 0, s,
+                         m->params + m->w_off[l], m->params + m->b_off[l], m->out_dim[l],
+                         m->in_dim[l], m->n_pad[l], m->k_pad[l], m->wpack + m->wp_off[l],
+                         m->bpack + m->bp_off[l]);
+    m->dirty = false;
+  }
+  InferArgs q;
+  q.p = p;
+  q.xmean = x_mean;
+  q.xistd = x_istd;
+  q.ymean = y_mean;
+  q.ystd = y_std;
+  for (int l = 0; l < 4; ++l) {
+    q.W[l] = m->wpack + m->wp_off[l];
+    q.b[l] = m->bpack + m->bp_off[l];
+    q.K_pad[l] = m->k_pad[l];
+    q.N_pad[l] = m->n_pad[l];
+  }
+  q.n_in = m->n_in;
+  q.n_out = m->n_out;
+  q.kind = guess_kind;
+  q.S = opt ? opt->S_g : nullptr;
+  q.guess = guess;
+  const int ldx = m->k_pad[0] + 8;
+  const size_t lds = sizeof(__bf16) * (size_t)kTile * ((ldx > kHPad ? ldx : kHPad) + kHPad) +
+                     sizeof(float) * (size_t)p.ng;
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    cus = (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+              ? prop.multiProcessorCount : 256;
+    // the input tile of 138 groups needs more than the default 64 KB of LDS
+    if (hipFuncSetAttribute((const void*)k_infer, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            96 * 1024) != hipSuccess)
+      return MGRHD_E_DEVICE;
+  }
+  const int64_t tiles = (n + kTile - 1) / kTile;
+  const int64_t blocks = tiles < (int64_t)cus * 4 ? tiles : (int64_t)cus * 4;
+  hipLaunchKernelGGL(k_infer, dim3((unsigned)blocks), dim3(256), lds, s, q);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : (int)e;
+}
+
 // plain product C = op(A) op(B) through the BF16 MFMA kernel (exposed for tests)
 int mgrhd_mlp_gemm(const float* A, int32_t lda, int32_t trans_a, const float* B, int32_t ldb,
                    int32_t trans_b, float* C, int32_t ldc, int64_t M, int32_t N, int32_t K,
@@ -657,6 +928,8 @@ void mgrhd_mlp_destroy(mgrhd_mlp* m) {
   if (m->adam_v) (void)hipFree(m->adam_v);
   if (m->act) (void)hipFree(m->act);
   if (m->loss) (void)hipFree(m->loss);
+  if (m->wpack) (void)hipFree(m->wpack);
+  if (m->bpack) (void)hipFree(m->bpack);
   delete m;
 }
 

@@ -53,6 +53,8 @@ def _lib():
         L.mgrhd_mlp_targets.argtypes = phys + [vp, vp, vp, vp, vp]
         L.mgrhd_mlp_guess.restype = C.c_int
         L.mgrhd_mlp_guess.argtypes = phys + [vp, vp, vp, i32, vp, vp]
+        L.mgrhd_mlp_infer.restype = C.c_int
+        L.mgrhd_mlp_infer.argtypes = [vp] + phys + [vp, vp, vp, vp, i32, vp, vp]
         L.mgrhd_mlp_gemm.restype = C.c_int
         L.mgrhd_mlp_gemm.argtypes = [vp, i32, i32, vp, i32, i32, vp, i32, i64, i32, i32, vp]
         L.mgrhd_mlp_destroy.restype = None
@@ -218,10 +220,25 @@ class WarmStart:
     y_std: torch.Tensor
     history: list
 
-    def guess(self, state, tables, kappa, consts, S_g=None, kind=1):
-        X = features(state, tables, kappa, consts, self.x_mean, self.x_istd)
-        Yn = self.net.forward(X)
-        return guess_from(state, tables, kappa, consts, Yn, self.y_mean, self.y_std, S_g, kind)
+    def guess(self, state, tables, kappa, consts, S_g=None, kind=1, fused=True):
+        """Newton guess for the cells of `state`: kind 1 E_gas [n], kind 0
+        [N_g+1, n].  fused: one kernel (mgrhd_mlp_infer); else features,
+        forward and guess as three steps."""
+        if not fused:
+            X = features(state, tables, kappa, consts, self.x_mean, self.x_istd)
+            Yn = self.net.forward(X)
+            return guess_from(state, tables, kappa, consts, Yn, self.y_mean, self.y_std, S_g,
+                              kind)
+        ng, n = state["E_g"].shape
+        shape = (n,) if kind == 1 else (ng + 1, n)
+        g = torch.empty(shape, dtype=torch.float64, device=state["E_g"].device)
+        args, keep = _phys(state, tables, kappa, consts, S_g)
+        _check(_lib().mgrhd_mlp_infer(self.net._h, *args, _f32(self.x_mean, "x_mean"),
+                                      _f32(self.x_istd, "x_istd"), _f32(self.y_mean, "y_mean"),
+                                      _f32(self.y_std, "y_std"), int(kind), g.data_ptr(),
+                                      torch.cuda.current_stream().cuda_stream),
+               "mgrhd_mlp_infer")
+        return g
 
     def save(self, path):
         np.savez(path, params=self.net.get_params(), x_mean=self.x_mean.cpu().numpy(),

@@ -84,6 +84,36 @@ def test_training_reduces_loss_on_a_smooth_map():
     assert final < 0.1 * first, (first, final)
 
 
+@pytest.mark.parametrize("n", [1000, 4096 + 17])
+def test_fused_inference_matches_three_kernel_path(n):
+    """mgrhd_mlp_infer (features, layers and guess in one kernel) against the
+    three-kernel path (features, matrix-core forward, guess) on a random
+    network with the 64-group feature layout: both guess kinds, ragged tile."""
+    dw = synth.device_workload("config2", n=n)
+    ng = dw.ng
+    net = warmstart.MLP(2 + 3 * ng, 1 + ng, 128, max_rows=2048, seed=5)
+    rng = np.random.default_rng(1)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+    Xr = warmstart.features(dw.state, dw.tables, dw.kappa, dw.consts(),
+                            torch.zeros(2 + 3 * ng, device="cuda"),
+                            torch.ones(2 + 3 * ng, device="cuda"))
+    x_mean, x_std = Xr.mean(1), Xr.std(1).clamp_min(1e-3)
+    ws = warmstart.WarmStart(net, x_mean.contiguous(), (1.0 / x_std).contiguous(),
+                             t(rng.normal(0, 0.1, 1 + ng)), t(np.full(1 + ng, 0.05)), [])
+    for kind in (1, 0):
+        a = ws.guess(dw.state, dw.tables, dw.kappa, dw.consts(), kind=kind, fused=True)
+        b = ws.guess(dw.state, dw.tables, dw.kappa, dw.consts(), kind=kind, fused=False)
+        torch.cuda.synchronize()
+        a, b = a.cpu().numpy(), b.cpu().numpy()
+        assert np.isfinite(a).all()
+        e0 = np.abs(a.reshape(-1, n)[0] - b.reshape(-1, n)[0]) / np.abs(b.reshape(-1, n)[0])
+        assert e0.max() < 5e-3, (kind, e0.max())          # BF16 products, FP32 features
+        if kind == 0:
+            E0 = dw.state["E_g"].cpu().numpy()
+            ra, rb = a[1:] + E0, b[1:] + E0                     # the guessed E_g
+            assert (np.abs(ra - rb) <= 5e-3 * np.abs(rb) + 1e-300).all()
+
+
 def test_warm_start_same_result_fewer_iterations():
     """Train on solver-generated pairs of the 64-group workload (training
     seed), then solve fresh cells of the workload itself with and without the
