@@ -72,8 +72,9 @@ __device__ __forceinline__ bool stage_tables_wave(const KArgs& a, Tables<kBatchN
 template <int G, int MODE>
 __global__ __launch_bounds__(kBlock, 2) void k_batch(BatchArgs b) {
   __shared__ Tables<kBatchNGM> tabs[kBlock / kWave];
-  __shared__ double lane_lds[LaneStore<G>::kSlots * kBlock];
-  const LaneStore<G> ls{lane_lds + threadIdx.x};
+  using LS = LaneStore<G, false>;
+  __shared__ double lane_lds[LS::kSlots * kBlock];
+  const LS ls{lane_lds + threadIdx.x};
   const int lane = threadIdx.x % kWave;
   Tables<kBatchNGM>& tab = tabs[threadIdx.x / kWave];
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));

@@ -210,17 +210,24 @@ __device__ __forceinline__ bool stage_tables(const KArgs& a, Tables<NGM>& t) {
 }
 
 // Per-lane values held in LDS instead of registers: the fluxes F_k of the
-// lane's groups during the outer iteration (3G) and, in PC and PPL-fixed, the
+// lane's groups during the outer iteration (3G), in PC and PPL-fixed the
 // per-cell constants 1/tau_g = 1/(c_hat dt chi_0E,g) and 1/J_gg of eq. matrix
-// (2G).  Slot s of thread t lives at lds[s * kBlock + t]: the 64 lanes of a
-// wave touch 64 consecutive words, free of bank conflicts.
-template <int G>
+// (2G), and with KEEP0 the old-time fluxes F^(t) (3G) and velocity v^(t) (3)
+// that every outer stage needs (without KEEP0 they are re-read from HBM).
+// Slot s of thread t lives at lds[s * kBlock + t]: the 64 lanes of a wave
+// touch 64 consecutive words, free of bank conflicts.
+template <int G, bool KEEP0>
 struct LaneStore {
-  static constexpr int kSlots = 5 * G;
+  static constexpr bool kKeep0 = KEEP0;
+  static constexpr int kSlots = 5 * G + (KEEP0 ? 3 * G + 3 : 0);
   double* base;  // &lds[threadIdx.x]
   __device__ __forceinline__ double& F(int d, int k) const { return base[(d * G + k) * kBlock]; }
   __device__ __forceinline__ double& itau(int k) const { return base[(3 * G + k) * kBlock]; }
   __device__ __forceinline__ double& iJgg(int k) const { return base[(4 * G + k) * kBlock]; }
+  __device__ __forceinline__ double& F0(int d, int k) const {
+    return base[(5 * G + d * G + k) * kBlock];
+  }
+  __device__ __forceinline__ double& v0(int d) const { return base[(8 * G + d) * kBlock]; }
 };
 
 // Material data of this lane's groups at one temperature.
@@ -407,9 +414,9 @@ struct CellState {
   double vF[G];        // v_k . F_g,k of the current outer pass
 };
 
-template <int G, int LPC, int MODE, int NGM>
+template <int G, int LPC, int MODE, int NGM, class LS>
 __device__ __forceinline__ void load_cell(const KArgs& a, const Tables<NGM>& t, int j, int64_t i,
-                                          CellState<G>& s, const LaneStore<G>& ls) {
+                                          CellState<G>& s, const LS& ls) {
   const int64_t n = a.n;
   const int ng = a.ng;
   s.i = i;
@@ -428,6 +435,10 @@ __device__ __forceinline__ void load_cell(const KArgs& a, const Tables<NGM>& t, 
             isfinite(s.v[0]) && isfinite(s.v[1]) && isfinite(s.v[2]);
   s.rho_kappa = s.rho * kap;
   s.ircv = 1.0 / (s.rho * a.cv);
+  if (LS::kKeep0) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) ls.v0(d) = s.v[d];
+  }
   const double cdt = a.cdt;
   double sumE = 0.0;
 #pragma unroll
@@ -456,7 +467,10 @@ __device__ __forceinline__ void load_cell(const KArgs& a, const Tables<NGM>& t, 
       }
     }
 #pragma unroll
-    for (int d = 0; d < 3; ++d) ls.F(d, k) = f[d];
+    for (int d = 0; d < 3; ++d) {
+      ls.F(d, k) = f[d];
+      if (LS::kKeep0) ls.F0(d, k) = f[d];
+    }
     if (MODE != MGRHD_MEAN_PPL_FREE) {
       ls.itau(k) = it;
       ls.iJgg(k) = ij;
@@ -492,9 +506,9 @@ __device__ __forceinline__ void load_cell(const KArgs& a, const Tables<NGM>& t, 
   }
 }
 
-template <int G, int LPC>
+template <int G, int LPC, class LS>
 __device__ __forceinline__ void finish_cell(const KArgs& a, int j, CellState<G>& s,
-                                            const LaneStore<G>& ls, bool store) {
+                                            const LS& ls, bool store) {
   const int64_t n = a.n, i = s.i;
   const int ng = a.ng;
   if (store) {
@@ -537,9 +551,9 @@ __device__ __forceinline__ void finish_cell(const KArgs& a, int j, CellState<G>&
 }
 
 // End of an inner pass with result rc (0 converged, 1 max_newton, 2 T <= 0).
-template <int G, int LPC>
+template <int G, int LPC, class LS>
 __device__ __forceinline__ void newton_done(const KArgs& a, int j, CellState<G>& s,
-                                            const LaneStore<G>& ls, int rc) {
+                                            const LS& ls, int rc) {
   if (s.k_out == 0 && s.warm && rc != 0 && !s.fell_back) {
     // warm start failed: plain Newton from the old state (status bit 4)
     s.st |= MGRHD_ST_FALLBACK;
@@ -568,9 +582,9 @@ __device__ __forceinline__ void newton_done(const KArgs& a, int j, CellState<G>&
 
 // Temperature-only start: at the cached material state, eq. Rnew inverted for
 // E_g and F_R,g = 0 (eq. FGFR) are linear in R_g alone; take that R_g.
-template <int G, int LPC, int MODE, int NGM>
+template <int G, int LPC, int MODE, int NGM, class LS>
 __device__ __forceinline__ void group_balance(const KArgs& a, const Tables<NGM>& t, int j,
-                                              CellState<G>& s, const LaneStore<G>& ls,
+                                              CellState<G>& s, const LS& ls,
                                               const Cache<G>& c) {
   const int ng = a.ng;
   const double cdt = a.cdt;
@@ -594,9 +608,9 @@ __device__ __forceinline__ void group_balance(const KArgs& a, const Tables<NGM>&
 
 // Newton consumer: residual of eq. FGFR at the cached material state, the
 // elimination of eq. matrix, and the step.
-template <int G, int LPC, int MODE, int NGM>
+template <int G, int LPC, int MODE, int NGM, class LS>
 __device__ __forceinline__ void newton_step(const KArgs& a, const Tables<NGM>& t, int j,
-                                            CellState<G>& s, const LaneStore<G>& ls,
+                                            CellState<G>& s, const LS& ls,
                                             const Cache<G>& c) {
   const int ng = a.ng;
   const double cc = a.cc;
@@ -667,9 +681,9 @@ __device__ __forceinline__ void newton_step(const KArgs& a, const Tables<NGM>& t
 // Outer-stage consumer: flux update eq. numF1 with the outdated velocity,
 // momentum update, outer test.  Returns true when the next inner pass starts
 // (at the same temperature, so the caller reuses this evaluation).
-template <int G, int LPC, int MODE, int NGM>
+template <int G, int LPC, int MODE, int NGM, class LS>
 __device__ __forceinline__ bool flux_step(const KArgs& a, const Tables<NGM>& t, int j,
-                                          CellState<G>& s, const LaneStore<G>& ls,
+                                          CellState<G>& s, const LS& ls,
                                           const Cache<G>& c) {
   const int ng = a.ng;
   const int64_t n = a.n, i = s.i;
@@ -687,7 +701,7 @@ __device__ __forceinline__ bool flux_step(const KArgs& a, const Tables<NGM>& t, 
     const double q = (1.0 + t.achi[g]) * chE;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      const double f0 = a.F[((int64_t)d * ng + g) * n + i];  // F_g^(t)
+      const double f0 = LS::kKeep0 ? ls.F0(d, k) : a.F[((int64_t)d * ng + g) * n + i];  // F_g^(t)
       const double f = (f0 + cdt * (s.v[d] * c.emit[k] + q * Pv[d])) * iden;
       ls.F(d, k) = f;  // F_k+1 replaces F_k (v_k . F_k stays in s.vF)
       dmom[d] += f - f0;
@@ -699,7 +713,8 @@ __device__ __forceinline__ bool flux_step(const KArgs& a, const Tables<NGM>& t, 
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     dmom[d] = cell_sum<LPC>(dmom[d], s.lpc);
-    vn[d] = (s.rho * a.v[(int64_t)d * n + i] - dmom[d] * ccc) * irho;  // momentum update
+    const double v0 = LS::kKeep0 ? ls.v0(d) : a.v[(int64_t)d * n + i];  // v^(t)
+    vn[d] = (s.rho * v0 - dmom[d] * ccc) * irho;  // momentum update
   }
   double dW = 0.0;
 #pragma unroll

@@ -42,8 +42,9 @@ __global__ __launch_bounds__(kBlock, WPE) void k_source_update(KArgs a) {
   constexpr int NGM = G * LPC;
   constexpr int kGroupsPerWave = kWave / LPC;
   __shared__ Tables<NGM> tab;
-  __shared__ double lane_lds[LaneStore<G>::kSlots * kBlock];
-  const LaneStore<G> ls{lane_lds + threadIdx.x};
+  using LS = LaneStore<G, true>;
+  __shared__ double lane_lds[LS::kSlots * kBlock];
+  const LS ls{lane_lds + threadIdx.x};
   const bool table_ok = stage_tables<NGM, MODE>(a, tab);
 
   const int lane = threadIdx.x % kWave;
