@@ -246,7 +246,10 @@ void mgrhd_batch_destroy(mgrhd_batch* b);
  * Features (n_in = 2 + 3 N_g): ln T, ln rho, ln(E_g/a T^4), |F_g|/(c E_g),
  * ln(c_hat dt chi_0E,g); outputs (n_out = 1 + N_g): ln(T_new/T),
  * ln(E_g,new/a T^4).  The handle owns its device buffers (allocated once in
- * create for up to max_rows rows per call). */
+ * create for up to max_rows rows per call).  n_hidden and n_out are at most
+ * 256 (MGRHD_E_SIZE otherwise).  Weight gradients are summed over row blocks
+ * with atomic adds, so gradients (and training) agree between runs to
+ * rounding, not bit for bit. */
 typedef struct mgrhd_mlp mgrhd_mlp;
 int mgrhd_mlp_create(int32_t n_in, int32_t n_hidden, int32_t n_out, int64_t max_rows,
                      uint64_t seed, mgrhd_mlp** out);

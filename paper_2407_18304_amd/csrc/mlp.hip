@@ -33,7 +33,7 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 constexpr int BM = 64, BN = 64, BK = 32;
 constexpr int LDK = BK + 8;  // LDS row pitch in bf16 (80 bytes: 16-byte aligned, skewed banks)
 
-enum Epi : int { EPI_NONE = 0, EPI_BIAS = 1, EPI_BIAS_SILU = 2 };
+enum Epi : int { EPI_NONE = 0, EPI_BIAS = 1, EPI_BIAS_SILU = 2, EPI_ATOMIC = 3 };
 
 // C[M x N] = op(A)[M x K] op(B)[K x N] (+ bias[N]) (SiLU, keeping the
 // pre-activation in Z).  op(A) = A (row-major, lda) or A^T (A stored K x M);
@@ -57,7 +57,11 @@ __global__ __launch_bounds__(256) void k_gemm(const float* __restrict__ A, int l
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  for (int k0 = 0; k0 < K; k0 += BK) {
+  // split-K (EPI_ATOMIC): block z reduces K range [z Kc, (z+1) Kc) and adds into C
+  const int Kc = (EPI == EPI_ATOMIC) ? (((K + gridDim.z - 1) / gridDim.z + BK - 1) / BK) * BK : K;
+  const int kbeg = (EPI == EPI_ATOMIC) ? (int)blockIdx.z * Kc : 0;
+  const int kend = (EPI == EPI_ATOMIC) ? min(K, kbeg + Kc) : K;
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
     // stage A tile (BM x BK) and B tile (BK x BN) as bf16, k contiguous
 #pragma unroll
     for (int r = 0; r < (BM * BK) / 256; ++r) {
@@ -73,7 +77,7 @@ __global__ __launch_bounds__(256) void k_gemm(const float* __restrict__ A, int l
       const int64_t gm = m0 + mm;
       const int gk = k0 + kk;
       float x = 0.f;
-      if (gm < M && gk < K) x = TA ? A[(int64_t)gk * lda + gm] : A[gm * lda + gk];
+      if (gm < M && gk < kend) x = TA ? A[(int64_t)gk * lda + gm] : A[gm * lda + gk];
       As[mm][kk] = (__bf16)x;
     }
 #pragma unroll
@@ -89,7 +93,7 @@ __global__ __launch_bounds__(256) void k_gemm(const float* __restrict__ A, int l
       }
       const int gn = n0 + nn, gk = k0 + kk;
       float x = 0.f;
-      if (gn < N && gk < K) x = TB ? B[(int64_t)gn * ldb + gk] : B[(int64_t)gk * ldb + gn];
+      if (gn < N && gk < kend) x = TB ? B[(int64_t)gn * ldb + gk] : B[(int64_t)gk * ldb + gn];
       Bs[nn][kk] = (__bf16)x;
     }
     __syncthreads();
@@ -114,7 +118,7 @@ __global__ __launch_bounds__(256) void k_gemm(const float* __restrict__ A, int l
     for (int b = 0; b < 2; ++b) {
       const int n = n0 + wn + 16 * b + col16;
       if (n >= N) continue;
-      const float bv = (EPI != EPI_NONE) ? bias[n] : 0.f;
+      const float bv = (EPI == EPI_BIAS || EPI == EPI_BIAS_SILU) ? bias[n] : 0.f;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int64_t m = m0 + wm + 16 * a + row4 + i;
@@ -124,7 +128,10 @@ __global__ __launch_bounds__(256) void k_gemm(const float* __restrict__ A, int l
           if (Z) Z[m * ldc + n] = z;  // pre-activation, kept for the backward pass
           z = z / (1.f + expf(-z));
         }
-        C[m * ldc + n] = z;
+        if (EPI == EPI_ATOMIC)
+          atomicAdd(&C[m * ldc + n], z);
+        else
+          C[m * ldc + n] = z;
       }
     }
 }
@@ -140,13 +147,16 @@ __global__ void k_silu_bwd(const float* __restrict__ dH, const float* __restrict
   }
 }
 
-// column sums of a row-major [rows x N] matrix (bias gradients), one thread per column
+// column sums of a row-major [rows x N] matrix (bias gradients) added into
+// out (cleared before): block b sums rows [256 b, 256 b + 256), thread n
+// column n (N <= 256)
 __global__ void k_colsum(const float* __restrict__ X, int64_t rows, int N, float* __restrict__ out) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = threadIdx.x;
   if (n >= N) return;
+  const int64_t r0 = (int64_t)blockIdx.x * 256, r1 = min(rows, r0 + 256);
   float s = 0.f;
-  for (int64_t r = 0; r < rows; ++r) s += X[r * N + n];
-  out[n] = s;
+  for (int64_t r = r0; r < r1; ++r) s += X[r * N + n];
+  atomicAdd(&out[n], s);
 }
 
 // mean-squared error: dY = 2 (Y - T) / (rows * N), loss = mean (Y - T)^2
@@ -539,8 +549,8 @@ static inline dim3 grid1(int64_t n) {
 
 template <bool TA, bool TB, int EPI>
 static void gemm(hipStream_t s, const float* A, int lda, const float* B, int ldb, const float* bias,
-                 float* C, int ldc, float* Z, int64_t M, int N, int K) {
-  dim3 grid((unsigned)((M + BM - 1) / BM), (unsigned)((N + BN - 1) / BN));
+                 float* C, int ldc, float* Z, int64_t M, int N, int K, int splits = 1) {
+  dim3 grid((unsigned)((M + BM - 1) / BM), (unsigned)((N + BN - 1) / BN), (unsigned)splits);
   hipLaunchKernelGGL((k_gemm<TA, TB, EPI>), grid, dim3(256), 0, s, A, lda, B, ldb, bias, C, ldc, Z,
                      M, N, K);
 }
@@ -575,6 +585,10 @@ static void backward(mgrhd_mlp* m, hipStream_t s, const float* X_fm, int64_t ld_
   hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, s, m->loss, (int64_t)1);
   hipLaunchKernelGGL(k_mse, grid1(ny), dim3(256), 0, s, m->Y, Tgt, ny, 1.f / (float)ny, m->dY,
                      m->loss);
+  // the weight and bias gradients are accumulated (split over rows): clear them
+  hipLaunchKernelGGL(k_zero, grid1(m->n_params), dim3(256), 0, s, m->grads, m->n_params);
+  // rows per split of the weight-gradient products: enough blocks to fill the chip
+  const int splits = (int)std::max<int64_t>(1, std::min<int64_t>(64, rows / 256));
   const float* dOut = m->dY;  // gradient w.r.t. the current layer's output (pre-activation for l=3)
   for (int l = 3; l >= 0; --l) {
     const int no = m->out_dim[l], ni = m->in_dim[l];
@@ -582,12 +596,13 @@ static void backward(mgrhd_mlp* m, hipStream_t s, const float* X_fm, int64_t ld_
     float* db = m->grads + m->b_off[l];
     // dW = dOut^T [no x rows] . input [rows x ni]
     if (l == 0)  // input X feature-major: op(B) = (X_fm)^T, stored ni x ld_x
-      gemm<true, true, EPI_NONE>(s, dOut, no, X_fm, (int)ld_x, nullptr, dW, ni, nullptr, no, ni,
-                                 (int)rows);
+      gemm<true, true, EPI_ATOMIC>(s, dOut, no, X_fm, (int)ld_x, nullptr, dW, ni, nullptr, no,
+                                   ni, (int)rows, splits);
     else
-      gemm<true, false, EPI_NONE>(s, dOut, no, m->H[l - 1], ni, nullptr, dW, ni, nullptr, no, ni,
-                                  (int)rows);
-    hipLaunchKernelGGL(k_colsum, dim3((no + 127) / 128), dim3(128), 0, s, dOut, rows, no, db);
+      gemm<true, false, EPI_ATOMIC>(s, dOut, no, m->H[l - 1], ni, nullptr, dW, ni, nullptr, no,
+                                    ni, (int)rows, splits);
+    hipLaunchKernelGGL(k_colsum, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, dOut,
+                       rows, no, db);
     if (l == 0) break;
     // dH_{l-1} = dOut [rows x no] . W_l [no x ni]; then through SiLU
     float* dH = m->dA;
@@ -608,6 +623,7 @@ int mgrhd_mlp_create(int32_t n_in, int32_t n_hidden, int32_t n_out, int64_t max_
   if (!out) return MGRHD_E_NULL;
   *out = nullptr;
   if (n_in < 1 || n_hidden < 1 || n_out < 1 || max_rows < 1) return MGRHD_E_SIZE;
+  if (n_hidden > 256 || n_out > 256) return MGRHD_E_SIZE;  // bias-gradient kernel width
   mgrhd_mlp* m = new (std::nothrow) mgrhd_mlp();
   if (!m) return MGRHD_E_DEVICE;
   m->n_in = n_in;
