@@ -79,6 +79,33 @@ __host__ __device__ __forceinline__ Edge planck_edge(double x) {
   return e;
 }
 
+// The same edge data for small x (the lowest edge of a group structure):
+// for x <= kLowEdge the polynomials truncated to degree kLowDeg in y = x^2
+// reach the accuracy of the full ones (relative error below 2e-16), at a
+// quarter of the work.  Falls back to planck_edge above kLowEdge.
+constexpr double kLowEdge = 0.1;
+constexpr int kLowDeg = 3;
+
+__host__ __device__ __forceinline__ Edge planck_edge_low(double x) {
+  if (!(x <= kLowEdge)) return planck_edge(x);
+  Edge e;
+  e.x = x;
+  e.inf = false;
+  e.wien = false;
+  e.u = 1.0;
+  const double y = x * x;
+  const double x3 = y * x;
+  double ap = planck_ap(kLowDeg), ep = planck_ep(kLowDeg);
+#pragma unroll
+  for (int k = kLowDeg - 1; k >= 0; --k) {
+    ap = fma(ap, y, planck_ap(k));
+    ep = fma(ep, y, planck_ep(k));
+  }
+  e.val = kC15 * x3 * ((1.0 / 3.0 - 0.125 * x) + ap * y);
+  e.eps = kC15 * x3 * ((1.0 - 0.5 * x) + ep * y);
+  return e;
+}
+
 // Group data from its two edges:
 //   b      group fraction, times e^{sigma}
 //   elo    edge term at nu_g-, times e^{sigma}

@@ -291,7 +291,7 @@ __device__ __forceinline__ void evaluate(const Tables<NGM>& t, int ng, int j, in
   const double hkT = hk * invT;
   Edge prev;
   prev.x = prev.u = prev.val = prev.eps = 0.0;
-  if (j == n - 1) prev = planck_edge(hkT * t.nu[0]);  // edge 0, handed to lane 0
+  if (j == n - 1) prev = planck_edge_low(hkT * t.nu[0]);  // edge 0, handed to lane 0
   if (MODE != MGRHD_MEAN_PPL_FREE) {
 #pragma unroll
     for (int k = 0; k < G; ++k) {

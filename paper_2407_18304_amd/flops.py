@@ -51,6 +51,8 @@ def unit_costs(w=W):
         "x<=2": edge_common + poly_P + poly_E,
         "2<x<=4": edge_common + poly_P + poly_E,
         "x>4": edge_common + e + 2 + (10 * 6 + 9 * 2) + 1 + (3 + dv),  # 10-term tail
+        # the lowest edge at x <= 0.1: both polynomials truncated to degree 3
+        "low": edge_common + 2 * (3 * 2 + 6),
     }
     # group data from its two edges (group_planck)
     group = {"both<=4": 1, "straddle": 4, "wien": 3 + dv}
@@ -102,7 +104,8 @@ def edge_mix(nu, hk, T):
     g_wien = xp.clip(ng - n4, 0, None) if xp is np else (ng - n4).clamp(min=0)
     g_strad = ((n4 >= 1) & (n4 <= ng)) * 1
     g_both = ng - g_wien - g_strad
-    return e_le2, e_24, e_gt4, g_both, g_strad, g_wien
+    low0 = (nu_t[0] * hk / T <= 0.1) * 1     # the lowest edge takes the short path
+    return e_le2, e_24, e_gt4, g_both, g_strad, g_wien, low0
 
 
 def _xp(a):
@@ -118,12 +121,13 @@ def _searchsorted(xp, sorted_seq, v):
 def flops_per_cell(ng, mode, iters, outer, mix, u=UNIT, valid=None):
     """FLOP-equivalents per cell (array).  iters, outer: the kernel's per-cell
     counters; mix: edge_mix(...) of the cell's final temperature."""
-    e_le2, e_24, e_gt4, g_both, g_strad, g_wien = mix
+    e_le2, e_24, e_gt4, g_both, g_strad, g_wien, low0 = mix
     E = u["edge"]
     G = u["group"]
     per_eval = (e_le2 * E["x<=2"] + e_24 * E["2<x<=4"] + e_gt4 * E["x>4"] +
                 g_both * G["both<=4"] + g_strad * G["straddle"] + g_wien * G["wien"] +
-                ng * u["ev_group"][mode] + u["ev_cell"])
+                ng * u["ev_group"][mode] + u["ev_cell"] -
+                low0 * (E["x<=2"] - E["low"]))
     n_eval = iters + outer + 1
     n_newton = iters + outer
     f = (n_eval * per_eval + n_newton * (ng * u["nt_group"][mode] + u["nt_cell"]) +

@@ -10,6 +10,13 @@ void dm_edge(double x, double* out) {
   out[2] = e.u;
   out[3] = e.wien ? 1.0 : 0.0;
 }
+void dm_edge_low(double x, double* out) {
+  const mgrhd::Edge e = mgrhd::planck_edge_low(x);
+  out[0] = e.val;
+  out[1] = e.eps;
+  out[2] = e.u;
+  out[3] = e.wien ? 1.0 : 0.0;
+}
 void dm_group(double xl, double xh, double* out) {
   const mgrhd::GroupPlanck p = mgrhd::group_planck(mgrhd::planck_edge(xl), mgrhd::planck_edge(xh));
   out[0] = p.b;

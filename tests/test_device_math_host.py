@@ -28,6 +28,7 @@ def dm(tmp_path_factory):
     L = C.CDLL(out)
     dp = C.POINTER(C.c_double)
     L.dm_edge.argtypes = [C.c_double, dp]
+    L.dm_edge_low.argtypes = [C.c_double, dp]
     L.dm_group.argtypes = [C.c_double, C.c_double, dp]
     L.dm_mean_ratio.restype = C.c_double
     L.dm_mean_ratio.argtypes = [C.c_double, C.c_double, C.c_double]
@@ -80,3 +81,18 @@ def test_mean_ratio(dm, ac, aq, L):
     den = mp.quad(lambda u: mp.exp((aq + 1) * u), [0, L])
     ref = num / den
     assert abs(dm.dm_mean_ratio(ac, aq, L) - ref) <= 1e-13 * ref
+
+
+@pytest.mark.parametrize("x", [0.0, 1e-8, 1e-3, 0.01, 0.033, 0.0999, 0.1, 0.2, 3.0, 9.0])
+def test_low_edge_matches_full_edge(dm, x):
+    """The lowest-edge shortcut (truncated polynomials below x = 0.1, the full
+    evaluation above) agrees with mpmath like the full edge."""
+    val, eps, u, wien = _call(dm.dm_edge_low, x, n=4)
+    full = _call(dm.dm_edge, x, n=4)
+    if x > 0.1:
+        assert (val, eps, u, wien) == tuple(full)
+        return
+    assert wien == 0.0 and u == 1.0
+    p = 1 - mp_ref.Q_polylog(x) if x > 0 else 0
+    assert abs(val - p) <= 1e-15 * p + 1e-300
+    assert abs(eps - mp_ref.edge_term(x)) <= 1e-15 * mp_ref.edge_term(x) + 1e-300

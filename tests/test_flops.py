@@ -37,7 +37,9 @@ def test_flops_bookkeeping():
     ev = (mix[0][0] * u["edge"]["x<=2"] + mix[1][0] * u["edge"]["2<x<=4"] +
           mix[2][0] * u["edge"]["x>4"] + mix[3][0] * u["group"]["both<=4"] +
           mix[4][0] * u["group"]["straddle"] + mix[5][0] * u["group"]["wien"] +
-          64 * u["ev_group"][F.FIXED] + u["ev_cell"])
+          64 * u["ev_group"][F.FIXED] + u["ev_cell"] -
+          mix[6][0] * (u["edge"]["x<=2"] - u["edge"]["low"]))
+    assert mix[6][0] == 1                     # x = 1e-3 at T = 1: the short path
     nt = 64 * u["nt_group"][F.FIXED] + u["nt_cell"]
     assert f[1] - f[0] == pytest.approx(ev + nt)
     # one more pass adds an evaluation, a Newton step (its polish) and a flux update
