@@ -31,6 +31,33 @@ PEAK_HBM = 8.0e12            # bytes/s
 PEAK_FP64 = 78.6e12          # FP64 vector FLOP/s
 
 
+def kernel_source_sha() -> str:
+    """Hash of the kernel sources (csrc/*.hip, *.hpp, *.inc): a measured HBM
+    traffic is reported only for the sources it was measured on."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2407_18304_amd", "csrc", "*"))):
+        if f.endswith((".hip", ".hpp", ".inc")):
+            h.update(os.path.basename(f).encode())
+            h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` on `workload` from the rocprofv3 PMC
+    summary in profiles/traffic.json (FETCH_SIZE and WRITE_SIZE, each scaled
+    by the same counter on a plain copy of known size), or None when there is
+    none or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(workload)
+    if not rec or rec.get("source_sha") != kernel_source_sha() or rec.get("kernel") != kernel:
+        return None
+    return rec["traffic_bytes"]
+
+
 def bytes_per_cell(ng: int) -> int:
     """Algorithmic HBM bytes per cell-update: E_g, F_g, E_gas, v read and
     written (8(4 N_g + 4) each way), rho and the opacity scale read (16), and
@@ -155,11 +182,14 @@ def main():
     # the binding ceiling is the lower of the two for this workload
     ceil_alu = PEAK_FP64 / (flop / n)
     ceil_hbm = PEAK_HBM / bpc
+    lpc_, g_, w_ = mgrhd.get_variant(ng, args.mode)
+    kname = f"k_source_update<{g_}, {lpc_}, {args.mode}, {w_}>"
+    traffic = None if (args.warm or args.cells or args.mode != 1) else measured_traffic(name, kname)
     roof_alu = {"bound": "alu", "achieved": achieved_fl / 1e12, "peak": PEAK_FP64 / 1e12,
-                "unit": "TFLOP/s", "frac": achieved_fl / PEAK_FP64, "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved_fl / PEAK_FP64, "traffic": traffic,
                 "flop_per_cell": flop / n, "ceiling_cells_per_s": ceil_alu}
     roof_hbm = {"bound": "hbm", "achieved": achieved_bw / 1e9, "peak": PEAK_HBM / 1e9,
-                "unit": "GB/s", "frac": achieved_bw / PEAK_HBM, "traffic": None,
+                "unit": "GB/s", "frac": achieved_bw / PEAK_HBM, "traffic": traffic,
                 "bytes_per_cell": bpc, "ceiling_cells_per_s": ceil_hbm}
     roof, other = (roof_alu, roof_hbm) if ceil_alu <= ceil_hbm else (roof_hbm, roof_alu)
 

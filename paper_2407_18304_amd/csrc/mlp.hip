@@ -359,17 +359,33 @@ __device__ __forceinline__ void tile_layer(const __bf16* in, int ldi, const __bf
     for (int a = 0; a < 4; ++a)
 #pragma unroll
       for (int t = 0; t < 2; ++t) acc[a][t] = floatx4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < K_pad; k0 += 32) {
-      bf16x8 bfr[2];
-      bfr[0] = *(const bf16x8*)(W + (int64_t)(16 * nts[0] + r16) * K_pad + k0 + kq);
-      bfr[1] = two ? *(const bf16x8*)(W + (int64_t)(16 * nts[1] + r16) * K_pad + k0 + kq)
-                   : bfr[0];
+    const __bf16* w0 = W + (int64_t)(16 * nts[0] + r16) * K_pad + kq;
+    const __bf16* w1 = W + (int64_t)(16 * (two ? nts[1] : nts[0]) + r16) * K_pad + kq;
+    const int ksteps = K_pad / 32;
+    // the B fragments of up to kPre k-steps are requested at once (one L2
+    // latency per layer instead of one per k-step)
+    constexpr int kPre = 8;
+    for (int kb = 0; kb < ksteps; kb += kPre) {
+      bf16x8 bfr[kPre][2];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const bf16x8 af = *(const bf16x8*)(in + (16 * a + r16) * ldi + k0 + kq);
-        acc[a][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfr[0], acc[a][0], 0, 0, 0);
-        if (two)
-          acc[a][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfr[1], acc[a][1], 0, 0, 0);
+      for (int kk = 0; kk < kPre; ++kk) {
+        if (kb + kk < ksteps) {
+          bfr[kk][0] = *(const bf16x8*)(w0 + 32 * (kb + kk));
+          bfr[kk][1] = *(const bf16x8*)(w1 + 32 * (kb + kk));
+        }
+      }
+#pragma unroll
+      for (int kk = 0; kk < kPre; ++kk) {
+        if (kb + kk >= ksteps) break;
+        const int k0 = 32 * (kb + kk);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const bf16x8 af = *(const bf16x8*)(in + (16 * a + r16) * ldi + k0 + kq);
+          acc[a][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfr[kk][0], acc[a][0], 0, 0, 0);
+          if (two)
+            acc[a][1] =
+                __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfr[kk][1], acc[a][1], 0, 0, 0);
+        }
       }
     }
     const int col16 = lane % 16, row4 = 4 * (lane / 16);
