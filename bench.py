@@ -80,6 +80,8 @@ def main():
                     help="learned warm start: train the network on 2^20 solver pairs of the "
                          "same distribution (training seed, untimed), then time network "
                          "inference + solve per step, and plain steps for comparison")
+    ap.add_argument("--tune", action="store_true",
+                    help="config4: run the batch autotuner before timing")
     ap.add_argument("--train-cells", type=int, default=1 << 20)
     ap.add_argument("--epochs", type=int, default=8)
     ap.add_argument("--tuning", default="",
@@ -296,6 +298,11 @@ def run_batch(args):
     b = mgrhd.Batch(pd, mean_mode=args.mode, polish=1, c=u["c"], a_rad=u["a_rad"])
     if args.tuning:
         b.set_tuning(*(int(x) for x in args.tuning.split(",")))
+    elif args.tune:
+        from paper_2407_18304_amd import autotune
+        autotune.tune_batch(b, lambda: synth.fill_patches(dps), reps=1,
+                            path=os.path.join(ROOT, "gpurun_out", "tuning_batch.json"),
+                            log=lambda m: print(m, file=sys.stderr, flush=True))
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         b.capture(stream.cuda_stream)

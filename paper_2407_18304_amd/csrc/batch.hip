@@ -72,7 +72,9 @@ __device__ __forceinline__ bool stage_tables_wave(const KArgs& a, Tables<kBatchN
 template <int G, int MODE>
 __global__ __launch_bounds__(kBlock, 2) void k_batch(BatchArgs b) {
   __shared__ Tables<kBatchNGM> tabs[kBlock / kWave];
-  using LS = LaneStore<G, false>;
+  // 2 groups per lane leave room in LDS for the old-time fluxes and velocity;
+  // with 4 they are re-read from HBM by the outer stage
+  using LS = LaneStore<G, G == 2>;
   __shared__ double lane_lds[LS::kSlots * kBlock];
   const LS ls{lane_lds + threadIdx.x};
   const int lane = threadIdx.x % kWave;
