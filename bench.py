@@ -31,16 +31,18 @@ PEAK_HBM = 8.0e12            # bytes/s
 PEAK_FP64 = 78.6e12          # FP64 vector FLOP/s
 
 
+SOLVER_SOURCES = ("source_update.hip", "solver_device.hpp", "planck_device.hpp",
+                  "planck_poly.inc")
+
+
 def kernel_source_sha() -> str:
-    """Hash of the kernel sources (csrc/*.hip, *.hpp, *.inc): a measured HBM
+    """Hash of the sources of the single-table solver kernel: a measured HBM
     traffic is reported only for the sources it was measured on."""
-    import glob
     import hashlib
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2407_18304_amd", "csrc", "*"))):
-        if f.endswith((".hip", ".hpp", ".inc")):
-            h.update(os.path.basename(f).encode())
-            h.update(open(f, "rb").read())
+    for name in SOLVER_SOURCES:
+        h.update(name.encode())
+        h.update(open(os.path.join(ROOT, "paper_2407_18304_amd", "csrc", name), "rb").read())
     return h.hexdigest()[:16]
 
 

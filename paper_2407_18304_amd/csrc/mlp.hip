@@ -364,7 +364,7 @@ __device__ __forceinline__ void tile_layer(const __bf16* in, int ldi, const __bf
     const int ksteps = K_pad / 32;
     // the B fragments of up to kPre k-steps are requested at once (one L2
     // latency per layer instead of one per k-step)
-    constexpr int kPre = 8;
+    constexpr int kPre = 4;
     for (int kb = 0; kb < ksteps; kb += kPre) {
       bf16x8 bfr[kPre][2];
 #pragma unroll
@@ -451,21 +451,35 @@ __global__ __launch_bounds__(256) void k_infer(InferArgs q) {
         put(0, live ? __logf(T) : 0.f);
         put(1, live ? __logf(rho) : 0.f);
       }
-      for (int g = qd; g < ng; g += 4) {
-        float le = -50.f, fr = 0.f;
-        if (live) {
-          const double E = p.E[(int64_t)g * n + i];
-          const double f0 = p.F[((int64_t)0 * ng + g) * n + i];
-          const double f1 = p.F[((int64_t)1 * ng + g) * n + i];
-          const double f2 = p.F[((int64_t)2 * ng + g) * n + i];
-          if (E > 0.0) {
-            le = fminf(fmaxf(__logf((float)(E / (double)aT4)), -50.f), 50.f);
-            fr = fminf((float)(sqrt(f0 * f0 + f1 * f1 + f2 * f2) / (p.c * E)), 2.f);
+      // four groups per chunk: their 16 loads are in flight together
+      constexpr int kU = 4;
+      for (int g0 = qd; g0 < ng; g0 += 4 * kU) {
+        double E[kU], f0[kU], f1[kU], f2[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int g = g0 + 4 * u;
+          E[u] = f0[u] = f1[u] = f2[u] = 0.0;
+          if (live && g < ng) {
+            E[u] = p.E[(int64_t)g * n + i];
+            f0[u] = p.F[((int64_t)0 * ng + g) * n + i];
+            f1[u] = p.F[((int64_t)1 * ng + g) * n + i];
+            f2[u] = p.F[((int64_t)2 * ng + g) * n + i];
           }
         }
-        put(2 + g, le);
-        put(2 + ng + g, fr);
-        put(2 + 2 * ng + g, lcell + lchi[g]);
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int g = g0 + 4 * u;
+          if (g >= ng) break;
+          float le = -50.f, fr = 0.f;
+          if (E[u] > 0.0) {
+            le = fminf(fmaxf(__logf((float)(E[u] / (double)aT4)), -50.f), 50.f);
+            fr = fminf((float)(sqrt(f0[u] * f0[u] + f1[u] * f1[u] + f2[u] * f2[u]) /
+                               (p.c * E[u])), 2.f);
+          }
+          put(2 + g, le);
+          put(2 + ng + g, fr);
+          put(2 + 2 * ng + g, lcell + lchi[g]);
+        }
       }
       for (int f = q.n_in + qd; f < q.K_pad[0]; f += 4) xr[f] = (__bf16)0.f;
     }
