@@ -27,6 +27,54 @@ constexpr double kPi = 3.14159265358979323846264338327950288;
 constexpr double kC15 = 15.0 / (kPi * kPi * kPi * kPi);
 constexpr int kTailTerms = 10;
 
+// 1/k^j, the coefficient of u^{k-1} in S_j(u) of the Wien tail
+__host__ __device__ constexpr double tail_coef(int k, int j) {
+  double r = 1.0;
+  for (int i = 0; i < j; ++i) r /= k;
+  return r;
+}
+
+// fma(a, b, c) for a compile-time constant c.  On the device c is handed to
+// v_fma_f64 as a scalar-register pair, built by two scalar moves that issue
+// beside the vector stream; left to itself the compiler builds every
+// polynomial coefficient with two vector moves, which cost as much issue time
+// as the FMA they feed.
+__host__ __device__ __forceinline__ double fma_c(double a, double b, double c) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+  return r;
+#else
+  return fma(a, b, c);
+#endif
+}
+
+// e^{-x} for x >= 0 (NaN passes through): Cody-Waite reduction
+// x = n ln2 + r, |r| <= ln2/2, with ln2 split in a head and a tail so that r
+// is exact to the last bits, then e^{-r} by its Taylor series to degree 13
+// (remainder below 5e-18 relative) and the scale 2^{-n}.  Results below the
+// normal range are rounded to subnormals by the scaling; x > 746 gives 0.
+constexpr double kInvLn2 = 1.4426950408889634074;
+constexpr double kLn2Hi = 0.69314718055994528623;      // ln 2 rounded to double
+constexpr double kLn2Lo = 2.3190468138462996154e-17;   // ln 2 - kLn2Hi
+constexpr int kExpDeg = 13;
+
+__host__ __device__ constexpr double inv_factorial(int k) {
+  double f = 1.0;
+  for (int i = 2; i <= k; ++i) f *= i;
+  return 1.0 / f;
+}
+
+__host__ __device__ __forceinline__ double exp_neg(double x) {
+  const double xc = x > 746.0 ? 746.0 : x;
+  const double n = rint(xc * kInvLn2);
+  const double mr = fma(n, kLn2Lo, fma(n, kLn2Hi, -xc));   // -r
+  double p = inv_factorial(kExpDeg);
+#pragma unroll
+  for (int k = kExpDeg - 1; k >= 0; --k) p = fma_c(p, mr, inv_factorial(k));
+  return ldexp(p, -static_cast<int>(fmax(n, 0.0)));   // a NaN n converts as 0
+}
+
 // +inf test usable on host and device
 __host__ __device__ __forceinline__ bool is_pinf(double x) { return x > 1.7976931348623157e308; }
 
@@ -47,33 +95,36 @@ __host__ __device__ __forceinline__ Edge planck_edge(double x) {
   e.wien = x > kPlanckSplit;
   static_assert(kEdgeSplit == kPlanckSplit, "one polynomial branch below the Wien side");
   double u = 1.0;
-  if (e.wien) u = exp(-x);
+  if (e.wien) u = exp_neg(x);
   e.u = u;
   const double y = x * x;
   const double x3 = y * x;
   if (!e.wien) {
     double ap = planck_ap(kApDeg);
 #pragma unroll
-    for (int k = kApDeg - 1; k >= 0; --k) ap = fma(ap, y, planck_ap(k));
+    for (int k = kApDeg - 1; k >= 0; --k) ap = fma_c(ap, y, planck_ap(k));
     e.val = kC15 * x3 * ((1.0 / 3.0 - 0.125 * x) + ap * y);
     double ep = planck_ep(kEpDeg);
 #pragma unroll
-    for (int k = kEpDeg - 1; k >= 0; --k) ep = fma(ep, y, planck_ep(k));
+    for (int k = kEpDeg - 1; k >= 0; --k) ep = fma_c(ep, y, planck_ep(k));
     e.eps = kC15 * x3 * ((1.0 - 0.5 * x) + ep * y);
   } else if (e.inf) {
     e.val = 0.0;
     e.eps = 0.0;
   } else {
-    // Horner in u over k = 10..1 of x^3/k + 3x^2/k^2 + 6x/k^3 + 6/k^4
-    const double a3 = x3, a2 = 3.0 * y, a1 = 6.0 * x;
-    double acc = 0.0;
+    // sum_k u^{k-1} (x^3/k + 3x^2/k^2 + 6x/k^3 + 6/k^4) as
+    // x^3 S1(u) + 3x^2 S2(u) + 6x S3(u) + 6 S4(u), S_j(u) = sum_k u^{k-1}/k^j:
+    // four Horner chains in u with constant coefficients 1/k^j
+    double s1 = tail_coef(kTailTerms, 1), s2 = tail_coef(kTailTerms, 2);
+    double s3 = tail_coef(kTailTerms, 3), s4 = tail_coef(kTailTerms, 4);
 #pragma unroll
-    for (int k = kTailTerms; k >= 1; --k) {
-      const double r = 1.0 / k;
-      const double q = fma(a3, r, fma(a2, r * r, fma(a1, r * r * r, 6.0 * r * r * r * r)));
-      acc = (k == kTailTerms) ? q : fma(acc, u, q);
+    for (int k = kTailTerms - 1; k >= 1; --k) {
+      s1 = fma_c(s1, u, tail_coef(k, 1));
+      s2 = fma_c(s2, u, tail_coef(k, 2));
+      s3 = fma_c(s3, u, tail_coef(k, 3));
+      s4 = fma_c(s4, u, tail_coef(k, 4));
     }
-    e.val = kC15 * acc;
+    e.val = kC15 * fma(x3, s1, fma(3.0 * y, s2, fma(6.0 * x, s3, 6.0 * s4)));
     e.eps = kC15 * x3 * x / (1.0 - u);
   }
   return e;
@@ -98,8 +149,8 @@ __host__ __device__ __forceinline__ Edge planck_edge_low(double x) {
   double ap = planck_ap(kLowDeg), ep = planck_ep(kLowDeg);
 #pragma unroll
   for (int k = kLowDeg - 1; k >= 0; --k) {
-    ap = fma(ap, y, planck_ap(k));
-    ep = fma(ep, y, planck_ep(k));
+    ap = fma_c(ap, y, planck_ap(k));
+    ep = fma_c(ep, y, planck_ep(k));
   }
   e.val = kC15 * x3 * ((1.0 / 3.0 - 0.125 * x) + ap * y);
   e.eps = kC15 * x3 * ((1.0 - 0.5 * x) + ep * y);
@@ -127,7 +178,7 @@ __host__ __device__ __forceinline__ GroupPlanck group_planck(const Edge& lo, con
     else if (lo.x < 700.0)
       d = hi.u / lo.u;
     else
-      d = exp(lo.x - hi.x);
+      d = exp_neg(hi.x - lo.x);
     p.b = lo.val - d * hi.val;
     p.elo = lo.eps;
     p.ehi = d * hi.eps;

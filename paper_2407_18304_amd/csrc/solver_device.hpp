@@ -77,11 +77,12 @@ struct Tables {
 
 // Lane exchange inside a row of 16 lanes through the DPP crossbar (no LDS
 // round trip).  All lanes of one cell group are active together, so the
-// source lane is always active.
+// source lane is always active, and the destination needs no prior value
+// (bound_ctrl: a lane with no source would read 0).
 template <int CTRL>
 __device__ __forceinline__ double dpp_swap(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
   return __hiloint2double(hi, lo);
 }
 

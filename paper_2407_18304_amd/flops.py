@@ -7,7 +7,8 @@ method as the kernels write it, per cell, in FLOP-equivalents:
 
 * +, -, x = 1 and fused multiply-add = 2; comparisons, selects, integer and
   memory work = 0;
-* a call of exp, expm1, log, sqrt or a division costs the FLOP-equivalents of
+* a call of exp, expm1, log, sqrt, a division or the kernels' own e^{-x}
+  (exp_neg of planck_device.hpp) costs the FLOP-equivalents of
   the FP64 instruction sequence gfx950 code uses for it (FMA = 2, every other
   FP64 arithmetic instruction = 1, compares 0), counted in the assembly of a
   probe kernel built with the library's flags (``python -m
@@ -34,8 +35,10 @@ from collections import Counter
 
 import numpy as np
 
+CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+
 # FLOP-equivalents of one call on gfx950 (measured by measure_weights())
-W = {"exp": 29, "expm1": 34, "log": 84, "div": 17, "sqrt": 19}
+W = {"exp": 29, "expm1": 34, "log": 84, "div": 17, "sqrt": 19, "exp_neg": 34}
 
 PC, FIXED, FREE = 0, 1, 2
 
@@ -43,6 +46,7 @@ PC, FIXED, FREE = 0, 1, 2
 def unit_costs(w=W):
     """Per-unit FLOP-equivalents of the kernel source (see module doc)."""
     e, m1, lg, dv, sq = w["exp"], w["expm1"], w["log"], w["div"], w["sqrt"]
+    en = w["exp_neg"]
     # one Planck edge: x = hk/T * nu (1), x^2 and x^3 (2), then by branch
     edge_common = 1 + 2
     poly_P = 14 * 2 + 6              # degree-14 Horner in x^2 and the bracket
@@ -50,7 +54,9 @@ def unit_costs(w=W):
     edge = {
         "x<=2": edge_common + poly_P + poly_E,
         "2<x<=4": edge_common + poly_P + poly_E,
-        "x>4": edge_common + e + 2 + (10 * 6 + 9 * 2) + 1 + (3 + dv),  # 10-term tail
+        # e^{-x}, the 10-term tail as four degree-9 Horner chains in u and their
+        # combination, then x^4/(1 - u)
+        "x>4": edge_common + en + 4 * 9 * 2 + 10 + (3 + dv),
         # the lowest edge at x <= 0.1: both polynomials truncated to degree 3
         "low": edge_common + 2 * (3 * 2 + 6),
     }
@@ -141,6 +147,7 @@ def flops_per_cell(ng, mode, iters, outer, mix, u=UNIT, valid=None):
 PROBE = r"""
 #include <hip/hip_runtime.h>
 #include <cmath>
+#include "planck_device.hpp"
 #define K(name, expr) extern "C" __global__ void name(const double* __restrict__ a, \
     double* __restrict__ o) { int i = threadIdx.x; double x = a[i]; o[i] = expr; }
 K(p_exp, exp(x))
@@ -148,6 +155,7 @@ K(p_expm1, expm1(x))
 K(p_log, log(x))
 K(p_div, a[i + 64] / x)
 K(p_sqrt, sqrt(x))
+K(p_exp_neg, mgrhd::exp_neg(x))
 """
 
 
@@ -167,8 +175,8 @@ def measure_weights(hipcc="/opt/rocm/bin/hipcc", arch="gfx950"):
         with open(src, "w") as f:
             f.write(PROBE)
         subprocess.run([hipcc, f"--offload-arch={arch}", "-O3", "-Xclang", "-target-feature",
-                        "-Xclang", "-packed-fp32-ops", "--cuda-device-only", "-S", "-o", asm,
-                        src], check=True, capture_output=True)
+                        "-Xclang", "-packed-fp32-ops", "-I", CSRC, "--cuda-device-only", "-S",
+                        "-o", asm, src], check=True, capture_output=True)
         text = open(asm).read()
     out, cur, body = {}, None, []
     for line in text.splitlines():

@@ -26,4 +26,5 @@ void dm_group(double xl, double xh, double* out) {
   out[4] = p.scale;
 }
 double dm_mean_ratio(double ac, double aq, double L) { return mgrhd::mean_ratio(ac, aq, L); }
+double dm_exp_neg(double x) { return mgrhd::exp_neg(x); }
 }

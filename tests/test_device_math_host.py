@@ -32,6 +32,8 @@ def dm(tmp_path_factory):
     L.dm_group.argtypes = [C.c_double, C.c_double, dp]
     L.dm_mean_ratio.restype = C.c_double
     L.dm_mean_ratio.argtypes = [C.c_double, C.c_double, C.c_double]
+    L.dm_exp_neg.restype = C.c_double
+    L.dm_exp_neg.argtypes = [C.c_double]
     return L
 
 
@@ -96,3 +98,26 @@ def test_low_edge_matches_full_edge(dm, x):
     p = 1 - mp_ref.Q_polylog(x) if x > 0 else 0
     assert abs(val - p) <= 1e-15 * p + 1e-300
     assert abs(eps - mp_ref.edge_term(x)) <= 1e-15 * mp_ref.edge_term(x) + 1e-300
+
+
+def test_exp_neg(dm):
+    """The kernels' own e^{-x} (Cody-Waite reduction and a degree-13 Taylor
+    polynomial): within 2 units in the last place of mpmath's value over the
+    normal range, within one subnormal step below it, 0 beyond x = 746, and
+    NaN passed through."""
+    rng = np.random.default_rng(5)
+    xs = np.concatenate([[0.0, 1e-300, 1e-17, 0.5 * np.log(2), np.log(2), 4.0, 4.0000001,
+                          700.0, 708.39, 708.4, 744.4, 745.1, 745.13],
+                         rng.uniform(0, 1, 200), rng.uniform(4, 60, 400),
+                         10.0 ** rng.uniform(-10, np.log10(745.0), 400)])
+    ulp_rel = 2.0 ** -52
+    for x in xs:
+        got = dm.dm_exp_neg(float(x))
+        ref = mp.exp(-mp.mpf(float(x)))
+        if ref >= mp.mpf(2.0) ** -1022:
+            assert abs(got - ref) <= 2 * ulp_rel * ref, x
+        else:
+            assert abs(got - ref) <= mp.mpf(2.0) ** -1074, x
+    for x in (746.0, 800.0, 1e5, 1e300, float("inf")):
+        assert dm.dm_exp_neg(x) == 0.0
+    assert np.isnan(dm.dm_exp_neg(float("nan")))
