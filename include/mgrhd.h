@@ -218,7 +218,9 @@ typedef struct mgrhd_batch mgrhd_batch;
 int mgrhd_batch_create(const mgrhd_patch* patches, int32_t n_patches, int32_t mean_mode,
                        const mgrhd_options* opt, mgrhd_batch** out);
 /* Tuning knobs (see the autotuner): groups per lane (2 or 4), resident
- * workgroups per CU (0 = as many as fit), cells per work item. */
+ * workgroups per CU (0 = as many as fit), cells per work item.  Defaults:
+ * 2, 0, 1024.  The per-cell state machine is compiled for every lane count
+ * per cell (a wave dispatches on its item's patch). */
 int mgrhd_batch_set_tuning(mgrhd_batch* b, int32_t groups_per_lane, int32_t blocks_per_cu,
                            int64_t chunk_cells);
 int mgrhd_batch_get_tuning(const mgrhd_batch* b, int32_t* groups_per_lane,

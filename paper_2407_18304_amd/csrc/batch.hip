@@ -50,125 +50,106 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // Stage the tables of one patch into this wave's LDS slot (wave scope).
-template <int MODE>
-__device__ __forceinline__ bool stage_tables_wave(const KArgs& a, Tables<kBatchNGM>& t, int lane) {
+template <int MODE, int NGM>
+__device__ __forceinline__ bool stage_tables_wave(const KArgs& a, Tables<NGM>& t, int lane) {
   if (lane == 0) t.bad = 0;
   wave_sync();
   const int ng = a.ng;
-  if (ng > kBatchNGM) {
+  if (ng > NGM) {
     t.bad = 1;
     wave_sync();
     return false;
   }
   for (int g = lane; g <= ng; g += kWave)
-    if (!table_edge<kBatchNGM, MODE>(a, t, g)) atomicOr(&t.bad, 1);
+    if (!table_edge<NGM, MODE>(a, t, g)) atomicOr(&t.bad, 1);
   wave_sync();
   for (int g = lane; g < ng; g += kWave)
-    if (!table_group<kBatchNGM, MODE>(a, t, g)) atomicOr(&t.bad, 1);
+    if (!table_group<NGM, MODE>(a, t, g)) atomicOr(&t.bad, 1);
   wave_sync();
   return t.bad == 0;
 }
 
-template <int G, int MODE>
+// A copy of *p in scalar registers: every lane reads the same words and the
+// first lane's value is taken, so the compiler knows the fields are uniform.
+template <class T>
+__device__ __forceinline__ T load_uniform(const T* p) {
+  static_assert(sizeof(T) % 4 == 0, "whole words");
+  constexpr int kWords = sizeof(T) / 4;
+  int w[kWords];
+  const int* src = reinterpret_cast<const int*>(p);
+#pragma unroll
+  for (int k = 0; k < kWords; ++k) w[k] = __builtin_amdgcn_readfirstlane(src[k]);
+  T r;
+  __builtin_memcpy(&r, w, sizeof(T));
+  return r;
+}
+
+// Lanes per cell for N_g groups at G groups per lane: the next power of two
+// >= N_g / G.  The state machine is compiled for each.
+template <int G, int MODE, int NGM, class LS>
+__device__ __forceinline__ void run_item(const KArgs& a, const Tables<NGM>& tab, const LS& ls,
+                                         int lane, int64_t c0, int64_t c1) {
+  int lpc = 1;
+  while (lpc * G < a.ng) lpc <<= 1;
+  switch (lpc) {
+    case 1: run_cells<G, 1, MODE, NGM>(a, tab, ls, lane, c0, c1); break;
+    case 2: run_cells<G, 2, MODE, NGM>(a, tab, ls, lane, c0, c1); break;
+    case 4: run_cells<G, 4, MODE, NGM>(a, tab, ls, lane, c0, c1); break;
+    case 8: run_cells<G, 8, MODE, NGM>(a, tab, ls, lane, c0, c1); break;
+    case 16: run_cells<G, 16, MODE, NGM>(a, tab, ls, lane, c0, c1); break;
+    case 32: run_cells<G, 32, MODE, NGM>(a, tab, ls, lane, c0, c1); break;
+    default:  // a patch wider than 32 lanes of G groups
+      if constexpr (G * 32 < NGM) run_cells<G, kWave, MODE, NGM>(a, tab, ls, lane, c0, c1);
+      break;
+  }
+}
+
+// 2 groups per lane leave room in LDS for the old-time fluxes and velocity
+// (re-reading them from HBM in the outer stage, or a table slot narrower than
+// 128 groups to fit a third workgroup per CU, measured slower: the extra
+// registers spill); with 4 they are re-read from HBM by the outer stage.
+template <int G, int MODE, int NGM>
 __global__ __launch_bounds__(kBlock, 2) void k_batch(BatchArgs b) {
-  __shared__ Tables<kBatchNGM> tabs[kBlock / kWave];
-  // 2 groups per lane leave room in LDS for the old-time fluxes and velocity;
-  // with 4 they are re-read from HBM by the outer stage
+  static_assert(G * kWave >= NGM, "a wave holds the widest patch");
+  __shared__ Tables<NGM> tabs[kBlock / kWave];
   using LS = LaneStore<G, G == 2>;
   __shared__ double lane_lds[LS::kSlots * kBlock];
   const LS ls{lane_lds + threadIdx.x};
   const int lane = threadIdx.x % kWave;
-  Tables<kBatchNGM>& tab = tabs[threadIdx.x / kWave];
-  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
-
-  CellState<G> s;
-  s.phase = P_IDLE;
-  s.i = -1;
-  s.lpc = 1;
-  Cache<G> c;
+  Tables<NGM>& tab = tabs[threadIdx.x / kWave];
   int cur_patch = -1;
   bool table_ok = false;
-  int64_t next = 0, hi = 0;
-  const KArgs* ap = b.patches;
-  int j = 0;
   for (;;) {
-    // all cell groups idle: take the next work item
-    if (__ballot(s.phase != P_IDLE) == 0) {
-      int it = 0;
-      if (lane == 0) it = atomicAdd(b.counter, 1);
-      it = __shfl(it, 0, kWave);
-      if (it >= b.n_items) break;
-      const Item item = b.items[it];
-      ap = b.patches + item.patch;
-      if (item.patch != cur_patch) {
-        table_ok = stage_tables_wave<MODE>(*ap, tab, lane);
-        cur_patch = item.patch;
-      }
-      int lpc = 1;
-      while (lpc * G < ap->ng) lpc <<= 1;
-      s.lpc = lpc;
-      j = lane % lpc;
-      next = item.c0;
-      hi = item.c1;
-      if (!table_ok) {
-        for (int64_t i = next + lane; i < hi; i += kWave) {
-          if (ap->status) ap->status[i] = MGRHD_ST_BAD_TABLE;
-          if (ap->iters) ap->iters[i] = 0;
-          if (ap->outer) ap->outer[i] = 0;
-        }
-        continue;
-      }
-      s.phase = P_EMPTY;
+    // the wave takes the next work item (all lanes are active here)
+    int it = 0;
+    if (lane == 0) it = atomicAdd(b.counter, 1);
+    it = __builtin_amdgcn_readfirstlane(it);
+    if (it >= b.n_items) break;
+    const Item item = load_uniform(b.items + it);
+    const KArgs& a = b.patches[item.patch];
+    if (item.patch != cur_patch) {
+      table_ok = stage_tables_wave<MODE, NGM>(a, tab, lane);
+      cur_patch = item.patch;
     }
-    const KArgs& a = *ap;
-    // refill from the item
-    const bool need = s.phase == P_EMPTY;
-    const uint64_t m = __ballot(need && j == 0);
-    if (m) {
-      const int rank = __popcll(m & below);
-      int64_t mine = next + rank;
-      next += __popcll(m);
-      mine = __shfl(mine, lane - j, kWave);
-      if (need) {
-        if (mine < hi) {
-          load_cell<G, 0, MODE, kBatchNGM>(a, tab, j, mine, s, ls);
-          if (s.phase == P_EMPTY) finish_cell<G, 0>(a, j, s, ls, false);
-        } else {
-          s.phase = P_IDLE;
-        }
-      }
-    }
-    if (s.phase != P_NEWTON && s.phase != P_FLUX) continue;
-
-    const double T = ((s.phase == P_FLUX ? s.egas_new : s.egv) - s.ke) * s.ircv;
-    if (!(T > 0.0) || !isfinite(T)) {
-      if (s.phase == P_NEWTON)
-        newton_done<G, 0>(a, j, s, ls, 2);
-      else {
-        s.st |= MGRHD_ST_INVALID;
-        finish_cell<G, 0>(a, j, s, ls, false);
+    if (!table_ok) {
+      for (int64_t i = item.c0 + lane; i < item.c1; i += kWave) {
+        if (a.status) a.status[i] = MGRHD_ST_BAD_TABLE;
+        if (a.iters) a.iters[i] = 0;
+        if (a.outer) a.outer[i] = 0;
       }
       continue;
     }
-    double Ecur[G];
-#pragma unroll
-    for (int k = 0; k < G; ++k) Ecur[k] = s.E0[k] + s.R[k];
-    const double aT4 = a.a * (T * T) * (T * T);
-    evaluate<G, 0, MODE, kBatchNGM>(tab, a.ng, j, s.lpc, T, aT4, a.hk, s.rho_kappa, Ecur, c);
-    if (s.phase == P_FLUX) {
-      if (!flux_step<G, 0, MODE, kBatchNGM>(a, tab, j, s, ls, c)) continue;
-    }
-    if (s.elim) group_balance<G, 0, MODE, kBatchNGM>(a, tab, j, s, ls, c);
-    newton_step<G, 0, MODE, kBatchNGM>(a, tab, j, s, ls, c);
+    run_item<G, MODE>(a, tab, ls, lane, item.c0, item.c1);
   }
 }
 
 using BatchFn = void (*)(BatchArgs);
-static const int kBatchG[] = {2, 4};
 static BatchFn batch_fn(int g, int mode) {
   static const BatchFn fns[2][3] = {
-      {k_batch<2, MGRHD_MEAN_PC>, k_batch<2, MGRHD_MEAN_PPL_FIXED>, k_batch<2, MGRHD_MEAN_PPL_FREE>},
-      {k_batch<4, MGRHD_MEAN_PC>, k_batch<4, MGRHD_MEAN_PPL_FIXED>, k_batch<4, MGRHD_MEAN_PPL_FREE>}};
+      {k_batch<2, MGRHD_MEAN_PC, kBatchNGM>, k_batch<2, MGRHD_MEAN_PPL_FIXED, kBatchNGM>,
+       k_batch<2, MGRHD_MEAN_PPL_FREE, kBatchNGM>},
+      {k_batch<4, MGRHD_MEAN_PC, kBatchNGM>, k_batch<4, MGRHD_MEAN_PPL_FIXED, kBatchNGM>,
+       k_batch<4, MGRHD_MEAN_PPL_FREE, kBatchNGM>}};
   return fns[g == 4 ? 1 : 0][mode];
 }
 
@@ -187,9 +168,9 @@ struct mgrhd_batch {
   int64_t n_items = 0;
   std::vector<KArgs> h_patches;
   // tuning
-  int32_t groups_per_lane = 4;
+  int32_t groups_per_lane = 2;
   int32_t blocks_per_cu = 0;  // 0 = all resident
-  int64_t chunk = 2048;
+  int64_t chunk = 1024;
   bool items_dirty = true;
   // graph
   hipGraph_t graph = nullptr;

@@ -748,6 +748,74 @@ __device__ __forceinline__ bool flux_step(const KArgs& a, const Tables<NGM>& t, 
   return true;
 }
 
+// The per-cell state machine of one wave over the cells [lo, hi): every cell
+// group without a cell takes the next one; each trip performs one material
+// evaluation for every active cell group, then the consumer of its phase (a
+// Newton step, or the flux/momentum update of the outer stage followed by the
+// first Newton step of the next pass at the same temperature).  Returns when
+// every cell is done.  Shared by the single-table and the batched kernels.
+template <int G, int LPC, int MODE, int NGM, class LS>
+__device__ __forceinline__ void run_cells(const KArgs& a, const Tables<NGM>& tab, const LS& ls,
+                                          int lane, int64_t lo, int64_t hi) {
+  static_assert(LPC >= 1 && LPC <= kWave && (LPC & (LPC - 1)) == 0, "lanes per cell");
+  const int j = lane % LPC;
+  CellState<G> s;
+  s.phase = P_EMPTY;
+  s.i = -1;
+  s.lpc = LPC;
+  Cache<G> c;
+  int64_t next = lo;  // wave-uniform queue position
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+  for (;;) {
+    // refill: every cell group without a cell takes the next one of the range
+    const bool need = s.phase == P_EMPTY;
+    const uint64_t m = __ballot(need && j == 0);
+    if (m) {
+      const int rank = __popcll(m & below);
+      int64_t mine = next + rank;
+      next += __popcll(m);
+      mine = __shfl(mine, lane - j, kWave);
+      if (need) {
+        if (mine < hi) {
+          load_cell<G, LPC, MODE, NGM>(a, tab, j, mine, s, ls);
+          if (s.phase == P_EMPTY) finish_cell<G, LPC>(a, j, s, ls, false);
+        } else {
+          s.phase = P_IDLE;
+        }
+      }
+    }
+    if (__ballot(s.phase == P_NEWTON || s.phase == P_FLUX) == 0) {
+      if (__ballot(s.phase == P_EMPTY) == 0) break;  // range exhausted
+      continue;
+    }
+    if (s.phase != P_NEWTON && s.phase != P_FLUX) continue;
+
+    // one material evaluation at this cell's current temperature
+    const double T = ((s.phase == P_FLUX ? s.egas_new : s.egv) - s.ke) * s.ircv;
+    if (!(T > 0.0) || !isfinite(T)) {
+      if (s.phase == P_NEWTON)
+        newton_done<G, LPC>(a, j, s, ls, 2);
+      else {
+        s.st |= MGRHD_ST_INVALID;
+        finish_cell<G, LPC>(a, j, s, ls, false);
+      }
+      continue;
+    }
+    double Ecur[G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) Ecur[k] = s.E0[k] + s.R[k];
+    const double aT4 = a.a * (T * T) * (T * T);
+    evaluate<G, LPC, MODE, NGM>(tab, a.ng, j, s.lpc, T, aT4, a.hk, s.rho_kappa, Ecur, c);
+
+    if (s.phase == P_FLUX) {
+      if (!flux_step<G, LPC, MODE, NGM>(a, tab, j, s, ls, c)) continue;
+      // the next inner pass starts at this temperature: fall through
+    }
+    if (s.elim) group_balance<G, LPC, MODE, NGM>(a, tab, j, s, ls, c);
+    newton_step<G, LPC, MODE, NGM>(a, tab, j, s, ls, c);
+  }
+}
+
 // WPE: minimum resident waves per SIMD the register allocation must allow
 
 }  // namespace mgrhd

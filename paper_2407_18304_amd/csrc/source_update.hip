@@ -40,7 +40,6 @@ namespace mgrhd {
 template <int G, int LPC, int MODE, int WPE>
 __global__ __launch_bounds__(kBlock, WPE) void k_source_update(KArgs a) {
   constexpr int NGM = G * LPC;
-  constexpr int kGroupsPerWave = kWave / LPC;
   __shared__ Tables<NGM> tab;
   using LS = LaneStore<G, true>;
   __shared__ double lane_lds[LS::kSlots * kBlock];
@@ -48,11 +47,9 @@ __global__ __launch_bounds__(kBlock, WPE) void k_source_update(KArgs a) {
   const bool table_ok = stage_tables<NGM, MODE>(a, tab);
 
   const int lane = threadIdx.x % kWave;
-  const int j = lane % LPC;
   const int64_t waves = (int64_t)gridDim.x * (kBlock / kWave);
   const int64_t wave = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
   const int64_t lo = a.n * wave / waves, hi = a.n * (wave + 1) / waves;
-  (void)kGroupsPerWave;
 
   if (!table_ok) {
     // the table is unusable: report every cell of this wave's chunk
@@ -64,61 +61,7 @@ __global__ __launch_bounds__(kBlock, WPE) void k_source_update(KArgs a) {
     return;
   }
 
-  CellState<G> s;
-  s.phase = P_EMPTY;
-  s.i = -1;
-  s.lpc = LPC;
-  Cache<G> c;
-  int64_t next = lo;  // wave-uniform queue position
-  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
-  for (;;) {
-    // refill: every cell group without a cell takes the next one of the chunk
-    const bool need = s.phase == P_EMPTY;
-    const uint64_t m = __ballot(need && j == 0);
-    if (m) {
-      const int rank = __popcll(m & below);
-      int64_t mine = next + rank;
-      next += __popcll(m);
-      mine = __shfl(mine, lane - j, kWave);
-      if (need) {
-        if (mine < hi) {
-          load_cell<G, LPC, MODE, NGM>(a, tab, j, mine, s, ls);
-          if (s.phase == P_EMPTY) finish_cell<G, LPC>(a, j, s, ls, false);
-        } else {
-          s.phase = P_IDLE;
-        }
-      }
-    }
-    if (__ballot(s.phase == P_NEWTON || s.phase == P_FLUX) == 0) {
-      if (__ballot(s.phase == P_EMPTY) == 0) break;  // chunk exhausted
-      continue;
-    }
-    if (s.phase != P_NEWTON && s.phase != P_FLUX) continue;
-
-    // one material evaluation at this cell's current temperature
-    const double T = ((s.phase == P_FLUX ? s.egas_new : s.egv) - s.ke) * s.ircv;
-    if (!(T > 0.0) || !isfinite(T)) {
-      if (s.phase == P_NEWTON)
-        newton_done<G, LPC>(a, j, s, ls, 2);
-      else {
-        s.st |= MGRHD_ST_INVALID;
-        finish_cell<G, LPC>(a, j, s, ls, false);
-      }
-      continue;
-    }
-    double Ecur[G];
-#pragma unroll
-    for (int k = 0; k < G; ++k) Ecur[k] = s.E0[k] + s.R[k];
-    const double aT4 = a.a * (T * T) * (T * T);
-    evaluate<G, LPC, MODE, NGM>(tab, a.ng, j, s.lpc, T, aT4, a.hk, s.rho_kappa, Ecur, c);
-
-    if (s.phase == P_FLUX) {
-      if (!flux_step<G, LPC, MODE, NGM>(a, tab, j, s, ls, c)) continue;
-      // the next inner pass starts at this temperature: fall through
-    }
-    if (s.elim) group_balance<G, LPC, MODE, NGM>(a, tab, j, s, ls, c);
-    newton_step<G, LPC, MODE, NGM>(a, tab, j, s, ls, c);
-  }
+  run_cells<G, LPC, MODE, NGM>(a, tab, ls, lane, lo, hi);
 }
 
 // ---------------------------------------------------------------------------

@@ -118,6 +118,26 @@ def test_batch_ragged_and_empty_patches():
         U.compare(w, res, U.run_oracle(w, 2), label=f"ragged patch N_g={w.ng} n={w.n}")
 
 
+@pytest.mark.parametrize("gpl", [2, 4])
+def test_batch_wide_patches(gpl):
+    """Patches wider than 64 groups (the kernels with 128-group table slots;
+    at 2 groups per lane a cell spans the whole wavefront) next to narrow ones."""
+    layouts = W.patch_layouts(n_patches=5, seed=78, sides=(2, 3), ngs=(8, 65, 100, 128))
+    assert max(L.ng for L in layouts) > 64
+    dps = synth.device_patches(layouts)
+    inputs = [synth.patch_to_host(dp) for dp in dps]
+    pd = _patch_dicts(dps)
+    b = mgrhd.Batch(pd, mean_mode=1, polish=1, **_consts())
+    b.set_tuning(gpl, 0, 16)
+    b.run()
+    torch.cuda.synchronize()
+    for w, d in zip(inputs, pd):
+        res = ({k: d[k].cpu().numpy() for k in ("E_g", "F_g", "e_gas", "v")},
+               d["iters"].cpu().numpy(), d["outer"].cpu().numpy(), d["status"].cpu().numpy())
+        assert (res[3] >= 0).all()
+        U.compare(w, res, U.run_oracle(w, 1), label=f"wide patch N_g={w.ng} n={w.n}")
+
+
 def test_batch_argument_errors():
     layouts = _layouts(2)
     dps = synth.device_patches(layouts)
