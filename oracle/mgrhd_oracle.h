@@ -50,6 +50,19 @@ typedef struct {
   const double* chi_hi;      /* [N_g] opacity at the upper edge (tabulated case,
                                 index derived as a log ratio), or NULL          */
   const double* kappa_scale; /* [n] per-cell multiplier, or NULL (=1)           */
+  /* Temperature dependence (Sec. 4.1.2 simulation (c); eq. pulsek):
+   *   chi_0(nu, T) = rho kappa_scale chi^(nu) (T / t_ref)^t_exp [1 - e^{-x}]^stim,
+   * x = (h/k) nu / T, chi^ the table above.  Every Newton iterate evaluates the
+   * opacities at its own temperature; the Jacobian drops their T-derivatives,
+   * as the paper does for chi_0B/chi_0E (Sec. 3).  READING: in the PPL modes
+   * the group's powerlaw passes through the T-dependent values at its two
+   * edges (the tabulated-opacity rule of Sec. 2.2.2); PC takes the value at
+   * the lower edge, as for a T-independent table.  t_exp = 0 and stim = 0:
+   * no temperature dependence. */
+  double t_exp;
+  double t_ref;              /* > 0 when t_exp != 0                             */
+  int32_t stim;              /* 0 or 1; 1 needs group_edges[0] > 0              */
+  int32_t reserved;
 } ora_opacity;
 
 typedef struct {

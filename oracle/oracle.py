@@ -42,7 +42,9 @@ def build(verbose: bool = False) -> str:
 class OraOpacity(C.Structure):
     _fields_ = [("n_groups", C.c_int32), ("mean_mode", C.c_int32),
                 ("chi_lo", C.POINTER(C.c_double)), ("alpha_chi", C.POINTER(C.c_double)),
-                ("chi_hi", C.POINTER(C.c_double)), ("kappa_scale", C.POINTER(C.c_double))]
+                ("chi_hi", C.POINTER(C.c_double)), ("kappa_scale", C.POINTER(C.c_double)),
+                ("t_exp", C.c_double), ("t_ref", C.c_double), ("stim", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class OraOptions(C.Structure):
@@ -148,9 +150,11 @@ def source_update(state: dict, edges, chi_lo, *, mean_mode=MEAN_PPL_FIXED, alpha
                   chi_hi=None, kappa_scale=None, dt=1.0, c_hat=1.0, c=1.0, a_rad=1.0,
                   h_over_k=1.0, c_v=1.5, eps_newton=1e-11, eps_outer=1e-13,
                   max_newton=100, max_outer=10, closure=CLOSURE_M1, polish=0, S_g=None,
-                  guess=None, guess_kind=0, n_threads=0):
+                  guess=None, guess_kind=0, t_exp=0.0, t_ref=1.0, stim=0, n_threads=0):
     """Run the oracle on a copy of ``state`` (dict of E_g [N_g,n], F_g [3,N_g,n],
-    rho [n], e_gas [n], v [3,n]).  Returns (new_state, iters, outer, status)."""
+    rho [n], e_gas [n], v [3,n]).  Returns (new_state, iters, outer, status).
+    t_exp, t_ref, stim: temperature dependence of the opacity,
+    chi_0 x (T/t_ref)^t_exp [1 - exp(-h nu / k T)]^stim."""
     E = np.array(state["E_g"], dtype=np.float64, order="C", copy=True)
     F = np.array(state["F_g"], dtype=np.float64, order="C", copy=True)
     rho = np.ascontiguousarray(state["rho"], dtype=np.float64)
@@ -170,7 +174,8 @@ def source_update(state: dict, edges, chi_lo, *, mean_mode=MEAN_PPL_FIXED, alpha
     iters = np.zeros(n, np.int32)
     outer = np.zeros(n, np.int32)
     status = np.zeros(n, np.int32)
-    op = OraOpacity(ng, mean_mode, _dp(chi_lo), _dp(alpha_chi), _dp(chi_hi), _dp(kappa_scale))
+    op = OraOpacity(ng, mean_mode, _dp(chi_lo), _dp(alpha_chi), _dp(chi_hi), _dp(kappa_scale),
+                    float(t_exp), float(t_ref), int(stim), 0)
     opt = OraOptions()
     lib().ora_default_options(C.byref(opt))
     opt.c, opt.a_rad, opt.h_over_k, opt.c_v = c, a_rad, h_over_k, c_v

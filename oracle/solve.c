@@ -45,6 +45,8 @@ typedef struct {
   double* lndnu; /* [ng] ln(nu_g+ - nu_g-) */
   const double* chilo;
   const double* kappa;
+  double t_exp, t_ref; /* temperature dependence of the opacity (0: none) */
+  int32_t stim;        /* 1: stimulated-emission factor 1 - e^{-x}         */
   double dt, chat, c, a, hk, cv, eps, eps_out;
   double *E_g, *F_g, *e_gas, *v;
   const double *rho, *S, *guess;
@@ -54,7 +56,7 @@ typedef struct {
 
 typedef struct {
   double *Bt, *Dnu, *dBdT, *b, *elo, *ehi, *sig, *chil;
-  double *chiB, *chiE, *chiF, *DchiB, *alB, *alE, *logq;
+  double *chiB, *chiE, *chiF, *DchiB, *alB, *alE, *logq, *ac;
   double *E0, *S, *R, *FR, *Jg0, *Jgg, *dx, *vF, *Ecur, *F0, *Fk, *Fn;
 } work;
 
@@ -75,7 +77,17 @@ static void material(const problem* p, work* w, double T, double rho_kappa,
     w->Bt[g] = aT4 * out[0] * scale;                /* B~_g = 4 pi B_g / c */
     w->Dnu[g] = aT4 * (out[2] - out[1]) * scale;    /* Delta_g(nu B~_nu)  */
     w->dBdT[g] = (4.0 * w->Bt[g] - w->Dnu[g]) / T;  /* d B~_g / dT        */
-    w->chil[g] = rho_kappa * p->chilo[g];           /* chi_{0,g-}         */
+    /* chi_{0,g-} at this temperature and the opacity index of the group */
+    double f = 1.0, ac = p->achi[g];
+    if (p->t_exp != 0.0) f = pow(T / p->t_ref, p->t_exp);
+    if (p->stim) {
+      double s_lo = -expm1(-p->hk * p->nu[g] / T);      /* 1 - e^{-x} at nu_g- */
+      double s_hi = -expm1(-p->hk * p->nu[g + 1] / T);  /* and at nu_g+       */
+      f *= s_lo;
+      if (p->mode != ORA_MEAN_PC) ac += log(s_hi / s_lo) / p->lnr[g];
+    }
+    w->chil[g] = rho_kappa * p->chilo[g] * f;
+    w->ac[g] = ac;
   }
   if (p->mode == ORA_MEAN_PC) {
     /* eq. m1e1: one constant per group; all means equal it, eq. G_model1b */
@@ -98,7 +110,7 @@ static void material(const problem* p, work* w, double T, double rho_kappa,
     ora_slopes(ng, p->nu, w->logq, w->alE);
   }
   for (int32_t g = 0; g < ng; ++g) {
-    double ac = p->achi[g], L = p->lnr[g], chl = w->chil[g];
+    double ac = w->ac[g], L = p->lnr[g], chl = w->chil[g];
     w->chiB[g] = chl * ora_mean_ratio(ac, w->alB[g], L); /* eq. chiQg, Q = B */
     w->chiE[g] = chl * ora_mean_ratio(ac, w->alE[g], L); /* eq. chiQg, Q = E */
     /* Delta_g(nu chi_0 B~_nu), group g's own powerlaw at both of its edges */
@@ -154,7 +166,7 @@ static int newton(const problem* p, work* w, double rho, double rho_kappa,
        * F_R,g = 0 (eq. FGFR) are linear in R_g alone; take that R_g */
       for (int32_t g = 0; g < ng; ++g) {
         double tauE = p->chat * p->dt * w->chiE[g];
-        double W = p->chat * p->dt * (1.0 + p->achi[g]) * w->chiF[g] * w->vF[g] /
+        double W = p->chat * p->dt * (1.0 + w->ac[g]) * w->chiF[g] * w->vF[g] /
                    (p->c * p->c);
         w->R[g] = (w->chiB[g] / w->chiE[g] * w->Bt[g] + W / tauE - w->E0[g] - w->S[g]) /
                   (1.0 + 1.0 / tauE);
@@ -168,7 +180,7 @@ static int newton(const problem* p, work* w, double rho, double rho_kappa,
     double FG = *egv - egas0 + cc * sumR;
     for (int32_t g = 0; g < ng; ++g) {
       double tauE = p->chat * p->dt * w->chiE[g];
-      double W = p->chat * p->dt * (1.0 + p->achi[g]) * w->chiF[g] * w->vF[g] /
+      double W = p->chat * p->dt * (1.0 + w->ac[g]) * w->chiF[g] * w->vF[g] /
                  (p->c * p->c);
       double Eg = w->chiB[g] / w->chiE[g] * w->Bt[g] + (W - w->R[g]) / tauE;
       w->FR[g] = Eg - w->E0[g] - w->R[g] - w->S[g];
@@ -290,7 +302,7 @@ static void solve_cell(const problem* p, work* w, int64_t i) {
       for (int d = 0; d < 3; ++d) {
         /* eq. numF1 */
         double Fn = (w->F0[3 * g + d] +
-                     p->chat * p->dt * (v[d] * emit + (1.0 + p->achi[g]) * w->chiE[g] * Pv[d])) /
+                     p->chat * p->dt * (v[d] * emit + (1.0 + w->ac[g]) * w->chiE[g] * Pv[d])) /
                     den;
         w->Fn[3 * g + d] = Fn;
         mom[d] -= (Fn - w->F0[3 * g + d]) / (p->c * p->chat); /* momentum update */
@@ -303,7 +315,7 @@ static void solve_cell(const problem* p, work* w, int64_t i) {
     for (int32_t g = 0; g < ng; ++g) {
       double vf_new = vn[0] * w->Fn[3 * g] + vn[1] * w->Fn[3 * g + 1] + vn[2] * w->Fn[3 * g + 2];
       double vf_old = v[0] * w->Fk[3 * g] + v[1] * w->Fk[3 * g + 1] + v[2] * w->Fk[3 * g + 2];
-      dW += fabs(p->chat * p->dt * (1.0 + p->achi[g]) * w->chiF[g] * (vf_new - vf_old)) /
+      dW += fabs(p->chat * p->dt * (1.0 + w->ac[g]) * w->chiF[g] * (vf_new - vf_old)) /
             (p->c * p->c);
     }
     /* READING: the next inner pass starts from the temperature of this
@@ -355,15 +367,15 @@ typedef struct {
 static void* worker(void* arg) {
   chunk* ch = (chunk*)arg;
   const int32_t ng = ch->p->ng;
-  /* 28 arrays of N_g doubles, three of them 3 N_g */
-  double* mem = (double*)malloc(sizeof(double) * (size_t)ng * 34);
+  /* 24 arrays of N_g doubles, one of N_g + 1 and three of 3 N_g */
+  double* mem = (double*)malloc(sizeof(double) * ((size_t)ng * 34 + 1));
   if (!mem) return (void*)1;
   work w;
   double* q = mem;
   double** slots[] = {&w.Bt,  &w.Dnu,  &w.dBdT, &w.b,   &w.elo, &w.ehi, &w.sig,
                       &w.chil, &w.chiB, &w.chiE, &w.chiF, &w.DchiB, &w.alB, &w.alE,
                       &w.logq, &w.E0,  &w.S,    &w.R,   &w.FR,  &w.Jg0, &w.Jgg,
-                      &w.vF,  &w.Ecur};
+                      &w.vF,  &w.Ecur, &w.ac};
   for (size_t s = 0; s < sizeof(slots) / sizeof(slots[0]); ++s) {
     *slots[s] = q;
     q += ng;
@@ -408,6 +420,9 @@ int ora_source_update(double* E_g, double* F_g, const double* rho, double* e_gas
       }
     }
   }
+  if (!isfinite(op->t_exp) || (op->t_exp != 0.0 && (!(op->t_ref > 0.0) || !isfinite(op->t_ref))))
+    return -4;
+  if (op->stim < 0 || op->stim > 1 || (op->stim && !(edges[0] > 0.0))) return -4;
   if (!(dt > 0.0) || !(c_hat > 0.0) || !isfinite(dt) || !isfinite(c_hat)) return -5;
   if (!(opt->c > 0.0) || !(opt->a_rad > 0.0) || !(opt->h_over_k > 0.0) || !(opt->c_v > 0.0))
     return -5;
@@ -428,6 +443,9 @@ int ora_source_update(double* E_g, double* F_g, const double* rho, double* e_gas
   p.nu = edges;
   p.chilo = op->chi_lo;
   p.kappa = op->kappa_scale;
+  p.t_exp = op->t_exp;
+  p.t_ref = op->t_ref;
+  p.stim = op->stim;
   p.dt = dt;
   p.chat = c_hat;
   p.c = opt->c;
