@@ -26,13 +26,15 @@ WORKLOADS = {
                "launch replayed from a hipGraph, FP64",
     "config2": "256^3 cells, 64 groups, PPL-fixed, FP64 (T over 3 decades, tau 1e-3..1e6)",
     "config0": "16^3 cells, 4 groups, PPL-fixed, FP64",
+    "config5": "128^3 cells, 16 groups, PPL-fixed, FP64, temperature-dependent opacity of the "
+               "pulse test (nu^-3, T^-1/2, stimulated emission) evaluated at every iterate",
 }
 PEAK_HBM = 8.0e12            # bytes/s
 PEAK_FP64 = 78.6e12          # FP64 vector FLOP/s
 
 
-SOLVER_SOURCES = ("source_update.hip", "solver_device.hpp", "planck_device.hpp",
-                  "planck_poly.inc")
+SOLVER_SOURCES = ("source_update.hip", "solver_kernel.hpp", "solver_device.hpp",
+                  "planck_device.hpp", "planck_poly.inc")
 
 
 def kernel_source_sha() -> str:
@@ -141,7 +143,7 @@ def main():
                             tab["chi_lo"], alpha_chi=tab["alpha"], kappa_scale=dw.kappa,
                             mean_mode=args.mode, polish=1, guess=guess, guess_kind=1,
                             iters=iters, outer=outer, status=status,
-                            stream=stream.cuda_stream, **dw.consts())
+                            stream=stream.cuda_stream, **dw.consts(), **dw.topacity())
 
     def timed(warm):
         for _ in range(args.warmup):
@@ -180,14 +182,16 @@ def main():
     T_fin = (st["e_gas"] - 0.5 * st["rho"] * (st["v"] ** 2).sum(0)) / (st["rho"] * u["c_v"])
     mix = F.edge_mix(W.spec_tables(name)[0], u["h_over_k"], T_fin.clamp(min=1e-300))
     valid = torch.from_numpy(((stt & 8) == 0).astype(np.float64)).to(dev)
-    fpc = F.flops_per_cell(ng, args.mode, iters.double(), outer.double(), mix, valid=valid)
+    fpc = F.flops_per_cell(ng, args.mode, iters.double(), outer.double(), mix, valid=valid,
+                           t_exp=dw.t_exp, stim=dw.stim)
     flop = float(fpc.sum())
     achieved_fl = flop / kern_s
     # the binding ceiling is the lower of the two for this workload
     ceil_alu = PEAK_FP64 / (flop / n)
     ceil_hbm = PEAK_HBM / bpc
     lpc_, g_, w_ = mgrhd.get_variant(ng, args.mode)
-    kname = f"k_source_update<{g_}, {lpc_}, {args.mode}, {w_}>"
+    td = "true" if (dw.t_exp != 0.0 or dw.stim) else "false"
+    kname = f"k_source_update<{g_}, {lpc_}, {args.mode}, {w_}, {td}>"
     traffic = None if (args.warm or args.cells or args.mode != 1) else measured_traffic(name, kname)
     roof_alu = {"bound": "alu", "achieved": achieved_fl / 1e12, "peak": PEAK_FP64 / 1e12,
                 "unit": "TFLOP/s", "frac": achieved_fl / PEAK_FP64, "traffic": traffic,
@@ -393,7 +397,8 @@ def cpu_baseline(dw, mode, target_s):
     w = synth.to_host(dw, idx)
     t0 = time.perf_counter()
     oracle.source_update(w.state, w.edges, w.chi_lo, alpha_chi=w.alpha_chi, kappa_scale=w.kappa,
-                         mean_mode=mode, polish=1, n_threads=cores, **w.consts())
+                         mean_mode=mode, polish=1, n_threads=cores, **w.consts(),
+                         **w.topacity())
     dt = time.perf_counter() - t0
     m2 = int(min(dw.n, max(m, m * target_s / max(dt, 1e-3))))
     if m2 > m:
@@ -402,7 +407,7 @@ def cpu_baseline(dw, mode, target_s):
         t0 = time.perf_counter()
         oracle.source_update(w.state, w.edges, w.chi_lo, alpha_chi=w.alpha_chi,
                              kappa_scale=w.kappa, mean_mode=mode, polish=1, n_threads=cores,
-                             **w.consts())
+                             **w.consts(), **w.topacity())
         dt = time.perf_counter() - t0
         m = m2
     return {"value": m / dt, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",

@@ -80,10 +80,22 @@ enum {
 
 /* Opacity description.  chi_0(nu) in group g is
  *   rho * kappa_scale[i] * chi_lo[g] * (nu / nu_g-)^alpha_chi[g]
- * (Sec. 2.2.2).  chi_lo, alpha_chi, chi_hi are DEVICE arrays of N_g entries;
- * when alpha_chi is NULL the index is ln(chi_hi/chi_lo)/ln(nu_g+/nu_g-)
- * (tabulated opacity).  PC ignores both and uses chi_lo as the group value.
- * kappa_scale is a DEVICE array of n_cells entries or NULL (= 1). */
+ *       * (T / t_ref)^t_exp * [1 - exp(-(h/k) nu / T)]^stim
+ * (Sec. 2.2.2; the temperature factors as in Sec. 4.1.2 simulation (c),
+ * t_exp = 3/2, and eq. pulsek, t_exp = -1/2 with stim = 1).  chi_lo,
+ * alpha_chi, chi_hi are DEVICE arrays of N_g entries; when alpha_chi is NULL
+ * the index is ln(chi_hi/chi_lo)/ln(nu_g+/nu_g-) (tabulated opacity).  PC
+ * ignores both and uses chi_lo as the group value.  kappa_scale is a DEVICE
+ * array of n_cells entries or NULL (= 1).
+ * Temperature dependence (t_exp != 0 or stim = 1): the opacities are
+ * evaluated at every Newton iterate's temperature and the Jacobian leaves
+ * out their T-derivatives (Sec. 3).  In the PPL modes the group's powerlaw
+ * passes through the T-dependent values at its two edges; PC takes the value
+ * at the lower edge.  t_exp must be finite, t_ref > 0 when t_exp != 0
+ * (MGRHD_E_TABLE otherwise), stim 0 or 1; with stim = 1 group_edges[0] must
+ * be > 0 (cells report MGRHD_ST_BAD_TABLE otherwise).  Zero-initialised
+ * fields give a T-independent opacity.  The batched entry points take
+ * T-independent tables only. */
 typedef struct {
   int32_t n_groups;
   int32_t mean_mode;
@@ -91,6 +103,10 @@ typedef struct {
   const double* alpha_chi;
   const double* chi_hi;
   const double* kappa_scale;
+  double t_exp;
+  double t_ref;
+  int32_t stim;
+  int32_t reserved;
 } mgrhd_opacity_params;
 
 /* Options; mgrhd_default_options() fills the paper's values. */
@@ -153,6 +169,16 @@ int mgrhd_get_variant(int32_t n_groups, int32_t mean_mode, int32_t* lanes_per_ce
                       int32_t* groups_per_lane, int32_t* waves_per_simd);
 int mgrhd_set_variant(int32_t n_groups, int32_t lanes_per_cell, int32_t groups_per_lane,
                       int32_t waves_per_simd);
+/* The mean-opacity method the paper recommends for a group structure
+ * (Sec. 4.1.3, after its Marshak-wave convergence study): PC when every
+ * group is narrower in ln nu than a tenth of the whole range ln(nu_max/nu_min),
+ * PPL with fixed slopes otherwise (which is also the choice for N_g <= 10
+ * log-uniform groups).  A grid that reaches 0 or +inf gets PC, the only
+ * method defined there.  edges: HOST array of n_groups + 1 ascending values.
+ * Returns MGRHD_MEAN_PC or MGRHD_MEAN_PPL_FIXED, or MGRHD_E_NULL / _SIZE /
+ * _TABLE (edges not ascending or negative). */
+int32_t mgrhd_recommend_mean_mode(int32_t n_groups, const double* edges);
+
 /* The compiled variants, k = 0 .. mgrhd_variant_count() - 1 (for autotuners). */
 int32_t mgrhd_variant_count(void);
 int mgrhd_variant_info(int32_t k, int32_t* lanes_per_cell, int32_t* groups_per_lane,

@@ -15,7 +15,7 @@ CSRC = os.path.join(PKG, "csrc")
 ARCH = os.environ.get("MGRHD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
-    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     # no packed FP32 instructions anywhere in this library
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     # keep loop-invariant FP64 constants (polynomial and exp coefficients) out of
@@ -25,7 +25,8 @@ HIPCC_FLAGS = [
 ]
 
 LIBS = {
-    "libmgrhd.so": ["source_update.hip", "batch.hip", "mlp.hip", "imex.hip"],
+    "libmgrhd.so": ["source_update.hip", "source_update_tdep.hip", "batch.hip", "mlp.hip",
+                    "imex.hip"],
     "libmgrhd_synth.so": ["synth.hip"],
 }
 
@@ -38,10 +39,24 @@ def hipcc() -> str:
 
 
 def build_lib(name: str, verbose: bool = True) -> str:
+    """Compile the library's sources to objects in parallel, then link."""
     srcs = [os.path.join(CSRC, s) for s in LIBS[name]]
     out = os.path.join(PKG, name)
+    objdir = os.path.join(PKG, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    procs = []
+    for src in srcs:
+        obj = os.path.join(objdir, os.path.basename(src) + ".o")
+        cmd = [hipcc(), *HIPCC_FLAGS, "-c", "-o", obj, src]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((obj, subprocess.Popen(cmd)))
+    failed = [obj for obj, pr in procs if pr.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, f"hipcc ({', '.join(failed)})")
     tmp = out + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-o", tmp, *srcs]
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp,
+           *[obj for obj, _ in procs]]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

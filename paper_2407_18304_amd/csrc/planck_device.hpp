@@ -84,9 +84,17 @@ struct Edge {
   double u;     // e^{-x} on the Wien side, else 1
   double val;   // P(x), or e^x Q(x) on the Wien side
   double eps;   // (15/pi^4) x^4/(e^x - 1), times e^x on the Wien side
+  double eb;    // x/(e^x - 1) below the Wien side (1 at x = 0)
   bool wien;    // x > kPlanckSplit
   bool inf;     // x = +inf
 };
+
+// 1 - e^{-x} of an edge (the stimulated-emission factor of an opacity): below
+// the Wien side x/(x + x/(e^x - 1)), with no exponential; beyond it 1 - u.
+// Needs x > 0 below the Wien side.
+__host__ __device__ __forceinline__ double stim_factor(const Edge& e) {
+  return e.wien ? 1.0 - e.u : e.x / (e.x + e.eb);
+}
 
 __host__ __device__ __forceinline__ Edge planck_edge(double x) {
   Edge e;
@@ -107,11 +115,14 @@ __host__ __device__ __forceinline__ Edge planck_edge(double x) {
     double ep = planck_ep(kEpDeg);
 #pragma unroll
     for (int k = kEpDeg - 1; k >= 0; --k) ep = fma_c(ep, y, planck_ep(k));
-    e.eps = kC15 * x3 * ((1.0 - 0.5 * x) + ep * y);
+    e.eb = (1.0 - 0.5 * x) + ep * y;
+    e.eps = kC15 * x3 * e.eb;
   } else if (e.inf) {
     e.val = 0.0;
     e.eps = 0.0;
+    e.eb = 0.0;
   } else {
+    e.eb = 0.0;
     // sum_k u^{k-1} (x^3/k + 3x^2/k^2 + 6x/k^3 + 6/k^4) as
     // x^3 S1(u) + 3x^2 S2(u) + 6x S3(u) + 6 S4(u), S_j(u) = sum_k u^{k-1}/k^j:
     // four Horner chains in u with constant coefficients 1/k^j
@@ -153,7 +164,8 @@ __host__ __device__ __forceinline__ Edge planck_edge_low(double x) {
     ep = fma_c(ep, y, planck_ep(k));
   }
   e.val = kC15 * x3 * ((1.0 / 3.0 - 0.125 * x) + ap * y);
-  e.eps = kC15 * x3 * ((1.0 - 0.5 * x) + ep * y);
+  e.eb = (1.0 - 0.5 * x) + ep * y;
+  e.eps = kC15 * x3 * e.eb;
   return e;
 }
 

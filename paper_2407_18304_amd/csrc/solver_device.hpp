@@ -44,6 +44,9 @@ struct KArgs {
   // derived on the host (set_derived): c/c_hat, c_hat/c, c_hat dt, 1/c^2,
   // 1/(c c_hat), c_hat dt / c^2
   double cc, icc, cdt, ic2, iccc, cdt_ic2;
+  // temperature dependence of the opacity: (T/T_ref)^t_exp [1 - e^{-x}]^stim
+  double t_exp, itref;  // itref = 1/T_ref
+  int32_t stim, pad;
 };
 
 // Fill the derived constants of a (host side).
@@ -193,6 +196,7 @@ __device__ __forceinline__ bool table_edge(const KArgs& a, Tables<NGM>& t, int g
   t.nu[g] = nu;
   bool ok = nu >= 0.0;
   if (MODE != MGRHD_MEAN_PC) ok = ok && nu > 0.0 && !is_pinf(nu);
+  if (a.stim && g == 0) ok = ok && nu > 0.0;  // 1 - e^{-x} vanishes at x = 0
   return ok;
 }
 
@@ -239,7 +243,8 @@ struct Cache {
   double chiF[G];  // flux mean (eq. chiDiff)
   double emit[G];  // chi_0B B~_g - Delta_g(nu chi_0 B~)/3  (flux source, eq. numF1)
   double chiB[G];  // PPL-free only (otherwise the per-cell constants)
-  double chiE[G];
+  double chiE[G];  // PPL-free, and every mode with a T-dependent opacity
+  double ac[G];    // opacity index at this temperature (T-dependent opacity only)
 };
 
 // Appendix A slopes of the lane's groups from ln Qbar (lq, per slot).  The
@@ -281,18 +286,35 @@ __device__ __forceinline__ Edge low_edge(const Edge& hi, const Edge& prev, int j
   return lo;
 }
 
+// Temperature dependence of the opacity at one evaluation: fT = (T/T_ref)^beta
+// and whether the stimulated-emission factor 1 - e^{-x} applies.
+struct OpacityT {
+  double fT;
+  bool stim;
+};
+
 // One material evaluation: Planck data, slopes (PPL-free), group means.
-// In PC and PPL-fixed chi_0E = chi_0B = rho kappa chk_g is fixed per cell.
-template <int G, int LPC, int MODE, int NGM>
+// Without temperature dependence (TD false) chi_0E = chi_0B = rho kappa chk_g
+// is fixed per cell in PC and PPL-fixed.  With it (TD), the opacity at the
+// group's lower edge is rho kappa chit_g fT [1 - e^{-x_g-}], and in the PPL
+// modes the group's index passes through the T-dependent values at both
+// edges, alpha_g + ln(s_g+/s_g-)/ln r_g, which makes r^alpha follow as
+// r^alpha_g s_g+/s_g-; the means of eq. chiQg are then taken at that index.
+template <int G, int LPC, int MODE, int NGM, bool TD = false>
 __device__ __forceinline__ void evaluate(const Tables<NGM>& t, int ng, int j, int lpc, double T,
                                          double aT4, double hk, double rho_kappa,
-                                         const double* Ecur, Cache<G>& c) {
+                                         const double* Ecur, Cache<G>& c,
+                                         OpacityT ot = OpacityT{1.0, false}) {
   const int n = LPC > 0 ? LPC : lpc;
   const double invT = 1.0 / T;
   const double hkT = hk * invT;
   Edge prev;
-  prev.x = prev.u = prev.val = prev.eps = 0.0;
+  prev.x = prev.u = prev.val = prev.eps = prev.eb = 0.0;
   if (j == n - 1) prev = planck_edge_low(hkT * t.nu[0]);  // edge 0, handed to lane 0
+  // stimulated-emission factor of the previous slot's high edge (edge 0 first)
+  double prev_s = 1.0;
+  if (TD && ot.stim && j == n - 1) prev_s = stim_factor(prev);
+  const bool last = j == n - 1;
   if (MODE != MGRHD_MEAN_PPL_FREE) {
 #pragma unroll
     for (int k = 0; k < G; ++k) {
@@ -300,35 +322,76 @@ __device__ __forceinline__ void evaluate(const Tables<NGM>& t, int ng, int j, in
       const Edge hi = planck_edge(hkT * t.nu[min(g + 1, ng)]);
       const Edge lo = low_edge<LPC>(hi, prev, j, lpc);
       prev = hi;
+      double s_lo = 1.0, s_hi = 1.0;
+      if (TD && ot.stim) {
+        s_hi = stim_factor(hi);
+        s_lo = from_left<LPC>(last ? prev_s : s_hi, lpc);
+        prev_s = s_hi;
+      }
       if (g >= ng) continue;
       const GroupPlanck p = group_planck(lo, hi);
       const double Bt = aT4 * p.b * p.scale;
       const double Dnu = aT4 * (p.ehi - p.elo) * p.scale;
       c.Bt[k] = Bt;
       c.dBdT[k] = (4.0 * Bt - Dnu) * invT;
-      const double ch = rho_kappa * t.chk[g];
-      if (MODE == MGRHD_MEAN_PC) {
-        c.chiF[k] = ch;
-        c.emit[k] = ch * (Bt - Dnu * kThird);
+      if (!TD) {
+        const double ch = rho_kappa * t.chk[g];
+        if (MODE == MGRHD_MEAN_PC) {
+          c.chiF[k] = ch;
+          c.emit[k] = ch * (Bt - Dnu * kThird);
+        } else {
+          const double ac = t.achi[g];
+          const double dchib = rho_kappa * t.chit[g] * (t.rac[g] * p.ehi - p.elo);
+          // eq. chiDiff with numerator and denominator both multiplied by 3
+          const double num = (4.0 + ac) * ch * p.b - dchib;
+          const double den = 4.0 * p.b - (p.ehi - p.elo);
+          const double f = num / den;
+          c.chiF[k] = (den > 0.0 && isfinite(f)) ? f : ch;
+          c.emit[k] = ch * Bt - aT4 * dchib * p.scale * kThird;
+        }
       } else {
-        const double ac = t.achi[g];
-        const double dchib = rho_kappa * t.chit[g] * (t.rac[g] * p.ehi - p.elo);
-        // eq. chiDiff with numerator and denominator both multiplied by 3
-        const double num = (4.0 + ac) * ch * p.b - dchib;
-        const double den = 4.0 * p.b - (p.ehi - p.elo);
-        const double f = num / den;
-        c.chiF[k] = (den > 0.0 && isfinite(f)) ? f : ch;
-        c.emit[k] = ch * Bt - aT4 * dchib * p.scale * kThird;
+        const double chl = rho_kappa * t.chit[g] * ot.fT * s_lo;  // chi_0,g- at T
+        if (MODE == MGRHD_MEAN_PC) {
+          c.chiE[k] = chl;
+          c.ac[k] = 0.0;
+          c.chiF[k] = chl;
+          c.emit[k] = chl * (Bt - Dnu * kThird);
+        } else {
+          double ac = t.achi[g], rac = t.rac[g], mr = t.mfix[g];
+          if (ot.stim) {
+            const double q = s_hi / s_lo;
+            ac += log(q) / t.lnr[g];
+            rac *= q;
+            mr = mean_ratio(ac, -1.0, t.lnr[g]);  // eq. chiQg, alpha_Q = -1
+          }
+          const double ch = chl * mr;
+          const double dchib = chl * (rac * p.ehi - p.elo);
+          const double num = (4.0 + ac) * ch * p.b - dchib;
+          const double den = 4.0 * p.b - (p.ehi - p.elo);
+          const double f = num / den;
+          c.chiE[k] = ch;
+          c.ac[k] = ac;
+          c.chiF[k] = (den > 0.0 && isfinite(f)) ? f : ch;
+          c.emit[k] = ch * Bt - aT4 * dchib * p.scale * kThird;
+        }
       }
     }
   } else {
     double b[G], elo[G], ehi[G], sig[G], scale[G], lqB[G], lqE[G], aB[G], aE[G];
+    double slo[G], sq[G];  // with TD: 1 - e^{-x} at the lower edge, and s_g+/s_g-
 #pragma unroll
     for (int k = 0; k < G; ++k) {
       const int g = gidx<LPC>(j, k, lpc);
       const Edge hi = planck_edge(hkT * t.nu[min(g + 1, ng)]);
       const Edge lo = low_edge<LPC>(hi, prev, j, lpc);
       prev = hi;
+      slo[k] = sq[k] = 1.0;
+      if (TD && ot.stim) {
+        const double s_hi = stim_factor(hi);
+        slo[k] = from_left<LPC>(last ? prev_s : s_hi, lpc);
+        prev_s = s_hi;
+        sq[k] = s_hi / slo[k];
+      }
       lqB[k] = -INFINITY;
       lqE[k] = -INFINITY;
       b[k] = elo[k] = ehi[k] = sig[k] = 0.0;
@@ -349,8 +412,16 @@ __device__ __forceinline__ void evaluate(const Tables<NGM>& t, int ng, int j, in
     for (int k = 0; k < G; ++k) {
       const int g = gidx<LPC>(j, k, lpc);
       if (g >= ng) continue;
-      const double ac = t.achi[g], L = t.lnr[g];
-      const double chl = rho_kappa * t.chit[g];
+      double ac = t.achi[g], rac = t.rac[g], chl = rho_kappa * t.chit[g];
+      const double L = t.lnr[g];
+      if (TD) {
+        chl *= ot.fT * slo[k];
+        if (ot.stim) {
+          ac += log(sq[k]) / L;
+          rac *= sq[k];
+        }
+        c.ac[k] = ac;
+      }
       const double Bt = aT4 * b[k] * scale[k];
       const double Dnu = aT4 * (ehi[k] - elo[k]) * scale[k];
       c.Bt[k] = Bt;
@@ -359,7 +430,7 @@ __device__ __forceinline__ void evaluate(const Tables<NGM>& t, int ng, int j, in
       const double chE = chl * mean_ratio(ac, aE[k], L);
       c.chiB[k] = chB;
       c.chiE[k] = chE;
-      const double dchib = chl * (t.rac[g] * ehi[k] - elo[k]);
+      const double dchib = chl * (rac * ehi[k] - elo[k]);
       const double num = (3.0 * chB + (1.0 + ac) * chE) * b[k] - dchib;  // both times 3
       const double den = 4.0 * b[k] - (ehi[k] - elo[k]);
       const double f = num / den;
@@ -415,9 +486,11 @@ struct CellState {
   double vF[G];        // v_k . F_g,k of the current outer pass
 };
 
-template <int G, int LPC, int MODE, int NGM, class LS>
+template <int G, int LPC, int MODE, int NGM, bool TD = false, class LS>
 __device__ __forceinline__ void load_cell(const KArgs& a, const Tables<NGM>& t, int j, int64_t i,
                                           CellState<G>& s, const LS& ls) {
+  // 1/tau_g and 1/J_gg are constants of the cell unless the means depend on T
+  constexpr bool kFixedTau = MODE != MGRHD_MEAN_PPL_FREE && !TD;
   const int64_t n = a.n;
   const int ng = a.ng;
   s.i = i;
@@ -462,7 +535,7 @@ __device__ __forceinline__ void load_cell(const KArgs& a, const Tables<NGM>& t, 
         ok = ok && isfinite(f[d]);
       }
       s.vF[k] = s.v[0] * f[0] + s.v[1] * f[1] + s.v[2] * f[2];
-      if (MODE != MGRHD_MEAN_PPL_FREE) {
+      if (kFixedTau) {
         it = 1.0 / (cdt * s.rho_kappa * t.chk[g]);
         ij = 1.0 / (-it - 1.0);
       }
@@ -472,7 +545,7 @@ __device__ __forceinline__ void load_cell(const KArgs& a, const Tables<NGM>& t, 
       ls.F(d, k) = f[d];
       if (LS::kKeep0) ls.F0(d, k) = f[d];
     }
-    if (MODE != MGRHD_MEAN_PPL_FREE) {
+    if (kFixedTau) {
       ls.itau(k) = it;
       ls.iJgg(k) = ij;
     }
@@ -583,7 +656,7 @@ __device__ __forceinline__ void newton_done(const KArgs& a, int j, CellState<G>&
 
 // Temperature-only start: at the cached material state, eq. Rnew inverted for
 // E_g and F_R,g = 0 (eq. FGFR) are linear in R_g alone; take that R_g.
-template <int G, int LPC, int MODE, int NGM, class LS>
+template <int G, int LPC, int MODE, int NGM, bool TD = false, class LS>
 __device__ __forceinline__ void group_balance(const KArgs& a, const Tables<NGM>& t, int j,
                                               CellState<G>& s, const LS& ls,
                                               const Cache<G>& c) {
@@ -595,13 +668,14 @@ __device__ __forceinline__ void group_balance(const KArgs& a, const Tables<NGM>&
     const int g = gidx<LPC>(j, k, s.lpc);
     if (g >= ng) continue;
     double ratio = 1.0, itau;
-    if (MODE == MGRHD_MEAN_PPL_FREE) {
-      ratio = c.chiB[k] / c.chiE[k];
+    if (MODE == MGRHD_MEAN_PPL_FREE || TD) {
+      if (MODE == MGRHD_MEAN_PPL_FREE) ratio = c.chiB[k] / c.chiE[k];
       itau = 1.0 / (cdt * c.chiE[k]);
     } else {
       itau = ls.itau(k);
     }
-    const double W = cdt * (1.0 + t.achi[g]) * c.chiF[k] * s.vF[k] * ic2;
+    const double ac = TD ? c.ac[k] : t.achi[g];
+    const double W = cdt * (1.0 + ac) * c.chiF[k] * s.vF[k] * ic2;
     s.R[k] = (ratio * c.Bt[k] + W * itau - s.E0[k]) / (1.0 + itau);
   }
   s.elim = false;
@@ -609,7 +683,7 @@ __device__ __forceinline__ void group_balance(const KArgs& a, const Tables<NGM>&
 
 // Newton consumer: residual of eq. FGFR at the cached material state, the
 // elimination of eq. matrix, and the step.
-template <int G, int LPC, int MODE, int NGM, class LS>
+template <int G, int LPC, int MODE, int NGM, bool TD = false, class LS>
 __device__ __forceinline__ void newton_step(const KArgs& a, const Tables<NGM>& t, int j,
                                             CellState<G>& s, const LS& ls,
                                             const Cache<G>& c) {
@@ -627,15 +701,16 @@ __device__ __forceinline__ void newton_step(const KArgs& a, const Tables<NGM>& t
     const int g = gidx<LPC>(j, k, s.lpc);
     if (g >= ng) continue;
     double ratio = 1.0, itau, iJgg;
-    if (MODE == MGRHD_MEAN_PPL_FREE) {
-      ratio = c.chiB[k] / c.chiE[k];
+    if (MODE == MGRHD_MEAN_PPL_FREE || TD) {
+      if (MODE == MGRHD_MEAN_PPL_FREE) ratio = c.chiB[k] / c.chiE[k];
       itau = 1.0 / (cdt * c.chiE[k]);
       iJgg = 1.0 / (-itau - 1.0);
     } else {
       itau = ls.itau(k);
       iJgg = ls.iJgg(k);
     }
-    const double W = cdt * (1.0 + t.achi[g]) * c.chiF[k] * s.vF[k] * ic2;  // eq. Rnew
+    const double ac = TD ? c.ac[k] : t.achi[g];
+    const double W = cdt * (1.0 + ac) * c.chiF[k] * s.vF[k] * ic2;  // eq. Rnew
     const double Eg = ratio * c.Bt[k] + (W - s.R[k]) * itau;  // eq. Rnew solved for E_g
     const double FR = Eg - s.E0[k] - s.R[k];
     const double Jg0 = ratio * c.dBdT[k] * ircv;               // eq. linear
@@ -682,7 +757,7 @@ __device__ __forceinline__ void newton_step(const KArgs& a, const Tables<NGM>& t
 // Outer-stage consumer: flux update eq. numF1 with the outdated velocity,
 // momentum update, outer test.  Returns true when the next inner pass starts
 // (at the same temperature, so the caller reuses this evaluation).
-template <int G, int LPC, int MODE, int NGM, class LS>
+template <int G, int LPC, int MODE, int NGM, bool TD = false, class LS>
 __device__ __forceinline__ bool flux_step(const KArgs& a, const Tables<NGM>& t, int j,
                                           CellState<G>& s, const LS& ls,
                                           const Cache<G>& c) {
@@ -695,11 +770,13 @@ __device__ __forceinline__ bool flux_step(const KArgs& a, const Tables<NGM>& t, 
     const int g = gidx<LPC>(j, k, s.lpc);
     if (g >= ng) continue;
     const double Enew = s.E0[k] + s.R[k];
-    const double chE = (MODE == MGRHD_MEAN_PPL_FREE) ? c.chiE[k] : s.rho_kappa * t.chk[g];
+    const double chE =
+        (MODE == MGRHD_MEAN_PPL_FREE || TD) ? c.chiE[k] : s.rho_kappa * t.chk[g];
+    const double ac = TD ? c.ac[k] : t.achi[g];
     double Pv[3];
     pressure_dot_v(a.closure, a.c, Enew, ls.F(0, k), ls.F(1, k), ls.F(2, k), s.v, Pv);
     const double iden = 1.0 / (1.0 + cdt * c.chiF[k]);
-    const double q = (1.0 + t.achi[g]) * chE;
+    const double q = (1.0 + ac) * chE;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const double f0 = LS::kKeep0 ? ls.F0(d, k) : a.F[((int64_t)d * ng + g) * n + i];  // F_g^(t)
@@ -723,7 +800,7 @@ __device__ __forceinline__ bool flux_step(const KArgs& a, const Tables<NGM>& t, 
     const int g = gidx<LPC>(j, k, s.lpc);
     if (g >= ng) continue;
     const double vf_new = vn[0] * ls.F(0, k) + vn[1] * ls.F(1, k) + vn[2] * ls.F(2, k);
-    dW += fabs((1.0 + t.achi[g]) * c.chiF[k] * (vf_new - s.vF[k]));
+    dW += fabs((1.0 + (TD ? c.ac[k] : t.achi[g])) * c.chiF[k] * (vf_new - s.vF[k]));
     s.vF[k] = vf_new;
   }
   dW = cell_sum<LPC>(dW, s.lpc) * a.cdt_ic2;
@@ -754,7 +831,7 @@ __device__ __forceinline__ bool flux_step(const KArgs& a, const Tables<NGM>& t, 
 // Newton step, or the flux/momentum update of the outer stage followed by the
 // first Newton step of the next pass at the same temperature).  Returns when
 // every cell is done.  Shared by the single-table and the batched kernels.
-template <int G, int LPC, int MODE, int NGM, class LS>
+template <int G, int LPC, int MODE, int NGM, bool TD = false, class LS>
 __device__ __forceinline__ void run_cells(const KArgs& a, const Tables<NGM>& tab, const LS& ls,
                                           int lane, int64_t lo, int64_t hi) {
   static_assert(LPC >= 1 && LPC <= kWave && (LPC & (LPC - 1)) == 0, "lanes per cell");
@@ -777,7 +854,7 @@ __device__ __forceinline__ void run_cells(const KArgs& a, const Tables<NGM>& tab
       mine = __shfl(mine, lane - j, kWave);
       if (need) {
         if (mine < hi) {
-          load_cell<G, LPC, MODE, NGM>(a, tab, j, mine, s, ls);
+          load_cell<G, LPC, MODE, NGM, TD>(a, tab, j, mine, s, ls);
           if (s.phase == P_EMPTY) finish_cell<G, LPC>(a, j, s, ls, false);
         } else {
           s.phase = P_IDLE;
@@ -805,14 +882,19 @@ __device__ __forceinline__ void run_cells(const KArgs& a, const Tables<NGM>& tab
 #pragma unroll
     for (int k = 0; k < G; ++k) Ecur[k] = s.E0[k] + s.R[k];
     const double aT4 = a.a * (T * T) * (T * T);
-    evaluate<G, LPC, MODE, NGM>(tab, a.ng, j, s.lpc, T, aT4, a.hk, s.rho_kappa, Ecur, c);
+    OpacityT ot{1.0, false};
+    if (TD) {
+      ot.fT = a.t_exp != 0.0 ? exp(a.t_exp * log(T * a.itref)) : 1.0;
+      ot.stim = a.stim != 0;
+    }
+    evaluate<G, LPC, MODE, NGM, TD>(tab, a.ng, j, s.lpc, T, aT4, a.hk, s.rho_kappa, Ecur, c, ot);
 
     if (s.phase == P_FLUX) {
-      if (!flux_step<G, LPC, MODE, NGM>(a, tab, j, s, ls, c)) continue;
+      if (!flux_step<G, LPC, MODE, NGM, TD>(a, tab, j, s, ls, c)) continue;
       // the next inner pass starts at this temperature: fall through
     }
-    if (s.elim) group_balance<G, LPC, MODE, NGM>(a, tab, j, s, ls, c);
-    newton_step<G, LPC, MODE, NGM>(a, tab, j, s, ls, c);
+    if (s.elim) group_balance<G, LPC, MODE, NGM, TD>(a, tab, j, s, ls, c);
+    newton_step<G, LPC, MODE, NGM, TD>(a, tab, j, s, ls, c);
   }
 }
 

@@ -1,0 +1,63 @@
+// solver_kernel.hpp -- the single-table source-update kernel and the list of
+// its compiled variants, shared by the two translation units that instantiate
+// it (T-independent opacity in source_update.hip, T-dependent opacity in
+// source_update_tdep.hip, so the two compile in parallel).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "solver_device.hpp"
+
+namespace mgrhd {
+
+// TD: the opacity depends on temperature (evaluated at every iterate)
+template <int G, int LPC, int MODE, int WPE, bool TD>
+__global__ __launch_bounds__(kBlock, WPE) void k_source_update(KArgs a) {
+  constexpr int NGM = G * LPC;
+  __shared__ Tables<NGM> tab;
+  using LS = LaneStore<G, true>;
+  __shared__ double lane_lds[LS::kSlots * kBlock];
+  const LS ls{lane_lds + threadIdx.x};
+  const bool table_ok = stage_tables<NGM, MODE>(a, tab);
+
+  const int lane = threadIdx.x % kWave;
+  const int64_t waves = (int64_t)gridDim.x * (kBlock / kWave);
+  const int64_t wave = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+  const int64_t lo = a.n * wave / waves, hi = a.n * (wave + 1) / waves;
+
+  if (!table_ok) {
+    // the table is unusable: report every cell of this wave's chunk
+    for (int64_t i = lo + lane; i < hi; i += kWave) {
+      if (a.status) a.status[i] = MGRHD_ST_BAD_TABLE;
+      if (a.iters) a.iters[i] = 0;
+      if (a.outer) a.outer[i] = 0;
+    }
+    return;
+  }
+
+  run_cells<G, LPC, MODE, NGM, TD>(a, tab, ls, lane, lo, hi);
+}
+
+using KernelFn = void (*)(KArgs);
+
+// (groups per lane, lanes per cell, minimum waves per SIMD) of every compiled
+// variant.  The first entry of each (lanes per cell, groups per lane) pair is
+// its default register budget; the others trade registers (spills) for waves.
+#define MGRHD_FOR_EACH_VARIANT(X)                                                 \
+  X(4, 1, 2) X(4, 2, 2) X(4, 4, 2) X(4, 8, 2) X(4, 16, 2) X(4, 32, 2) X(4, 64, 2) \
+  X(2, 2, 3) X(2, 4, 3) X(2, 8, 3) X(2, 16, 3) X(2, 32, 3)                        \
+  X(1, 4, 4) X(1, 8, 4) X(1, 16, 4) X(1, 32, 4) X(1, 64, 4)                       \
+  X(2, 8, 4) X(2, 32, 4)
+
+// the three mean modes of one variant
+#define MGRHD_VARIANT_MODES(G_, LPC_, WPE_, TD_)                                   \
+  {                                                                               \
+    k_source_update<G_, LPC_, MGRHD_MEAN_PC, WPE_, TD_>,                          \
+        k_source_update<G_, LPC_, MGRHD_MEAN_PPL_FIXED, WPE_, TD_>,               \
+        k_source_update<G_, LPC_, MGRHD_MEAN_PPL_FREE, WPE_, TD_>                 \
+  }
+
+// The kernels of variant k (in MGRHD_FOR_EACH_VARIANT order) for a
+// T-dependent opacity, by mean mode (source_update_tdep.hip).
+KernelFn tdep_kernel(int k, int mode);
+
+}  // namespace mgrhd

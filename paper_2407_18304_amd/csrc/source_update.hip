@@ -26,6 +26,7 @@
 // done.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -33,69 +34,32 @@
 
 #include "../../include/mgrhd.h"
 
-#include "solver_device.hpp"
+#include "solver_kernel.hpp"
 
 namespace mgrhd {
 
-template <int G, int LPC, int MODE, int WPE>
-__global__ __launch_bounds__(kBlock, WPE) void k_source_update(KArgs a) {
-  constexpr int NGM = G * LPC;
-  __shared__ Tables<NGM> tab;
-  using LS = LaneStore<G, true>;
-  __shared__ double lane_lds[LS::kSlots * kBlock];
-  const LS ls{lane_lds + threadIdx.x};
-  const bool table_ok = stage_tables<NGM, MODE>(a, tab);
-
-  const int lane = threadIdx.x % kWave;
-  const int64_t waves = (int64_t)gridDim.x * (kBlock / kWave);
-  const int64_t wave = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
-  const int64_t lo = a.n * wave / waves, hi = a.n * (wave + 1) / waves;
-
-  if (!table_ok) {
-    // the table is unusable: report every cell of this wave's chunk
-    for (int64_t i = lo + lane; i < hi; i += kWave) {
-      if (a.status) a.status[i] = MGRHD_ST_BAD_TABLE;
-      if (a.iters) a.iters[i] = 0;
-      if (a.outer) a.outer[i] = 0;
-    }
-    return;
-  }
-
-  run_cells<G, LPC, MODE, NGM>(a, tab, ls, lane, lo, hi);
-}
-
 // ---------------------------------------------------------------------------
 // Variant table
-using KernelFn = void (*)(KArgs);
-
 struct Variant {
   int lpc, g, wpe;  // lanes per cell, groups per lane, minimum waves per SIMD
-  KernelFn fn[3];
-  int blocks_per_cu[3];
+  KernelFn fn[2][3];  // [temperature-dependent opacity][mean mode]
+  int blocks_per_cu[2][3];
 };
 
-#define MGRHD_VARIANT(G_, LPC_, WPE_)                                             \
-  {                                                                               \
-    LPC_, G_, WPE_,                                                               \
-        {k_source_update<G_, LPC_, MGRHD_MEAN_PC, WPE_>,                          \
-         k_source_update<G_, LPC_, MGRHD_MEAN_PPL_FIXED, WPE_>,                   \
-         k_source_update<G_, LPC_, MGRHD_MEAN_PPL_FREE, WPE_>},                   \
-    {                                                                             \
-      0, 0, 0                                                                     \
-    }                                                                             \
-  }
+#define MGRHD_VARIANT(G_, LPC_, WPE_) \
+  {LPC_, G_, WPE_, {MGRHD_VARIANT_MODES(G_, LPC_, WPE_, false), {}}, {}},
+static Variant kVariants[] = {MGRHD_FOR_EACH_VARIANT(MGRHD_VARIANT)};
+#undef MGRHD_VARIANT
+constexpr int kNumVariants = (int)(sizeof(kVariants) / sizeof(kVariants[0]));
 
-// The first entry of each (lanes per cell, groups per lane) pair is its
-// default register budget; the others trade registers (spills) for waves.
-static Variant kVariants[] = {
-    MGRHD_VARIANT(4, 1, 2),  MGRHD_VARIANT(4, 2, 2),  MGRHD_VARIANT(4, 4, 2),
-    MGRHD_VARIANT(4, 8, 2),  MGRHD_VARIANT(4, 16, 2), MGRHD_VARIANT(4, 32, 2),
-    MGRHD_VARIANT(4, 64, 2), MGRHD_VARIANT(2, 2, 3),  MGRHD_VARIANT(2, 4, 3),
-    MGRHD_VARIANT(2, 8, 3),  MGRHD_VARIANT(2, 16, 3), MGRHD_VARIANT(2, 32, 3),
-    MGRHD_VARIANT(1, 4, 4),  MGRHD_VARIANT(1, 8, 4),  MGRHD_VARIANT(1, 16, 4),
-    MGRHD_VARIANT(1, 32, 4), MGRHD_VARIANT(1, 64, 4), MGRHD_VARIANT(2, 8, 4),
-    MGRHD_VARIANT(2, 32, 4),
-};
+// the T-dependent kernels come from their own translation unit
+static void link_tdep_kernels() {
+  static std::once_flag once;
+  std::call_once(once, [] {
+    for (int k = 0; k < kNumVariants; ++k)
+      for (int m = 0; m < 3; ++m) kVariants[k].fn[1][m] = tdep_kernel(k, m);
+  });
+}
 
 // user overrides per group count (0 = built-in choice)
 static int g_override_lpc[MGRHD_MAX_GROUPS + 1];
@@ -122,16 +86,17 @@ static Variant* choose_variant(int ng) {
 }
 
 // resident workgroups per CU of a variant (queried once)
-static int resident_blocks(Variant* v, int mode) {
+static int resident_blocks(Variant* v, int td, int mode) {
   std::lock_guard<std::mutex> lk(g_mutex);
-  if (v->blocks_per_cu[mode] == 0) {
+  if (v->blocks_per_cu[td][mode] == 0) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, v->fn[mode], kBlock, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, v->fn[td][mode], kBlock, 0) !=
+            hipSuccess ||
         nb < 1)
       nb = 1;
-    v->blocks_per_cu[mode] = nb;
+    v->blocks_per_cu[td][mode] = nb;
   }
-  return v->blocks_per_cu[mode];
+  return v->blocks_per_cu[td][mode];
 }
 
 static int num_cus() {
@@ -182,7 +147,21 @@ int mgrhd_get_variant(int32_t n_groups, int32_t mean_mode, int32_t* lpc, int32_t
   return 0;
 }
 
-int32_t mgrhd_variant_count(void) { return (int32_t)(sizeof(kVariants) / sizeof(kVariants[0])); }
+int32_t mgrhd_variant_count(void) { return kNumVariants; }
+
+int32_t mgrhd_recommend_mean_mode(int32_t n_groups, const double* edges) {
+  if (!edges) return MGRHD_E_NULL;
+  if (n_groups < 1 || n_groups > MGRHD_MAX_GROUPS) return MGRHD_E_SIZE;
+  for (int32_t g = 0; g < n_groups; ++g)
+    if (!(edges[g] >= 0.0) || !(edges[g + 1] > edges[g])) return MGRHD_E_TABLE;
+  // a grid reaching 0 or infinity has no finite log width: only PC is defined
+  if (!(edges[0] > 0.0) || !std::isfinite(edges[n_groups])) return MGRHD_MEAN_PC;
+  const double W = std::log(edges[n_groups] / edges[0]);
+  double widest = 0.0;
+  for (int32_t g = 0; g < n_groups; ++g)
+    widest = std::max(widest, std::log(edges[g + 1] / edges[g]));
+  return widest < 0.1 * W ? MGRHD_MEAN_PC : MGRHD_MEAN_PPL_FIXED;
+}
 
 int mgrhd_variant_info(int32_t k, int32_t* lpc, int32_t* gpl, int32_t* waves_per_simd) {
   if (k < 0 || k >= mgrhd_variant_count()) return MGRHD_E_OPTION;
@@ -230,9 +209,14 @@ int mgrhd_source_update(double* E_g, double* F_g, const double* rho, double* e_g
       opt->max_outer < 1 || opt->polish < 0 || opt->polish > 4 || opt->guess_kind < 0 ||
       opt->guess_kind > 1)
     return MGRHD_E_OPTION;
+  if (!std::isfinite(op->t_exp) || (op->t_exp != 0.0 && !pos(op->t_ref)) || op->stim < 0 ||
+      op->stim > 1)
+    return MGRHD_E_TABLE;
+  const int td = (op->t_exp != 0.0 || op->stim != 0) ? 1 : 0;
 
   Variant* var = choose_variant(ng);
   if (!var) return MGRHD_E_OPTION;
+  link_tdep_kernels();
 
   KArgs a;
   std::memset(&a, 0, sizeof(a));
@@ -266,14 +250,17 @@ int mgrhd_source_update(double* E_g, double* F_g, const double* rho, double* e_g
   a.max_newton = opt->max_newton;
   a.max_outer = opt->max_outer;
   a.polish = opt->polish;
+  a.t_exp = op->t_exp;
+  a.itref = op->t_exp != 0.0 ? 1.0 / op->t_ref : 1.0;
+  a.stim = op->stim;
   set_derived(a);
 
   // persistent grid: one resident wave of workgroups, never more workgroups
   // than there are cell groups to fill them
   const int64_t needed = (n_cells * var->lpc + kBlock - 1) / kBlock;
-  const int64_t resident = (int64_t)num_cus() * resident_blocks(var, op->mean_mode);
+  const int64_t resident = (int64_t)num_cus() * resident_blocks(var, td, op->mean_mode);
   const int64_t blocks = needed < resident ? needed : resident;
-  hipLaunchKernelGGL(var->fn[op->mean_mode], dim3((unsigned)blocks), dim3(kBlock), 0,
+  hipLaunchKernelGGL(var->fn[td][op->mean_mode], dim3((unsigned)blocks), dim3(kBlock), 0,
                      (hipStream_t)stream, a);
   const hipError_t err = hipGetLastError();
   return err == hipSuccess ? 0 : (int)err;

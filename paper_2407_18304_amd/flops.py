@@ -87,9 +87,27 @@ def unit_costs(w=W):
     # cell load: per group E0 (1), sum (1), v.F (5), 1/tau and 1/J_gg (3 + 2 div)
     ld_group = {PC: 10 + 2 * dv, FIXED: 10 + 2 * dv, FREE: 7}
     ld_cell = 2 + 7 + 2 + dv
+    # Temperature-dependent opacity, on top of the above.  Per evaluation and
+    # cell: (T/T_ref)^beta = exp(beta ln(T/T_ref)).  Per edge with the
+    # stimulated-emission factor: x/(x + x/(e^x-1)) below the Wien side, 1 - u
+    # beyond.  Per group: chi_0,g- at T (2 products, 3 with the factor); with
+    # the factor in PPL, the ratio s_g+/s_g-, the index change ln(ratio)/ln r,
+    # r^alpha times the ratio, and in PPL-fixed the mean of eq. chiQg at the
+    # new index (a y = aL, an expm1-bracket, a division, the rescaling exp of
+    # half the groups, the product).  Per Newton step and group: 1/tau and
+    # 1/J_gg (no longer per-cell constants); the cell load skips them.
+    td = dict(
+        ev_cell_pow=1 + lg + e + 1,
+        edge_stim={"nonwien": 1 + dv, "wien": 1},
+        ev_group={PC: 2, FIXED: 3, FREE: 2},
+        ev_group_stim={PC: 1, FIXED: 1 + dv + lg + dv + 1 + 1 + (1 + m1 + dv) + dv + e / 2,
+                       FREE: 1 + dv + lg + dv + 1 + 1},
+        nt_group={PC: 2 + 2 * dv, FIXED: 2 + 2 * dv, FREE: 0},
+        ld_group={PC: -(3 + 2 * dv), FIXED: -(3 + 2 * dv), FREE: 0},
+    )
     return dict(edge=edge, group=group, ev_group=ev_group, ev_cell=ev_cell,
                 nt_group=nt_group, nt_cell=nt_cell, fx_group=fx_group, fx_cell=fx_cell,
-                ld_group=ld_group, ld_cell=ld_cell)
+                ld_group=ld_group, ld_cell=ld_cell, td=td)
 
 
 UNIT = unit_costs()
@@ -124,9 +142,10 @@ def _searchsorted(xp, sorted_seq, v):
     return xp.searchsorted(sorted_seq, v.contiguous(), right=True)
 
 
-def flops_per_cell(ng, mode, iters, outer, mix, u=UNIT, valid=None):
+def flops_per_cell(ng, mode, iters, outer, mix, u=UNIT, valid=None, t_exp=0.0, stim=0):
     """FLOP-equivalents per cell (array).  iters, outer: the kernel's per-cell
-    counters; mix: edge_mix(...) of the cell's final temperature."""
+    counters; mix: edge_mix(...) of the cell's final temperature; t_exp, stim:
+    the opacity's temperature dependence."""
     e_le2, e_24, e_gt4, g_both, g_strad, g_wien, low0 = mix
     E = u["edge"]
     G = u["group"]
@@ -134,10 +153,22 @@ def flops_per_cell(ng, mode, iters, outer, mix, u=UNIT, valid=None):
                 g_both * G["both<=4"] + g_strad * G["straddle"] + g_wien * G["wien"] +
                 ng * u["ev_group"][mode] + u["ev_cell"] -
                 low0 * (E["x<=2"] - E["low"]))
+    tdep = t_exp != 0.0 or stim != 0
+    if tdep:
+        T = u["td"]
+        per_eval = per_eval + ng * T["ev_group"][mode]
+        if t_exp != 0.0:
+            per_eval = per_eval + T["ev_cell_pow"]
+        if stim:
+            per_eval = per_eval + ((e_le2 + e_24) * T["edge_stim"]["nonwien"] +
+                                   e_gt4 * T["edge_stim"]["wien"] +
+                                   ng * T["ev_group_stim"][mode])
     n_eval = iters + outer + 1
     n_newton = iters + outer
-    f = (n_eval * per_eval + n_newton * (ng * u["nt_group"][mode] + u["nt_cell"]) +
-         outer * (ng * u["fx_group"] + u["fx_cell"]) + ng * u["ld_group"][mode] + u["ld_cell"])
+    nt_group = u["nt_group"][mode] + (u["td"]["nt_group"][mode] if tdep else 0)
+    ld_group = u["ld_group"][mode] + (u["td"]["ld_group"][mode] if tdep else 0)
+    f = (n_eval * per_eval + n_newton * (ng * nt_group + u["nt_cell"]) +
+         outer * (ng * u["fx_group"] + u["fx_cell"]) + ng * ld_group + u["ld_cell"])
     if valid is not None:
         f = f * valid
     return f

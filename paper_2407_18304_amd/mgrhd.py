@@ -10,6 +10,8 @@ from __future__ import annotations
 import ctypes as C
 import os
 
+import numpy as np
+
 import torch
 
 PKG = os.path.dirname(os.path.abspath(__file__))
@@ -36,7 +38,9 @@ class MgrhdError(RuntimeError):
 
 class OpacityParams(C.Structure):
     _fields_ = [("n_groups", C.c_int32), ("mean_mode", C.c_int32), ("chi_lo", C.c_void_p),
-                ("alpha_chi", C.c_void_p), ("chi_hi", C.c_void_p), ("kappa_scale", C.c_void_p)]
+                ("alpha_chi", C.c_void_p), ("chi_hi", C.c_void_p), ("kappa_scale", C.c_void_p),
+                ("t_exp", C.c_double), ("t_ref", C.c_double), ("stim", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class Options(C.Structure):
@@ -52,6 +56,7 @@ _lib = None
 
 # exported symbols of include/mgrhd.h
 SYMBOLS = ["mgrhd_source_update", "mgrhd_default_options", "mgrhd_get_variant",
+           "mgrhd_recommend_mean_mode",
            "mgrhd_set_variant", "mgrhd_variant_count", "mgrhd_variant_info",
            "mgrhd_imex_workspace_bytes", "mgrhd_imex_step", "mgrhd_version"]
 
@@ -133,6 +138,19 @@ def variants():
     return out
 
 
+def recommend_mean_mode(edges) -> int:
+    """The paper's choice of mean-opacity method for a group structure
+    (mgrhd_recommend_mean_mode): MEAN_PC or MEAN_PPL_FIXED."""
+    e = np.ascontiguousarray(np.asarray(edges, dtype=np.float64))
+    L = lib()
+    L.mgrhd_recommend_mean_mode.restype = C.c_int32
+    L.mgrhd_recommend_mean_mode.argtypes = [C.c_int32, C.c_void_p]
+    rc = L.mgrhd_recommend_mean_mode(len(e) - 1, e.ctypes.data)
+    if rc < 0:
+        raise MgrhdError(rc, "mgrhd_recommend_mean_mode")
+    return rc
+
+
 def set_variant(n_groups: int, lanes_per_cell: int, groups_per_lane: int,
                 waves_per_simd: int = 0):
     rc = lib().mgrhd_set_variant(n_groups, lanes_per_cell, groups_per_lane, waves_per_simd)
@@ -145,11 +163,13 @@ def source_update(E_g, F_g, rho, e_gas, v, group_edges, chi_lo, *, dt, c_hat,
                   c=1.0, a_rad=1.0, h_over_k=1.0, c_v=1.5, eps_newton=1e-11, eps_outer=1e-13,
                   max_newton=100, max_outer=10, closure=CLOSURE_M1, polish=0, S_g=None,
                   guess=None, guess_kind=0, iters=None, outer=None, status=None, stream=None,
-                  imex_work=None):
+                  imex_work=None, t_exp=0.0, t_ref=1.0, stim=0):
     """In-place source update of the device state (see include/mgrhd.h).
     guess_kind 0: guess is [N_g+1, n] (E_gas, R_g); 1: guess is [n] (E_gas).
     imex_work: a device tensor of at least imex_workspace_bytes(n, N_g) bytes
-    turns the call into one two-stage IMEX step (mgrhd_imex_step)."""
+    turns the call into one two-stage IMEX step (mgrhd_imex_step).
+    t_exp, t_ref, stim: temperature dependence of the opacity,
+    (T/t_ref)^t_exp [1 - exp(-h nu / k T)]^stim."""
     ng, n = E_g.shape
     o = default_options()
     o.c, o.a_rad, o.h_over_k, o.c_v = c, a_rad, h_over_k, c_v
@@ -164,7 +184,8 @@ def source_update(E_g, F_g, rho, e_gas, v, group_edges, chi_lo, *, dt, c_hat,
     op = OpacityParams(ng, mean_mode, _ptr(chi_lo, (ng,), name="chi_lo"),
                        _ptr(alpha_chi, (ng,), name="alpha_chi"),
                        _ptr(chi_hi, (ng,), name="chi_hi"),
-                       _ptr(kappa_scale, (n,), name="kappa_scale"))
+                       _ptr(kappa_scale, (n,), name="kappa_scale"),
+                       float(t_exp), float(t_ref), int(stim), 0)
     if stream is None:
         stream = torch.cuda.current_stream(E_g.device).cuda_stream
     args = (_ptr(E_g, (ng, n), name="E_g"), _ptr(F_g, (3, ng, n), name="F_g"),

@@ -53,6 +53,9 @@ class DeviceWorkload:
     tables: dict         # device tensors edges, chi_lo, alpha
     c_v: float = 1.5
     h_over_k: float = 1.0
+    t_exp: float = 0.0   # temperature dependence of the opacity (see workloads)
+    t_ref: float = 1.0
+    stim: int = 0
 
     @property
     def ng(self):
@@ -61,6 +64,9 @@ class DeviceWorkload:
     def consts(self):
         return dict(dt=self.dt, c_hat=self.c_hat, c=self.c, a_rad=self.a_rad, c_v=self.c_v,
                     h_over_k=self.h_over_k)
+
+    def topacity(self):
+        return dict(t_exp=self.t_exp, t_ref=self.t_ref, stim=self.stim)
 
     def fill(self, cell0: int = 0, stream=None, seed=None):
         """(Re)generate the state in place: cells cell0 .. cell0+n-1, drawn with
@@ -101,7 +107,8 @@ def device_workload(name: str, n: int | None = None, cell0: int = 0, dev="cuda",
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
     dw = DeviceWorkload(name, n, edges, chi_lo, alpha, 1.0 / u["c"], u["c"], u["c"], u["a_rad"],
                         state, torch.empty(n, **f64), torch.empty(n, **f64),
-                        {"edges": t(edges), "chi_lo": t(chi_lo), "alpha": t(alpha)})
+                        {"edges": t(edges), "chi_lo": t(chi_lo), "alpha": t(alpha)},
+                        **W.spec_topacity(name))
     dw.fill(cell0, seed=seed)
     return dw
 
@@ -115,7 +122,7 @@ def to_host(dw: DeviceWorkload, idx) -> W.Workload:
     st = {k: np.ascontiguousarray(v.cpu().numpy()) for k, v in st.items()}
     return W.Workload(dw.name, len(idx), dw.edges, dw.chi_lo, dw.alpha_chi,
                       dw.kappa[idx_t].cpu().numpy(), st, dw.T[idx_t].cpu().numpy(), dt=dw.dt,
-                      c_hat=dw.c_hat, c=dw.c, a_rad=dw.a_rad)
+                      c_hat=dw.c_hat, c=dw.c, a_rad=dw.a_rad, **dw.topacity())
 
 
 @dataclasses.dataclass

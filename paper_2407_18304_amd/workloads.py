@@ -30,6 +30,9 @@ Workloads (dimensionless, h/k = 1 so x = nu/T, rho = 1, c_v = 3/2):
   nu = 1 of 10^U(-3, 6) per cell, table as config1, v/c as config0.
 * ``patches``: AMR-like patches (cube sides {8,16,32,64}, N_g {8,16,32,64}),
   each with its own edges over [10^U(-3.5,-2.5), 10^U(2.5,3.5)] and table.
+* ``config5``: config1's cells and state recipe with the temperature-dependent
+  opacity of the paper's pulse test (eq. pulsek): chi^ = (nu/4.8)^-3 over 16
+  groups on [4.8e-3, 48], times (T/1)^(-1/2) [1 - e^{-nu/T}], v/c as config0.
 
 The speed of light c and the radiation constant a_R are per-workload unit
 choices; see ``UNITS``.
@@ -64,6 +67,7 @@ UNITS = {
     "config1": dict(c=1.0e3, a_rad=1.0),
     "config2": dict(c=1.0e3, a_rad=1.0e-4),
     "patches": dict(c=1.0e3, a_rad=1.0e-4),
+    "config5": dict(c=1.0e3, a_rad=1.0),
 }
 
 
@@ -142,6 +146,10 @@ class Workload:
     a_rad: float
     c_v: float = 1.5
     h_over_k: float = 1.0
+    # temperature dependence of the opacity: (T/t_ref)^t_exp [1 - e^{-x}]^stim
+    t_exp: float = 0.0
+    t_ref: float = 1.0
+    stim: int = 0
 
     @property
     def ng(self):
@@ -150,6 +158,9 @@ class Workload:
     def consts(self):
         return dict(dt=self.dt, c_hat=self.c_hat, c=self.c, a_rad=self.a_rad,
                     c_v=self.c_v, h_over_k=self.h_over_k)
+
+    def topacity(self):
+        return dict(t_exp=self.t_exp, t_ref=self.t_ref, stim=self.stim)
 
 
 def log_edges(lo, hi, ng):
@@ -210,17 +221,29 @@ SPECS = {
                     t_p=(0.0, 0.5), k_kind=0, k_p=(1e-2, 1e2), vmax=1e-2),
     "config2": dict(seed=BASE_SEED + 2, n=256 ** 3, ng=64, table="random", t_kind=1,
                     t_p=(-1.5, 1.5), k_kind=1, k_p=(-3.0, 6.0), vmax=1e-3),
+    # the opacity of eq. pulsek: chi^ ~ nu^-3, times (T/T_ref)^(-1/2) and the
+    # stimulated-emission factor; 16 groups over four decades of x at T = 1
+    # (the paper's 10^15 - 10^19 Hz at 10^7 K), nu^-3 anchored at x = 4.8
+    # (10^18 Hz at 10^7 K)
+    "config5": dict(seed=BASE_SEED + 5, n=128 ** 3, ng=16, table="pulse", t_kind=0,
+                    t_p=(0.0, 0.5), k_kind=0, k_p=(1e-2, 1e2), vmax=1e-3,
+                    nu_range=(4.8e-3, 48.0), t_exp=-0.5, t_ref=1.0, stim=1),
 }
 TRAD_RANGE = (0.5, 2.0)
+
+
+PULSE_NU = 4.8   # anchor of the nu^-3 opacity of eq. pulsek (x at 10^18 Hz, 10^7 K)
 
 
 def spec_tables(name, ng=None, seed=None):
     sp = SPECS[name]
     ng = ng or sp["ng"]
     seed = sp["seed"] if seed is None else seed
-    edges = log_edges(1e-3, 1e3, ng)
+    edges = log_edges(*sp.get("nu_range", (1e-3, 1e3)), ng)
     if sp["table"] == "nu^-2":
         return edges, edges[:-1] ** -2.0, np.full(ng, -2.0)
+    if sp["table"] == "pulse":
+        return edges, (edges[:-1] / PULSE_NU) ** -3.0, np.full(ng, -3.0)
     chi_lo, alpha = random_table(seed, edges)
     return edges, chi_lo, alpha
 
@@ -254,7 +277,16 @@ def make(name, cells=None, seed=None, n=None, ng=None, units=None):
     kappa = draw_kappa(name, cells, seed, dt, u["c"])
     st = _state(seed, cells, edges, T, *TRAD_RANGE, sp["vmax"], u["c"], u["a_rad"])
     return Workload(name, cells.size, edges, chi_lo, alpha, kappa, st, T, dt=dt, c_hat=u["c"],
-                    **u)
+                    **u, **spec_topacity(name))
+
+
+def spec_topacity(name):
+    sp = SPECS[name]
+    return dict(t_exp=sp.get("t_exp", 0.0), t_ref=sp.get("t_ref", 1.0), stim=sp.get("stim", 0))
+
+
+def config5(cells=None, seed=None, n=None):
+    return make("config5", cells, seed, n)
 
 
 def config0(cells=None, seed=None, n=None):

@@ -41,7 +41,7 @@ def run_gpu(w, mode, *, polish=1, closure=0, max_outer=10, max_newton=100, eps_n
                         max_outer=max_outer, max_newton=max_newton, eps_newton=eps_newton,
                         guess=None if guess is None else t(guess), guess_kind=guess_kind,
                         S_g=None if S_g is None else t(S_g), iters=iters, outer=outer,
-                        status=status)
+                        status=status, **w.topacity())
     torch.cuda.synchronize()
     out = {k: st[k].cpu().numpy() for k in st}
     return out, iters.cpu().numpy(), outer.cpu().numpy(), status.cpu().numpy()
@@ -53,7 +53,7 @@ def run_oracle(w, mode, *, polish=1, closure=0, max_outer=10, max_newton=100, ep
                                 kappa_scale=w.kappa, mean_mode=mode, polish=polish,
                                 closure=closure, max_outer=max_outer, max_newton=max_newton,
                                 eps_newton=eps_newton, guess=guess, guess_kind=guess_kind,
-                                S_g=S_g, **w.consts())
+                                S_g=S_g, **w.consts(), **w.topacity())
 
 
 def field_errors(w, gpu, ora, mask=None):
@@ -126,3 +126,41 @@ def compare(w, gpu, ref, label="", tol=TOL, tol_flip=TOL_COUNT_FLIP):
         a, b = g[k].reshape(-1, w.n)[:, inv], w.state[k].reshape(-1, w.n)[:, inv]
         assert np.array_equal(a, b), (label, k)
     return g, gs
+
+
+def full_size_sampled(name, mode, n_sample, seed):
+    """Draw the whole workload ``name`` on the device, solve it in place with
+    the benchmark's launch configuration (the autotuner's cached variant for
+    this GPU), and compare ``n_sample`` random cells with the oracle run on
+    the same (device-drawn) inputs."""
+    from paper_2407_18304_amd import autotune, synth
+    dw = synth.device_workload(name)
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(dw.n, n_sample, replace=False))
+    host = synth.to_host(dw, idx)                        # pristine inputs of the sample
+    cache = autotune.apply_cache(mode=mode)
+    try:
+        n = dw.n
+        iters = torch.zeros(n, dtype=torch.int32, device="cuda")
+        outer = torch.zeros(n, dtype=torch.int32, device="cuda")
+        status = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+        s = dw.state
+        mgrhd.source_update(s["E_g"], s["F_g"], s["rho"], s["e_gas"], s["v"],
+                            dw.tables["edges"], dw.tables["chi_lo"], mean_mode=mode,
+                            alpha_chi=dw.tables["alpha"], kappa_scale=dw.kappa, polish=1,
+                            iters=iters, outer=outer, status=status, **dw.consts(),
+                            **dw.topacity())
+        torch.cuda.synchronize()
+        assert bool((status >= 0).all())
+        it = torch.as_tensor(idx, device="cuda")
+        gpu = ({"E_g": s["E_g"][:, it].cpu().numpy(), "F_g": s["F_g"][:, :, it].cpu().numpy(),
+                "e_gas": s["e_gas"][it].cpu().numpy(), "v": s["v"][:, it].cpu().numpy()},
+               iters[it].cpu().numpy(), outer[it].cpu().numpy(), status[it].cpu().numpy())
+    finally:
+        for key in cache.get("single", {}):
+            mgrhd.set_variant(int(key.split(":")[0]), 0, 0)
+        del dw
+        torch.cuda.empty_cache()
+    compare(host, gpu, run_oracle(host, mode),
+            label=f"{name} full size, {n_sample} sampled cells, mode {mode}")
+    return idx, host

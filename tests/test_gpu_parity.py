@@ -45,6 +45,15 @@ def test_parity_config2_sample(mode):
     _check(w, mode)
 
 
+@pytest.mark.parametrize("name,mode,n_sample", [("config1", 1, 600), ("config1", 2, 300),
+                                                 ("config2", 1, 200)])
+def test_parity_full_size_sampled(name, mode, n_sample):
+    """The benchmark's workloads at their full sizes (128^3 x 16 and 256^3 x 64
+    groups), drawn on the device and solved in the benchmark's launch
+    configuration; sampled cells against the oracle on the same inputs."""
+    U.full_size_sampled(name, mode, n_sample, seed=3)
+
+
 @pytest.mark.parametrize("ng", [1, 3, 5, 7, 13, 33, 100])
 def test_parity_ragged_group_counts(ng):
     """Group counts that leave lanes partly empty and span several lanes."""
