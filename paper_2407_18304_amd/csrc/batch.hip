@@ -92,14 +92,14 @@ __device__ __forceinline__ void run_item(const KArgs& a, const Tables<NGM>& tab,
   int lpc = 1;
   while (lpc * G < a.ng) lpc <<= 1;
   switch (lpc) {
-    case 1: run_cells<G, 1, MODE, NGM>(a, tab, ls, lane, c0, c1); break;
-    case 2: run_cells<G, 2, MODE, NGM>(a, tab, ls, lane, c0, c1); break;
-    case 4: run_cells<G, 4, MODE, NGM>(a, tab, ls, lane, c0, c1); break;
-    case 8: run_cells<G, 8, MODE, NGM>(a, tab, ls, lane, c0, c1); break;
-    case 16: run_cells<G, 16, MODE, NGM>(a, tab, ls, lane, c0, c1); break;
-    case 32: run_cells<G, 32, MODE, NGM>(a, tab, ls, lane, c0, c1); break;
+    case 1: run_cells<G, 1, MODE, NGM>(a, tab, ls, lane, WaveRange{c0, c1}); break;
+    case 2: run_cells<G, 2, MODE, NGM>(a, tab, ls, lane, WaveRange{c0, c1}); break;
+    case 4: run_cells<G, 4, MODE, NGM>(a, tab, ls, lane, WaveRange{c0, c1}); break;
+    case 8: run_cells<G, 8, MODE, NGM>(a, tab, ls, lane, WaveRange{c0, c1}); break;
+    case 16: run_cells<G, 16, MODE, NGM>(a, tab, ls, lane, WaveRange{c0, c1}); break;
+    case 32: run_cells<G, 32, MODE, NGM>(a, tab, ls, lane, WaveRange{c0, c1}); break;
     default:  // a patch wider than 32 lanes of G groups
-      if constexpr (G * 32 < NGM) run_cells<G, kWave, MODE, NGM>(a, tab, ls, lane, c0, c1);
+      if constexpr (G * 32 < NGM) run_cells<G, kWave, MODE, NGM>(a, tab, ls, lane, WaveRange{c0, c1});
       break;
   }
 }

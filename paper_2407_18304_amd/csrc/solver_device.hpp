@@ -831,9 +831,33 @@ __device__ __forceinline__ bool flux_step(const KArgs& a, const Tables<NGM>& t, 
 // Newton step, or the flux/momentum update of the outer stage followed by the
 // first Newton step of the next pass at the same temperature).  Returns when
 // every cell is done.  Shared by the single-table and the batched kernels.
-template <int G, int LPC, int MODE, int NGM, bool TD = false, class LS>
+// Where a wave takes its next cells from.  WaveRange: the cells [lo, hi)
+// belong to this wave alone.  BlockQueue: the waves of a workgroup share the
+// range through a counter in LDS, so the cells in flight in a workgroup stay
+// within a narrow window of consecutive cells and share the cache lines of
+// every SoA row between them.
+struct WaveRange {
+  int64_t next, hi;
+  __device__ __forceinline__ int64_t take(int count) {  // wave-uniform
+    const int64_t base = next;
+    next += count;
+    return base;
+  }
+};
+
+struct BlockQueue {
+  int* counter;  // LDS, zeroed before the first take
+  int64_t lo, hi;
+  __device__ __forceinline__ int64_t take(int count) {  // all lanes active
+    int base = 0;
+    if (__lane_id() == 0) base = atomicAdd(counter, count);
+    return lo + __builtin_amdgcn_readfirstlane(base);
+  }
+};
+
+template <int G, int LPC, int MODE, int NGM, bool TD = false, class LS, class Q>
 __device__ __forceinline__ void run_cells(const KArgs& a, const Tables<NGM>& tab, const LS& ls,
-                                          int lane, int64_t lo, int64_t hi) {
+                                          int lane, Q q) {
   static_assert(LPC >= 1 && LPC <= kWave && (LPC & (LPC - 1)) == 0, "lanes per cell");
   const int j = lane % LPC;
   CellState<G> s;
@@ -841,16 +865,15 @@ __device__ __forceinline__ void run_cells(const KArgs& a, const Tables<NGM>& tab
   s.i = -1;
   s.lpc = LPC;
   Cache<G> c;
-  int64_t next = lo;  // wave-uniform queue position
+  const int64_t hi = q.hi;
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
   for (;;) {
-    // refill: every cell group without a cell takes the next one of the range
+    // refill: every cell group without a cell takes the next one of the queue
     const bool need = s.phase == P_EMPTY;
     const uint64_t m = __ballot(need && j == 0);
     if (m) {
       const int rank = __popcll(m & below);
-      int64_t mine = next + rank;
-      next += __popcll(m);
+      int64_t mine = q.take(__popcll(m)) + rank;
       mine = __shfl(mine, lane - j, kWave);
       if (need) {
         if (mine < hi) {

@@ -17,16 +17,17 @@ __global__ __launch_bounds__(kBlock, WPE) void k_source_update(KArgs a) {
   using LS = LaneStore<G, true>;
   __shared__ double lane_lds[LS::kSlots * kBlock];
   const LS ls{lane_lds + threadIdx.x};
-  const bool table_ok = stage_tables<NGM, MODE>(a, tab);
+  __shared__ int taken;  // cells of this workgroup's range handed out so far
+  if (threadIdx.x == 0) taken = 0;
+  const bool table_ok = stage_tables<NGM, MODE>(a, tab);  // (its barriers publish `taken`)
 
   const int lane = threadIdx.x % kWave;
-  const int64_t waves = (int64_t)gridDim.x * (kBlock / kWave);
-  const int64_t wave = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
-  const int64_t lo = a.n * wave / waves, hi = a.n * (wave + 1) / waves;
+  // each workgroup owns a contiguous range of cells, shared by its waves
+  const int64_t lo = a.n * blockIdx.x / gridDim.x, hi = a.n * (blockIdx.x + 1) / gridDim.x;
 
   if (!table_ok) {
-    // the table is unusable: report every cell of this wave's chunk
-    for (int64_t i = lo + lane; i < hi; i += kWave) {
+    // the table is unusable: report every cell of this workgroup's range
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
       if (a.status) a.status[i] = MGRHD_ST_BAD_TABLE;
       if (a.iters) a.iters[i] = 0;
       if (a.outer) a.outer[i] = 0;
@@ -34,7 +35,7 @@ __global__ __launch_bounds__(kBlock, WPE) void k_source_update(KArgs a) {
     return;
   }
 
-  run_cells<G, LPC, MODE, NGM, TD>(a, tab, ls, lane, lo, hi);
+  run_cells<G, LPC, MODE, NGM, TD>(a, tab, ls, lane, BlockQueue{&taken, lo, hi});
 }
 
 using KernelFn = void (*)(KArgs);
