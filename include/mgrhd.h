@@ -201,6 +201,36 @@ int mgrhd_imex_step(double* E_g, double* F_g, const double* rho, double* e_gas, 
                     mgrhd_stream_t stream, const mgrhd_options* opt, void* work,
                     size_t work_bytes);
 
+/* ---- Explicit stage of the IMEX integrator for a 1D column (Sec. 2.3) ----
+ * One launch writes, for every cell i of a 1D column and every group g,
+ *   out = a U0 + b U1 + dt_T T(U1)   (E_g, F_g)
+ *   out = a U0 + b U1                (e_gas, v)
+ * where T is the M1 transport of eq. ysf along x: dE_g/dt = -(c_hat/c) dF_g/dx,
+ * dF_g/dt = -c_hat c dP_g/dx, P_g = chi(f) E_g with Levermore's M1 factor,
+ * f = |F_g|/(c E_g) clipped to 1, in finite volumes with the local
+ * Lax-Friedrichs flux (wave speeds -+c_hat) at each face; the energy flux's
+ * dissipation is scaled by min(1, 1/tau)^2, tau = dx (chi_L + chi_R)/2 with
+ * chi_i = rho[i] chi_mid[g].  Ghost cells: E_left[g], E_right[g], zero flux.
+ * Only the x-components of F_g move; y and z are combined as the gas is.
+ * Stage 1 of eqs. imex1/imex2 is (a, b, dt_T) = (0, 1, dt) with U1 = U^n;
+ * stage 2 is (1/2, 1/2, dt/2) with U0 = U^n, U1 = U^(n+1/2); each is followed
+ * by mgrhd_source_update with theta dt = dt_T * (stage 1: 1, stage 2: 1).
+ * Layout as mgrhd_source_update (SoA, cell index fastest); all arrays are
+ * DEVICE arrays: E [N_g][n], F [3][N_g][n], e_gas [n], v [3][n], rho [n],
+ * chi_mid, E_left, E_right [N_g].  U0 may be NULL when a = 0.  The outputs
+ * may alias U0 but not U1 (the stencil reads U1's neighbours;
+ * MGRHD_E_OPTION if E_out == E1 or F_out == F1).  Returns 0, MGRHD_E_NULL,
+ * MGRHD_E_SIZE, MGRHD_E_SCALAR (dx, c, c_hat not positive, dt_T < 0), or a
+ * HIP error from the launch. */
+int mgrhd_transport1d_stage(double* E_out, double* F_out, double* e_gas_out, double* v_out,
+                            const double* E1, const double* F1, const double* e_gas1,
+                            const double* v1, const double* E0, const double* F0,
+                            const double* e_gas0, const double* v0, double a, double b,
+                            int64_t n_cells, int32_t n_groups, double dx, double dt_T, double c,
+                            double c_hat, const double* rho, const double* chi_mid,
+                            const double* E_left, const double* E_right,
+                            mgrhd_stream_t stream);
+
 /* ---- Batched AMR-like patches: one persistent launch over many patches ----
  * Each patch holds its own SoA block (same layout as mgrhd_source_update,
  * with its own n_cells), its own group count (1..128), edges and opacity

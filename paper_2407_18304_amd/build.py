@@ -26,7 +26,7 @@ HIPCC_FLAGS = [
 
 LIBS = {
     "libmgrhd.so": ["source_update.hip", "source_update_tdep.hip", "batch.hip", "mlp.hip",
-                    "imex.hip"],
+                    "imex.hip", "transport1d.hip"],
     "libmgrhd_synth.so": ["synth.hip"],
 }
 

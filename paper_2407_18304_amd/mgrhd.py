@@ -58,7 +58,8 @@ _lib = None
 SYMBOLS = ["mgrhd_source_update", "mgrhd_default_options", "mgrhd_get_variant",
            "mgrhd_recommend_mean_mode",
            "mgrhd_set_variant", "mgrhd_variant_count", "mgrhd_variant_info",
-           "mgrhd_imex_workspace_bytes", "mgrhd_imex_step", "mgrhd_version"]
+           "mgrhd_imex_workspace_bytes", "mgrhd_imex_step", "mgrhd_version",
+           "mgrhd_transport1d_stage"]
 
 
 def lib():
@@ -122,6 +123,33 @@ def get_variant(n_groups: int, mean_mode: int = MEAN_PPL_FIXED):
     if rc:
         raise MgrhdError(rc, "mgrhd_get_variant")
     return lpc.value, gpl.value, wps.value
+
+
+def transport1d_stage(out, U1, U0, *, a, b, dx, dt_T, c, c_hat, rho, chi_mid, E_left,
+                      E_right, stream=None):
+    """out = a U0 + b U1 + dt_T T(U1) for a 1D column (mgrhd_transport1d_stage).
+    out, U1, U0: dicts of device tensors E_g [N_g, n], F_g [3, N_g, n],
+    e_gas [n], v [3, n]; U0 may be None when a == 0."""
+    ng, n = U1["E_g"].shape
+    L = lib()
+    f = L.mgrhd_transport1d_stage
+    f.restype = C.c_int
+    f.argtypes = [C.c_void_p] * 12 + [C.c_double, C.c_double, C.c_int64, C.c_int32,
+                                      C.c_double, C.c_double, C.c_double, C.c_double,
+                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.c_void_p]
+    shapes = {"E_g": (ng, n), "F_g": (3, ng, n), "e_gas": (n,), "v": (3, n)}
+    keys = ("E_g", "F_g", "e_gas", "v")
+    po = [_ptr(out[k], shapes[k], name=k) for k in keys]
+    p1 = [_ptr(U1[k], shapes[k], name=k) for k in keys]
+    p0 = [_ptr(U0[k], shapes[k], name=k) if U0 is not None else None for k in keys]
+    if stream is None:
+        stream = torch.cuda.current_stream(U1["E_g"].device).cuda_stream
+    rc = f(*po, *p1, *p0, float(a), float(b), n, ng, float(dx), float(dt_T), float(c),
+           float(c_hat), _ptr(rho, (n,), name="rho"), _ptr(chi_mid, (ng,), name="chi_mid"),
+           _ptr(E_left, (ng,), name="E_left"), _ptr(E_right, (ng,), name="E_right"), stream)
+    if rc != 0:
+        raise MgrhdError(rc, "mgrhd_transport1d_stage")
 
 
 def imex_workspace_bytes(n_cells: int, n_groups: int) -> int:

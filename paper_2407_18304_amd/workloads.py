@@ -362,3 +362,66 @@ def subset(w: Workload, idx) -> Workload:
           "v": np.ascontiguousarray(w.state["v"][:, idx])}
     return dataclasses.replace(w, n=idx.size, kappa=np.ascontiguousarray(w.kappa[idx]),
                                state=st, T=np.ascontiguousarray(w.T[idx]))
+
+
+# ---------------------------------------------------------------------------
+# 1D Marshak wave with a continuously frequency-dependent opacity (Sec. 4.1.3,
+# on the setup of Sec. 4.1.2): cgs units, gas at rest, rho = 1e-3 g cm^-3,
+# rho C_v = 1e-3 erg cm^-3 K^-1, T = 300 K in equilibrium with the radiation,
+# chi_0 = 3.2e4 (nu / 1e13 Hz)^-2 cm^-1, groups log-spaced over
+# [6e10, 6e14] Hz, boundary radiation black body at 1000 K (left) and 300 K
+# (right) with zero flux, domain [0, 20] cm, 500 cells, t_end = 1.36e-7 s.
+CGS = dict(c=2.99792458e10, a_rad=7.5657e-15, h_over_k=4.799243e-11)
+MARSHAK = dict(length=20.0, n_cells=500, rho=1e-3, rho_cv=1e-3, T0=300.0, T_left=1000.0,
+               T_right=300.0, chi0=3.2e4, nu0=1e13, chi_index=-2.0, nu_lo=6e10, nu_hi=6e14,
+               t_end=1.36e-7, cfl=0.5)
+
+
+@dataclasses.dataclass
+class Marshak:
+    """Inputs of the 1D Marshak problem with N_g groups (host arrays)."""
+    ng: int
+    n: int
+    dx: float
+    edges: np.ndarray       # [N_g+1] Hz
+    chi_lo: np.ndarray      # [N_g] opacity at lower edges per unit rho (cm^2 g^-1)
+    alpha_chi: np.ndarray   # [N_g]
+    chi_mid: np.ndarray     # [N_g] opacity per unit rho at each group's log-centre
+    state: dict             # E_g [N_g,n], F_g [3,N_g,n], rho [n], e_gas [n], v [3,n]
+    E_left: np.ndarray      # [N_g] boundary radiation energy densities
+    E_right: np.ndarray
+    dt: float
+    t_end: float
+    c: float
+    a_rad: float
+    h_over_k: float
+    c_v: float
+
+    def consts(self):
+        return dict(c=self.c, a_rad=self.a_rad, h_over_k=self.h_over_k, c_v=self.c_v)
+
+
+def marshak(ng, n_cells=None, cfl=None):
+    m = MARSHAK
+    n = n_cells or m["n_cells"]
+    dx = m["length"] / n
+    u = CGS
+    edges = np.logspace(math.log10(m["nu_lo"]), math.log10(m["nu_hi"]), ng + 1)
+    # chi_0(nu) = chi0 (nu / nu0)^index, per unit rho
+    per_rho = m["chi0"] / m["rho"]
+    chi_lo = per_rho * (edges[:-1] / m["nu0"]) ** m["chi_index"]
+    chi_mid = per_rho * (np.sqrt(edges[:-1] * edges[1:]) / m["nu0"]) ** m["chi_index"]
+    alpha = np.full(ng, m["chi_index"])
+    # black-body group energies in frequency: x = (h/k) nu / T
+    def bb(T):
+        return planck_group_energy(np.array([T]), edges * u["h_over_k"], u["a_rad"])[:, 0]
+    c_v = m["rho_cv"] / m["rho"]
+    E = np.repeat(bb(m["T0"])[:, None], n, axis=1)
+    rho = np.full(n, m["rho"])
+    st = {"E_g": np.ascontiguousarray(E), "F_g": np.zeros((3, ng, n)), "rho": rho,
+          "e_gas": rho * c_v * m["T0"], "v": np.zeros((3, n))}
+    # the largest step within the CFL number that lands exactly on t_end
+    n_steps = int(math.ceil(m["t_end"] / ((cfl or m["cfl"]) * dx / u["c"])))
+    dt = m["t_end"] / n_steps
+    return Marshak(ng, n, dx, edges, chi_lo, alpha, chi_mid, st, bb(m["T_left"]),
+                   bb(m["T_right"]), dt, m["t_end"], u["c"], u["a_rad"], u["h_over_k"], c_v)
