@@ -49,6 +49,41 @@ __host__ __device__ __forceinline__ double fma_c(double a, double b, double c) {
 #endif
 }
 
+// 1/d for |d| in [2^-1000, 2^1000] (the callers' denominators are bounded
+// away from 0 and overflow): the hardware estimate refined by two
+// Newton-Raphson steps, within an ulp, without the scaling and fix-up steps
+// of a general division.  The host build divides.
+__host__ __device__ __forceinline__ double rcp_nr(double d) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, r, 1.0);
+  r = fma(e, r, r);
+  e = fma(-d, r, 1.0);
+  return fma(e, r, r);
+#else
+  return 1.0 / d;
+#endif
+}
+
+// sqrt(a) for a in [1, 4]: the hardware reciprocal square root refined by a
+// Goldschmidt step and two Newton corrections, without range scaling.  The
+// host build calls sqrt.
+__host__ __device__ __forceinline__ double sqrt_1_4(double a) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const double y = __builtin_amdgcn_rsq(a);
+  double g = a * y, h = 0.5 * y;
+  const double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  double d = fma(-g, g, a);
+  g = fma(d, h, g);
+  d = fma(-g, g, a);
+  return fma(d, h, g);
+#else
+  return sqrt(a);
+#endif
+}
+
 // e^{-x} for x >= 0 (NaN passes through): Cody-Waite reduction
 // x = n ln2 + r, |r| <= ln2/2, with ln2 split in a head and a tail so that r
 // is exact to the last bits, then e^{-r} by its Taylor series to degree 13
@@ -136,7 +171,7 @@ __host__ __device__ __forceinline__ Edge planck_edge(double x) {
       s4 = fma_c(s4, u, tail_coef(k, 4));
     }
     e.val = kC15 * fma(x3, s1, fma(3.0 * y, s2, fma(6.0 * x, s3, 6.0 * s4)));
-    e.eps = kC15 * x3 * x / (1.0 - u);
+    e.eps = kC15 * x3 * x * rcp_nr(1.0 - u);   // 1 - u in [0.98, 1)
   }
   return e;
 }

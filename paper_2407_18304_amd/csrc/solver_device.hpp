@@ -462,7 +462,8 @@ __device__ __forceinline__ void pressure_dot_v(int closure, double c, double E, 
   const double icE = 1.0 / (c * E);
   double f2 = FF * icE * icE;
   f2 = f2 > 1.0 ? 1.0 : f2;
-  const double chi = (3.0 + 4.0 * f2) / (5.0 + 2.0 * sqrt(4.0 - 3.0 * f2));
+  // 4 - 3 f^2 in [1, 4] and 5 + 2 sqrt(.) in [7, 9]: no range handling needed
+  const double chi = (3.0 + 4.0 * f2) * rcp_nr(5.0 + 2.0 * sqrt_1_4(4.0 - 3.0 * f2));
   const double p = 0.5 * (1.0 - chi);
   const double q = 0.5 * (3.0 * chi - 1.0) * (F0 * v[0] + F1 * v[1] + F2 * v[2]) / FF;
   Pv[0] = E * (p * v[0] + q * F0);
@@ -537,7 +538,7 @@ __device__ __forceinline__ void load_cell(const KArgs& a, const Tables<NGM>& t, 
       s.vF[k] = s.v[0] * f[0] + s.v[1] * f[1] + s.v[2] * f[2];
       if (kFixedTau) {
         it = 1.0 / (cdt * s.rho_kappa * t.chk[g]);
-        ij = 1.0 / (-it - 1.0);
+        ij = rcp_nr(-it - 1.0);  // |-it - 1| >= 1
       }
     }
 #pragma unroll
@@ -704,7 +705,7 @@ __device__ __forceinline__ void newton_step(const KArgs& a, const Tables<NGM>& t
     if (MODE == MGRHD_MEAN_PPL_FREE || TD) {
       if (MODE == MGRHD_MEAN_PPL_FREE) ratio = c.chiB[k] / c.chiE[k];
       itau = 1.0 / (cdt * c.chiE[k]);
-      iJgg = 1.0 / (-itau - 1.0);
+      iJgg = rcp_nr(-itau - 1.0);  // |-itau - 1| >= 1
     } else {
       itau = ls.itau(k);
       iJgg = ls.iJgg(k);
@@ -737,7 +738,12 @@ __device__ __forceinline__ void newton_step(const KArgs& a, const Tables<NGM>& t
     return;
   }
   // eq. matrix eliminated: dx0, then dx_g = -a_g - b_g dx0
-  const double dx0 = (-FG + cc * sumA) / (1.0 - cc * sumB);
+  // the denominator is >= 1 (J_gg < 0, J_g0 >= 0): no scaling needed
+  const double den0 = 1.0 - cc * sumB;
+  const double num0 = -FG + cc * sumA;
+  const double ir0 = rcp_nr(den0);
+  const double q0 = num0 * ir0;
+  const double dx0 = fma(fma(-den0, q0, num0), ir0, q0);
   double lam = 1.0;
   for (int h = 0; h < 30 && !(s.egv + lam * dx0 - s.ke > 0.0); ++h) lam *= 0.5;
   if (!(s.egv + lam * dx0 - s.ke > 0.0)) {
@@ -775,7 +781,7 @@ __device__ __forceinline__ bool flux_step(const KArgs& a, const Tables<NGM>& t, 
     const double ac = TD ? c.ac[k] : t.achi[g];
     double Pv[3];
     pressure_dot_v(a.closure, a.c, Enew, ls.F(0, k), ls.F(1, k), ls.F(2, k), s.v, Pv);
-    const double iden = 1.0 / (1.0 + cdt * c.chiF[k]);
+    const double iden = rcp_nr(1.0 + cdt * c.chiF[k]);  // >= 1
     const double q = (1.0 + ac) * chE;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {

@@ -7,8 +7,9 @@ method as the kernels write it, per cell, in FLOP-equivalents:
 
 * +, -, x = 1 and fused multiply-add = 2; comparisons, selects, integer and
   memory work = 0;
-* a call of exp, expm1, log, sqrt, a division or the kernels' own e^{-x}
-  (exp_neg of planck_device.hpp) costs the FLOP-equivalents of
+* a call of exp, expm1, log, sqrt, a division or the kernels' own e^{-x},
+  range-bounded reciprocal and square root (exp_neg, rcp_nr, sqrt_1_4 of
+  planck_device.hpp) costs the FLOP-equivalents of
   the FP64 instruction sequence gfx950 code uses for it (FMA = 2, every other
   FP64 arithmetic instruction = 1, compares 0), counted in the assembly of a
   probe kernel built with the library's flags (``python -m
@@ -38,7 +39,8 @@ import numpy as np
 CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 
 # FLOP-equivalents of one call on gfx950 (measured by measure_weights())
-W = {"exp": 29, "expm1": 34, "log": 84, "div": 17, "sqrt": 19, "exp_neg": 34}
+W = {"exp": 29, "expm1": 34, "log": 84, "div": 17, "sqrt": 19, "exp_neg": 34, "rcp_nr": 9,
+     "sqrt_1_4": 17}
 
 PC, FIXED, FREE = 0, 1, 2
 
@@ -46,7 +48,7 @@ PC, FIXED, FREE = 0, 1, 2
 def unit_costs(w=W):
     """Per-unit FLOP-equivalents of the kernel source (see module doc)."""
     e, m1, lg, dv, sq = w["exp"], w["expm1"], w["log"], w["div"], w["sqrt"]
-    en = w["exp_neg"]
+    en, rc, s14 = w["exp_neg"], w["rcp_nr"], w["sqrt_1_4"]
     # one Planck edge: x = hk/T * nu (1), x^2 and x^3 (2), then by branch
     edge_common = 1 + 2
     poly_P = 14 * 2 + 6              # degree-14 Horner in x^2 and the bracket
@@ -55,8 +57,8 @@ def unit_costs(w=W):
         "x<=2": edge_common + poly_P + poly_E,
         "2<x<=4": edge_common + poly_P + poly_E,
         # e^{-x}, the 10-term tail as four degree-9 Horner chains in u and their
-        # combination, then x^4/(1 - u)
-        "x>4": edge_common + en + 4 * 9 * 2 + 10 + (3 + dv),
+        # combination, then x^4/(1 - u) (three products, 1 - u, a reciprocal)
+        "x>4": edge_common + en + 4 * 9 * 2 + 10 + (4 + rc),
         # the lowest edge at x <= 0.1: both polynomials truncated to degree 3
         "low": edge_common + 2 * (3 * 2 + 6),
     }
@@ -66,27 +68,35 @@ def unit_costs(w=W):
     ev_group = {
         PC: 1 + 8 + 3,                                        # chi (1), emit
         FIXED: 1 + 8 + 4 + 4 + 3 + dv + 5,                    # chi, dchib, chi_F num/den, emit
-        # logs of the two slope fits (B and E), two slope pairs, two group means
-        # (two expm1-brackets, a division and a rescaling exp each), chi_F, emit
-        FREE: 8 + 1 + (2 * lg + 3) + 2 * (2 * (2 + dv)) +
+        # E_g of the iterate (1), logs of the two slope fits (B and E), two
+        # slope pairs, two group means (two expm1-brackets, a division and a
+        # rescaling exp each), chi_F, emit
+        FREE: 1 + 8 + 1 + (2 * lg + 3) + 2 * (2 * (2 + dv)) +
               2 * (1 + 1 + 2 * (2 + m1 + dv) + 3 + dv + e) + 3 + 6 + 3 + dv + 5,
     }
-    ev_cell = 19 + 3 + dv + 1          # T, a T^4, 1/T, hk/T
+    ev_cell = 2 + 3 + dv + 1           # T = (E_gas - ke)/(rho c_v) (2), a T^4, 1/T, hk/T
     # Newton step per group: W (5, with v.F cached per pass), E_g (3), F_R (2),
     # J_g0 (1), a_g b_g (2), four sums (4), update of R_g (4); PPL-free adds
-    # chi_B/chi_E, 1/tau, 1/J_gg
-    nt_group = {PC: 21, FIXED: 21, FREE: 21 + 1 + 3 * dv + 3}
-    nt_cell = 2 * (1 + dv) + 2 + (dv + 1) + (dv + 2) + (4 + dv) + 5   # 1/c^2, 1/(rho c_v),
-    #                                      F_G, two stop tests, dx_0, the step
+    # chi_B/chi_E and its two products, 1/tau (1 + div) and 1/J_gg (1 + rcp)
+    nt_group = {PC: 21, FIXED: 21, FREE: 21 + 2 + dv + (1 + dv) + (1 + rc)}
+    # per cell: F_G (3), the two stop tests (3), dx_0 (numerator and
+    # denominator 4, a division by a reciprocal and one correction: rc + 5),
+    # the positivity check of the step (3), the update of E_gas (2)
+    nt_cell = 3 + 3 + 4 + (rc + 5) + 3 + 2
     # flux update per group: E_new (1), M1 closure P.v (F.F: 5, 1/(cE): 1+div,
-    # f^2: 2, chi: 6+sqrt+div, p: 2, F.v: 5, q: 4+div, P.v: 12), 1/(1+cdt chi_F)
-    # (2+div), chi_E and (1+a)chi_E (3), three components (3 x 8), the new v.F (5)
-    # and the dW term (5)
-    fx_group = 1 + (37 + sq + 3 * dv) + (2 + dv) + 3 + 24 + 10
-    fx_cell = 2 * (1 + dv) + 12 + (2 + dv) + 7 + 2
-    # cell load: per group E0 (1), sum (1), v.F (5), 1/tau and 1/J_gg (3 + 2 div)
-    ld_group = {PC: 10 + 2 * dv, FIXED: 10 + 2 * dv, FREE: 7}
-    ld_cell = 2 + 7 + 2 + dv
+    # f^2: 2, chi: 2 + sqrt on [1,4] + 2 + reciprocal + 2 + 1, p: 2,
+    # q: 4 + F.v (5) + div, P.v: 12), 1/(1+cdt chi_F) (2 + reciprocal), chi_E and
+    # (1+a)chi_E (3), three components (3 x 8), the new v.F (5) and the dW term (5)
+    closure = 5 + (1 + dv) + 2 + (2 + s14 + 2 + rc + 2 + 1) + 2 + (9 + dv) + 12
+    fx_group = 1 + closure + (2 + rc) + 3 + 24 + 10
+    # per cell: 1/rho (1), the momentum update (12), dW scale (1), new kinetic
+    # energy (7), the next pass's E_gas (2), the outer test (1)
+    fx_cell = 1 + 12 + 1 + 7 + 2 + 1
+    # cell load: per group E0 (1), sum (1), v.F (5), 1/tau (2 + div) and
+    # 1/J_gg (1 + reciprocal) in PC and PPL-fixed; per cell rho kappa (1),
+    # 1/(rho c_v) (1 + div), kinetic energy (7), E_tot (2), 1/E_tot (div)
+    ld_group = {PC: 7 + (2 + dv) + (1 + rc), FIXED: 7 + (2 + dv) + (1 + rc), FREE: 7}
+    ld_cell = 1 + (1 + dv) + 7 + 2 + dv
     # Temperature-dependent opacity, on top of the above.  Per evaluation and
     # cell: (T/T_ref)^beta = exp(beta ln(T/T_ref)).  Per edge with the
     # stimulated-emission factor: x/(x + x/(e^x-1)) below the Wien side, 1 - u
@@ -102,8 +112,8 @@ def unit_costs(w=W):
         ev_group={PC: 2, FIXED: 3, FREE: 2},
         ev_group_stim={PC: 1, FIXED: 1 + dv + lg + dv + 1 + 1 + (1 + m1 + dv) + dv + e / 2,
                        FREE: 1 + dv + lg + dv + 1 + 1},
-        nt_group={PC: 2 + 2 * dv, FIXED: 2 + 2 * dv, FREE: 0},
-        ld_group={PC: -(3 + 2 * dv), FIXED: -(3 + 2 * dv), FREE: 0},
+        nt_group={PC: (1 + dv) + (1 + rc), FIXED: (1 + dv) + (1 + rc), FREE: 0},
+        ld_group={PC: -((2 + dv) + (1 + rc)), FIXED: -((2 + dv) + (1 + rc)), FREE: 0},
     )
     return dict(edge=edge, group=group, ev_group=ev_group, ev_cell=ev_cell,
                 nt_group=nt_group, nt_cell=nt_cell, fx_group=fx_group, fx_cell=fx_cell,
@@ -187,6 +197,8 @@ K(p_log, log(x))
 K(p_div, a[i + 64] / x)
 K(p_sqrt, sqrt(x))
 K(p_exp_neg, mgrhd::exp_neg(x))
+K(p_rcp_nr, mgrhd::rcp_nr(x))
+K(p_sqrt_1_4, mgrhd::sqrt_1_4(x))
 """
 
 
