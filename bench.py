@@ -92,8 +92,8 @@ def main():
     ap.add_argument("--train-cells", type=int, default=1 << 20)
     ap.add_argument("--epochs", type=int, default=8)
     ap.add_argument("--tuning", default="",
-                    help="config4: batch tuning G,B,C (groups per lane, workgroups per CU, "
-                         "cells per item)")
+                    help="config4: batch tuning G,B,C[,S] (groups per lane, workgroups per CU, "
+                         "cells per item, item scope: 0 wave, 1|2 workgroup)")
     ap.add_argument("--variant", default="",
                     help="kernel variant override LPCxG[xW] (lanes per cell, groups per lane, "
                          "waves per SIMD), e.g. 16x4 or 16x4x3")
@@ -190,6 +190,9 @@ def main():
     fpc = F.flops_per_cell(ng, args.mode, iters.double(), outer.double(), mix, valid=valid,
                            t_exp=dw.t_exp, stim=dw.stim)
     flop = float(fpc.sum())
+    flop1 = float(F.flops_per_cell(ng, args.mode, iters.double(), outer.double(), mix,
+                                   u=F.UNIT_DIV_SQRT_1, valid=valid, t_exp=dw.t_exp,
+                                   stim=dw.stim).sum())
     achieved_fl = flop / kern_s
     # the binding ceiling is the lower of the two for this workload
     ceil_alu = PEAK_FP64 / (flop / n)
@@ -200,7 +203,9 @@ def main():
     traffic = None if (args.warm or args.cells or args.mode != 1) else measured_traffic(name, kname)
     roof_alu = {"bound": "alu", "achieved": achieved_fl / 1e12, "peak": PEAK_FP64 / 1e12,
                 "unit": "TFLOP/s", "frac": achieved_fl / PEAK_FP64, "traffic": traffic,
-                "flop_per_cell": flop / n, "ceiling_cells_per_s": ceil_alu}
+                "flop_per_cell": flop / n, "ceiling_cells_per_s": ceil_alu,
+                "flop_per_cell_div_sqrt_as_1": flop1 / n,
+                "frac_div_sqrt_as_1": flop1 / kern_s / PEAK_FP64}
     roof_hbm = {"bound": "hbm", "achieved": achieved_bw / 1e9, "peak": PEAK_HBM / 1e9,
                 "unit": "GB/s", "frac": achieved_bw / PEAK_HBM, "traffic": traffic,
                 "bytes_per_cell": bpc, "ceiling_cells_per_s": ceil_hbm}
@@ -369,7 +374,10 @@ def run_batch(args):
         pd.append(d)
     b = mgrhd.Batch(pd, mean_mode=args.mode, polish=1, c=u["c"], a_rad=u["a_rad"])
     if args.tuning:
-        b.set_tuning(*(int(x) for x in args.tuning.split(",")))
+        tv = [int(x) for x in args.tuning.split(",")]
+        b.set_tuning(*tv[:3])
+        if len(tv) > 3:
+            b.set_item_scope(tv[3])
     elif args.tune:
         from paper_2407_18304_amd import autotune
         autotune.tune_batch(b, lambda: synth.fill_patches(dps), reps=1,
@@ -395,7 +403,7 @@ def run_batch(args):
         kern_ms.append(e0.elapsed_time(e1))
     kern_s = float(np.mean(kern_ms)) * 1e-3
     # per-cell work of the last step
-    flop = 0.0
+    flop = flop1 = 0.0
     byts = 0.0
     it_all, ou_all, st_all = [], [], []
     for dp, d in zip(dps, pd):
@@ -406,6 +414,9 @@ def run_batch(args):
         valid = ((d["status"] & 8) == 0).double()
         flop += float(F.flops_per_cell(L.ng, args.mode, d["iters"].double(), d["outer"].double(),
                                        mix, valid=valid).sum())
+        flop1 += float(F.flops_per_cell(L.ng, args.mode, d["iters"].double(),
+                                        d["outer"].double(), mix, u=F.UNIT_DIV_SQRT_1,
+                                        valid=valid).sum())
         byts += L.n * bytes_per_cell(L.ng)
         it_all.append(d["iters"].cpu().numpy())
         ou_all.append(d["outer"].cpu().numpy())
@@ -415,7 +426,9 @@ def run_batch(args):
     ceil_hbm = PEAK_HBM / (byts / n)
     roof_alu = {"bound": "alu", "achieved": flop / kern_s / 1e12, "peak": PEAK_FP64 / 1e12,
                 "unit": "TFLOP/s", "frac": flop / kern_s / PEAK_FP64, "traffic": None,
-                "flop_per_cell": flop / n, "ceiling_cells_per_s": ceil_alu}
+                "flop_per_cell": flop / n, "ceiling_cells_per_s": ceil_alu,
+                "flop_per_cell_div_sqrt_as_1": flop1 / n,
+                "frac_div_sqrt_as_1": flop1 / kern_s / PEAK_FP64}
     roof_hbm = {"bound": "hbm", "achieved": byts / kern_s / 1e9, "peak": PEAK_HBM / 1e9,
                 "unit": "GB/s", "frac": byts / kern_s / PEAK_HBM, "traffic": None,
                 "bytes_per_cell": byts / n, "ceiling_cells_per_s": ceil_hbm}
@@ -435,7 +448,7 @@ def run_batch(args):
         "data": "synthetic (seeded counter-based generator, drawn in HBM before each step)",
         "config": {"workload": WORKLOADS["config4"], "cells": n, "patches": len(layouts),
                    "mean_mode": ["PC", "PPL-fixed", "PPL-free"][args.mode],
-                   "batch_tuning": list(b.get_tuning()), "eps_newton": 1e-11, "polish": 1,
+                   "batch_tuning": list(b.get_tuning()), "item_scope": b.get_item_scope(), "eps_newton": 1e-11, "polish": 1,
                    "closure": "M1", "timing": "HIP events around each graph launch"},
         "newton_iters_per_cell": {"mean": float(it.mean()), "p50": float(np.percentile(it, 50)),
                                   "p99": float(np.percentile(it, 99)), "max": int(it.max())},

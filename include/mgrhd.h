@@ -275,12 +275,22 @@ int mgrhd_batch_create(const mgrhd_patch* patches, int32_t n_patches, int32_t me
                        const mgrhd_options* opt, mgrhd_batch** out);
 /* Tuning knobs (see the autotuner): groups per lane (2 or 4), resident
  * workgroups per CU (0 = as many as fit), cells per work item.  Defaults:
- * 2, 0, 1024.  The per-cell state machine is compiled for every lane count
- * per cell (a wave dispatches on its item's patch). */
+ * 2, 0, 256 (with work items taken per workgroup, item scope 1).  The
+ * per-cell state machine is compiled for every lane count per cell (a wave
+ * dispatches on its item's patch). */
 int mgrhd_batch_set_tuning(mgrhd_batch* b, int32_t groups_per_lane, int32_t blocks_per_cu,
                            int64_t chunk_cells);
 int mgrhd_batch_get_tuning(const mgrhd_batch* b, int32_t* groups_per_lane,
                            int32_t* blocks_per_cu, int64_t* chunk_cells);
+/* Who takes a work item: 0 = one wave (each wave stages its patch's tables
+ * in its own LDS slot); 1 or 2 = one workgroup (its four waves share the
+ * item's cells through an LDS counter and one table slot, which leaves LDS
+ * for three workgroups per CU; waves that run out of cells wait for the
+ * item's last cells), compiled for 3 (scope 1, at 2 groups per lane) or 2
+ * waves per SIMD (scope 2).  Default 1.  Changing it drops a captured graph.
+ * get returns the scope or MGRHD_E_NULL. */
+int mgrhd_batch_set_item_scope(mgrhd_batch* b, int32_t per_workgroup);
+int32_t mgrhd_batch_get_item_scope(const mgrhd_batch* b);
 /* Enqueue the counter reset and the persistent solver on `stream`. */
 int mgrhd_batch_run(mgrhd_batch* b, mgrhd_stream_t stream);
 /* Capture mgrhd_batch_run into a hipGraph kept by the batch; launch replays

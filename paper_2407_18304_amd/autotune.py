@@ -101,25 +101,32 @@ def tune_single(dw, mode=mgrhd.MEAN_PPL_FIXED, reps=3, path=CACHE, log=print):
 
 
 def tune_batch(batch, restore, candidates=None, reps=2, path=CACHE, key="patches", log=print):
-    """Time batch tunings (groups per lane, blocks per CU, cells per item)."""
+    """Time batch tunings (groups per lane, blocks per CU, cells per item,
+    item scope)."""
     if candidates is None:
-        candidates = [(g, b, ch) for g in (2, 4) for b in (0, 1) for ch in (1024, 4096)]
+        candidates = [(g, b, ch, 0) for g in (2, 4) for b in (0, 1) for ch in (1024, 4096)]
+        candidates += [(2, 0, ch, 1) for ch in (128, 256, 512, 1024)]
+        candidates += [(2, 0, ch, 2) for ch in (256, 1024)]
+        candidates += [(4, 0, 1024, 2)]
     results = []
-    for g, b, ch in candidates:
+    for g, b, ch, sc in candidates:
         try:
             batch.set_tuning(g, b, ch)
+            batch.set_item_scope(sc)
         except mgrhd.MgrhdError:
             continue
         batch.run()
         ms = _time(batch.run, restore, reps)
-        results.append((ms, g, b, ch))
-        log(f"  batch: {g} groups/lane, {b or 'all'} blocks/CU, {ch} cells/item -> {ms:.3f} ms")
+        results.append((ms, g, b, ch, sc))
+        log(f"  batch: {g} groups/lane, {b or 'all'} blocks/CU, {ch} cells/item, "
+            f"items per {'workgroup (%d waves/SIMD)' % (4 - sc) if sc else 'wave'} -> {ms:.3f} ms")
     restore()
-    ms, g, b, ch = min(results)
+    ms, g, b, ch, sc = min(results)
     batch.set_tuning(g, b, ch)
+    batch.set_item_scope(sc)
     cache = load_cache(path)
     cache.setdefault(arch(), {}).setdefault("batch", {})[key] = {
-        "groups_per_lane": g, "blocks_per_cu": b, "chunk_cells": ch, "ms": ms,
+        "groups_per_lane": g, "blocks_per_cu": b, "chunk_cells": ch, "item_scope": sc, "ms": ms,
         "all": [list(r) for r in sorted(results)]}
     save_cache(cache, path)
-    return g, b, ch, ms
+    return g, b, ch, sc, ms

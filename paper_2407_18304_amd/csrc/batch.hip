@@ -86,20 +86,20 @@ __device__ __forceinline__ T load_uniform(const T* p) {
 
 // Lanes per cell for N_g groups at G groups per lane: the next power of two
 // >= N_g / G.  The state machine is compiled for each.
-template <int G, int MODE, int NGM, class LS>
+template <int G, int MODE, int NGM, class LS, class Q>
 __device__ __forceinline__ void run_item(const KArgs& a, const Tables<NGM>& tab, const LS& ls,
-                                         int lane, int64_t c0, int64_t c1) {
+                                         int lane, Q q) {
   int lpc = 1;
   while (lpc * G < a.ng) lpc <<= 1;
   switch (lpc) {
-    case 1: run_cells<G, 1, MODE, NGM>(a, tab, ls, lane, WaveRange{c0, c1}); break;
-    case 2: run_cells<G, 2, MODE, NGM>(a, tab, ls, lane, WaveRange{c0, c1}); break;
-    case 4: run_cells<G, 4, MODE, NGM>(a, tab, ls, lane, WaveRange{c0, c1}); break;
-    case 8: run_cells<G, 8, MODE, NGM>(a, tab, ls, lane, WaveRange{c0, c1}); break;
-    case 16: run_cells<G, 16, MODE, NGM>(a, tab, ls, lane, WaveRange{c0, c1}); break;
-    case 32: run_cells<G, 32, MODE, NGM>(a, tab, ls, lane, WaveRange{c0, c1}); break;
+    case 1: run_cells<G, 1, MODE, NGM>(a, tab, ls, lane, q); break;
+    case 2: run_cells<G, 2, MODE, NGM>(a, tab, ls, lane, q); break;
+    case 4: run_cells<G, 4, MODE, NGM>(a, tab, ls, lane, q); break;
+    case 8: run_cells<G, 8, MODE, NGM>(a, tab, ls, lane, q); break;
+    case 16: run_cells<G, 16, MODE, NGM>(a, tab, ls, lane, q); break;
+    case 32: run_cells<G, 32, MODE, NGM>(a, tab, ls, lane, q); break;
     default:  // a patch wider than 32 lanes of G groups
-      if constexpr (G * 32 < NGM) run_cells<G, kWave, MODE, NGM>(a, tab, ls, lane, WaveRange{c0, c1});
+      if constexpr (G * 32 < NGM) run_cells<G, kWave, MODE, NGM>(a, tab, ls, lane, q);
       break;
   }
 }
@@ -139,18 +139,77 @@ __global__ __launch_bounds__(kBlock, 2) void k_batch(BatchArgs b) {
       }
       continue;
     }
-    run_item<G, MODE>(a, tab, ls, lane, item.c0, item.c1);
+    run_item<G, MODE>(a, tab, ls, lane, WaveRange{item.c0, item.c1});
+  }
+}
+
+// Items per workgroup: the four waves of a workgroup take one item together,
+// share one LDS table slot (so LDS leaves room for 3 workgroups per CU) and
+// take the item's cells through an LDS counter, so the cells in flight in a
+// workgroup share the cache lines of every SoA row.  Waves that run out of
+// cells wait at the item's end for the others.
+// WPE: waves per SIMD the register allocation must allow (LDS allows 3 at 2
+// groups per lane; at 3 a few registers spill, at 2 none do).
+template <int G, int MODE, int NGM, int WPE>
+__global__ __launch_bounds__(kBlock, WPE) void k_batch_wg(BatchArgs b) {
+  static_assert(G * kWave >= NGM, "a wave holds the widest patch");
+  __shared__ Tables<NGM> tab;
+  __shared__ int item_s, taken;
+  using LS = LaneStore<G, G == 2>;
+  __shared__ double lane_lds[LS::kSlots * kBlock];
+  const LS ls{lane_lds + threadIdx.x};
+  const int lane = threadIdx.x % kWave;
+  int cur_patch = -1;
+  bool table_ok = false;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      item_s = atomicAdd(b.counter, 1);
+      taken = 0;
+    }
+    __syncthreads();
+    const int it = __builtin_amdgcn_readfirstlane(item_s);
+    if (it >= b.n_items) break;
+    const Item item = load_uniform(b.items + it);
+    const KArgs& a = b.patches[item.patch];
+    if (item.patch != cur_patch) {  // uniform over the workgroup
+      table_ok = stage_tables<NGM, MODE>(a, tab);
+      cur_patch = item.patch;
+    }
+    if (!table_ok) {
+      for (int64_t i = item.c0 + threadIdx.x; i < item.c1; i += kBlock) {
+        if (a.status) a.status[i] = MGRHD_ST_BAD_TABLE;
+        if (a.iters) a.iters[i] = 0;
+        if (a.outer) a.outer[i] = 0;
+      }
+    } else {
+      run_item<G, MODE>(a, tab, ls, lane, BlockQueue{&taken, item.c0, item.c1});
+    }
+    __syncthreads();  // the item is done before the next one resets the counter
   }
 }
 
 using BatchFn = void (*)(BatchArgs);
-static BatchFn batch_fn(int g, int mode) {
-  static const BatchFn fns[2][3] = {
+// the kernel for g groups per lane, mean mode, and items per wave (scope 0) or
+// per workgroup (scope 1: register budget for 3 waves per SIMD at 2 groups
+// per lane; scope 2: for 2 waves)
+static BatchFn batch_fn(int g, int mode, int scope) {
+  static const BatchFn wave[2][3] = {
       {k_batch<2, MGRHD_MEAN_PC, kBatchNGM>, k_batch<2, MGRHD_MEAN_PPL_FIXED, kBatchNGM>,
        k_batch<2, MGRHD_MEAN_PPL_FREE, kBatchNGM>},
       {k_batch<4, MGRHD_MEAN_PC, kBatchNGM>, k_batch<4, MGRHD_MEAN_PPL_FIXED, kBatchNGM>,
        k_batch<4, MGRHD_MEAN_PPL_FREE, kBatchNGM>}};
-  return fns[g == 4 ? 1 : 0][mode];
+  static const BatchFn wg3[3] = {k_batch_wg<2, MGRHD_MEAN_PC, kBatchNGM, 3>,
+                                 k_batch_wg<2, MGRHD_MEAN_PPL_FIXED, kBatchNGM, 3>,
+                                 k_batch_wg<2, MGRHD_MEAN_PPL_FREE, kBatchNGM, 3>};
+  static const BatchFn wg2[2][3] = {
+      {k_batch_wg<2, MGRHD_MEAN_PC, kBatchNGM, 2>, k_batch_wg<2, MGRHD_MEAN_PPL_FIXED, kBatchNGM, 2>,
+       k_batch_wg<2, MGRHD_MEAN_PPL_FREE, kBatchNGM, 2>},
+      {k_batch_wg<4, MGRHD_MEAN_PC, kBatchNGM, 2>, k_batch_wg<4, MGRHD_MEAN_PPL_FIXED, kBatchNGM, 2>,
+       k_batch_wg<4, MGRHD_MEAN_PPL_FREE, kBatchNGM, 2>}};
+  const int gi = g == 4 ? 1 : 0;
+  if (scope == 0) return wave[gi][mode];
+  if (scope == 1 && g == 2) return wg3[mode];
+  return wg2[gi][mode];
 }
 
 }  // namespace mgrhd
@@ -169,8 +228,9 @@ struct mgrhd_batch {
   std::vector<KArgs> h_patches;
   // tuning
   int32_t groups_per_lane = 2;
+  int32_t scope = 1;          // 0: items per wave, 1 | 2: items per workgroup
   int32_t blocks_per_cu = 0;  // 0 = all resident
-  int64_t chunk = 1024;
+  int64_t chunk = 256;
   bool items_dirty = true;
   // graph
   hipGraph_t graph = nullptr;
@@ -327,6 +387,20 @@ int mgrhd_batch_set_tuning(mgrhd_batch* bt, int32_t groups_per_lane, int32_t blo
   return 0;
 }
 
+int mgrhd_batch_set_item_scope(mgrhd_batch* bt, int32_t per_workgroup) {
+  if (!bt) return MGRHD_E_NULL;
+  if (per_workgroup < 0 || per_workgroup > 2) return MGRHD_E_OPTION;
+  if (per_workgroup != bt->scope) {
+    bt->scope = per_workgroup;
+    drop_graph(bt);
+  }
+  return 0;
+}
+
+int32_t mgrhd_batch_get_item_scope(const mgrhd_batch* bt) {
+  return bt ? bt->scope : MGRHD_E_NULL;
+}
+
 int mgrhd_batch_get_tuning(const mgrhd_batch* bt, int32_t* groups_per_lane,
                            int32_t* blocks_per_cu, int64_t* chunk_cells) {
   if (!bt) return MGRHD_E_NULL;
@@ -342,7 +416,7 @@ static int enqueue(mgrhd_batch* bt, hipStream_t stream) {
     if (rc) return rc;
   }
   if (bt->n_items == 0) return 0;
-  BatchFn fn = batch_fn(bt->groups_per_lane, bt->mode);
+  BatchFn fn = batch_fn(bt->groups_per_lane, bt->mode, bt->scope);
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kBlock, 0) != hipSuccess || nb < 1)
     nb = 1;
@@ -352,8 +426,12 @@ static int enqueue(mgrhd_batch* bt, hipStream_t stream) {
   if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
     cus = prop.multiProcessorCount;
   int64_t blocks = (int64_t)cus * nb;
-  const int64_t waves_needed = bt->n_items;
-  if (blocks * (kBlock / kWave) > waves_needed) blocks = (waves_needed + 3) / 4;
+  // never more takers than items: waves (scope 0) or workgroups (scope 1)
+  if (bt->scope) {
+    if (blocks > bt->n_items) blocks = bt->n_items;
+  } else if (blocks * (kBlock / kWave) > bt->n_items) {
+    blocks = (bt->n_items + 3) / 4;
+  }
   hipLaunchKernelGGL(k_clear_counter, dim3(1), dim3(64), 0, stream, bt->d_counter);
   BatchArgs args{bt->d_patches, bt->d_items, bt->d_counter, bt->n_items};
   hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(kBlock), 0, stream, args);

@@ -121,6 +121,11 @@ def unit_costs(w=W):
 
 
 UNIT = unit_costs()
+# The same count with every division and square root (the kernels' range-bounded
+# reciprocal and square root included) as one operation, transcendentals as
+# above: the lower figure a convention that prices only exp/expm1/log by their
+# instruction sequences gives.
+UNIT_DIV_SQRT_1 = unit_costs(dict(W, div=1, sqrt=1, rcp_nr=1, sqrt_1_4=1))
 
 
 def edge_mix(nu, hk, T):

@@ -244,6 +244,7 @@ class Patch(C.Structure):
                 ("dt", C.c_double), ("c_hat", C.c_double)]
 
 
+SYMBOLS += ["mgrhd_batch_set_item_scope", "mgrhd_batch_get_item_scope"]
 SYMBOLS += ["mgrhd_batch_create", "mgrhd_batch_set_tuning", "mgrhd_batch_get_tuning",
             "mgrhd_batch_run", "mgrhd_batch_capture", "mgrhd_batch_launch", "mgrhd_batch_cells",
             "mgrhd_batch_destroy"]
@@ -318,6 +319,20 @@ class Batch:
 
     def _stream(self, stream):
         return torch.cuda.current_stream().cuda_stream if stream is None else stream
+
+    def set_item_scope(self, per_workgroup: int):
+        L = _batch_lib()
+        L.mgrhd_batch_set_item_scope.restype = C.c_int
+        L.mgrhd_batch_set_item_scope.argtypes = [C.c_void_p, C.c_int32]
+        rc = L.mgrhd_batch_set_item_scope(self._h, int(per_workgroup))
+        if rc != 0:
+            raise MgrhdError(rc, "mgrhd_batch_set_item_scope")
+
+    def get_item_scope(self) -> int:
+        L = _batch_lib()
+        L.mgrhd_batch_get_item_scope.restype = C.c_int32
+        L.mgrhd_batch_get_item_scope.argtypes = [C.c_void_p]
+        return int(L.mgrhd_batch_get_item_scope(self._h))
 
     def set_tuning(self, groups_per_lane, blocks_per_cu, chunk_cells):
         rc = _batch_lib().mgrhd_batch_set_tuning(self._h, groups_per_lane, blocks_per_cu,

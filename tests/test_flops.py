@@ -48,6 +48,16 @@ def test_flops_bookkeeping():
     assert F.flops_per_cell(64, F.FIXED, it, ou, mix, valid=np.zeros(3)).sum() == 0
     # PPL-free costs more per evaluation than PPL-fixed, which costs more than PC
     assert u["ev_group"][F.FREE] > u["ev_group"][F.FIXED] > u["ev_group"][F.PC]
+    # with divisions and square roots as one operation: the Planck edges below
+    # the Wien side hold none, so they cost the same; the closure holds two
+    # divisions, a reciprocal and a square root, each now 1
+    u1 = F.UNIT_DIV_SQRT_1
+    assert u1["edge"]["x<=2"] == u["edge"]["x<=2"]
+    w = F.W
+    assert u["fx_group"] - u1["fx_group"] == (2 * (w["div"] - 1) + 2 * (w["rcp_nr"] - 1) +
+                                              (w["sqrt_1_4"] - 1))
+    f1 = F.flops_per_cell(64, F.FIXED, it, ou, mix, u=u1)
+    assert (f1 < f).all()
 
 
 @pytest.mark.skipif(not shutil.which("hipcc") and not os.path.exists("/opt/rocm/bin/hipcc"),

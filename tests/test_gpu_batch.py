@@ -40,14 +40,21 @@ def _consts():
     return dict(c=u["c"], a_rad=u["a_rad"])
 
 
-@pytest.mark.parametrize("gpl", [2, 4])
-def test_batch_matches_single_table_and_oracle(gpl):
+# (groups per lane, item scope): items per wave, or per workgroup compiled for
+# 3 or 2 waves per SIMD
+TUNINGS = [(2, 0), (4, 0), (2, 1), (2, 2), (4, 2)]
+
+
+@pytest.mark.parametrize("gpl,scope", TUNINGS)
+def test_batch_matches_single_table_and_oracle(gpl, scope):
     layouts = _layouts()
     dps = synth.device_patches(layouts)
     inputs = [synth.patch_to_host(dp) for dp in dps]          # pristine inputs
     pd = _patch_dicts(dps)
     b = mgrhd.Batch(pd, mean_mode=1, polish=1, **_consts())
     b.set_tuning(gpl, 0, 300)                                   # several items per patch
+    b.set_item_scope(scope)
+    assert b.get_item_scope() == scope
     assert b.n_cells == sum(L.n for L in layouts)
     b.run()
     torch.cuda.synchronize()
@@ -62,7 +69,8 @@ def test_batch_matches_single_table_and_oracle(gpl):
         U.compare(w, res, U.run_oracle(w, 1), label=f"patch {L.index} vs oracle")
 
 
-def test_batch_graph_replay_matches_direct_run():
+@pytest.mark.parametrize("scope", [0, 1])
+def test_batch_graph_replay_matches_direct_run(scope):
     """Capture [counter clear -> persistent solver] once, replay it several
     times on restored inputs, with eager work between the replays: every
     replay equals the direct run bit for bit."""
@@ -71,7 +79,8 @@ def test_batch_graph_replay_matches_direct_run():
     pristine = [{k: v.clone() for k, v in dp.state.items()} for dp in dps]
     pd = _patch_dicts(dps)
     b = mgrhd.Batch(pd, mean_mode=1, polish=1, **_consts())
-    b.set_tuning(4, 0, 256)
+    b.set_tuning(4 if scope == 0 else 2, 0, 256)
+    b.set_item_scope(scope)
 
     def restore():
         for dp, p in zip(dps, pristine):
@@ -99,7 +108,8 @@ def test_batch_graph_replay_matches_direct_run():
         del x
 
 
-def test_batch_ragged_and_empty_patches():
+@pytest.mark.parametrize("scope", [0, 1])
+def test_batch_ragged_and_empty_patches(scope):
     layouts = W.patch_layouts(n_patches=5, sides=(1, 3, 5), ngs=(1, 3, 8, 13, 33))
     dps = synth.device_patches(layouts)
     inputs = [synth.patch_to_host(dp) for dp in dps]
@@ -110,6 +120,7 @@ def test_batch_ragged_and_empty_patches():
     e.update(edges=pd[0]["edges"], chi_lo=pd[0]["chi_lo"], alpha_chi=pd[0]["alpha_chi"],
              dt=pd[0]["dt"], c_hat=pd[0]["c_hat"])
     b = mgrhd.Batch(pd + [e], mean_mode=2, polish=1, **_consts())
+    b.set_item_scope(scope)
     b.run()
     torch.cuda.synchronize()
     for w, d in zip(inputs, pd):
@@ -118,8 +129,8 @@ def test_batch_ragged_and_empty_patches():
         U.compare(w, res, U.run_oracle(w, 2), label=f"ragged patch N_g={w.ng} n={w.n}")
 
 
-@pytest.mark.parametrize("gpl", [2, 4])
-def test_batch_wide_patches(gpl):
+@pytest.mark.parametrize("gpl,scope", TUNINGS)
+def test_batch_wide_patches(gpl, scope):
     """Patches wider than 64 groups (the kernels with 128-group table slots;
     at 2 groups per lane a cell spans the whole wavefront) next to narrow ones."""
     layouts = W.patch_layouts(n_patches=5, seed=78, sides=(2, 3), ngs=(8, 65, 100, 128))
@@ -129,6 +140,7 @@ def test_batch_wide_patches(gpl):
     pd = _patch_dicts(dps)
     b = mgrhd.Batch(pd, mean_mode=1, polish=1, **_consts())
     b.set_tuning(gpl, 0, 16)
+    b.set_item_scope(scope)
     b.run()
     torch.cuda.synchronize()
     for w, d in zip(inputs, pd):
@@ -147,4 +159,36 @@ def test_batch_argument_errors():
     b = mgrhd.Batch(pd, mean_mode=1, **_consts())
     with pytest.raises(mgrhd.MgrhdError):
         b.set_tuning(3, 0, 100)
+    for bad in (-1, 3):
+        with pytest.raises(mgrhd.MgrhdError) as e:
+            b.set_item_scope(bad)
+        assert e.value.code == mgrhd.E_OPTION
+    assert b.get_item_scope() == 1            # the default
     b.close()
+
+
+@pytest.mark.parametrize("gpl,scope", TUNINGS)
+def test_batch_bad_table_patch(gpl, scope):
+    """A patch whose table is invalid (a negative group opacity) is flagged
+    cell by cell and left unchanged; the patches around it are solved."""
+    layouts = _layouts(6)
+    dps = synth.device_patches(layouts)
+    inputs = [synth.patch_to_host(dp) for dp in dps]
+    pd = _patch_dicts(dps)
+    bad = 2
+    pd[bad]["chi_lo"] = pd[bad]["chi_lo"].clone()
+    pd[bad]["chi_lo"][1] = -1.0
+    b = mgrhd.Batch(pd, mean_mode=1, polish=1, **_consts())
+    b.set_tuning(gpl, 0, 100)
+    b.set_item_scope(scope)
+    b.run()
+    torch.cuda.synchronize()
+    for i, (w, d) in enumerate(zip(inputs, pd)):
+        st = d["status"].cpu().numpy()
+        if i == bad:
+            assert (st == mgrhd.ST_BAD_TABLE).all()
+            assert (d["iters"].cpu().numpy() == 0).all()
+            for k in ("E_g", "F_g", "e_gas", "v"):
+                assert np.array_equal(d[k].cpu().numpy(), w.state[k]), k
+        else:
+            assert (st >= 0).all() and (st != mgrhd.ST_BAD_TABLE).all()
