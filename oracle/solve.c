@@ -13,6 +13,11 @@
  * Mean opacities follow Sec. 2.2 (PC, PPL with fixed slopes, PPL with the
  * Appendix A slopes) and eq. chiDiff for the flux mean.  Readings taken where
  * the paper is silent are marked READING.  Test infrastructure only.
+ *
+ * Parity unpinned: which root the PPL-free iteration reaches where the
+ * minmod slopes kink and several fixed points exist (the slopes lag the
+ * iterate); the tests pin that the output is a root of the implicit system,
+ * not which one a warm start reaches.
  */
 #include <math.h>
 #include <pthread.h>

@@ -79,8 +79,13 @@ static Variant* choose_variant(int ng) {
     Variant* v = find_variant(g_override_lpc[ng], g_override_g[ng], g_override_wpe[ng]);
     if (v && v->lpc * v->g >= ng) return v;
   }
-  // default: 4 groups per lane, enough lanes to cover N_g
+  // default: 2 groups per lane at 3 waves per SIMD and enough lanes to cover
+  // N_g (the fastest on gfx950 at 16 and 64 groups); 4 groups per lane where
+  // no 2-group variant covers N_g
   int lpc = 1;
+  while (lpc * 2 < ng) lpc <<= 1;
+  if (Variant* v = find_variant(lpc, 2, 0)) return v;
+  lpc = 1;
   while (lpc * 4 < ng) lpc <<= 1;
   return find_variant(lpc, 4, 0);
 }

@@ -51,6 +51,8 @@ def test_defaults_version_and_variants(lib):
     for ng in (1, 4, 16, 64, 100, 256):
         lpc, g, w = mgrhd.get_variant(ng)
         assert lpc * g >= ng and (lpc, g, w) in vs
+        # built-in choice: 2 groups per lane where a variant covers N_g, else 4
+        assert g == (2 if 2 < ng <= 64 else 4)
     with pytest.raises(mgrhd.MgrhdError):
         mgrhd.set_variant(64, 4, 4)          # 16 lanes-groups < 64 groups
     with pytest.raises(mgrhd.MgrhdError):
