@@ -85,8 +85,9 @@ def main():
     ap.add_argument("--patches", type=int, default=0, help="config4: override the patch count")
     ap.add_argument("--warm", action="store_true",
                     help="learned warm start: train the network on 2^20 solver pairs of the "
-                         "same distribution (training seed, untimed), then time network "
-                         "inference + solve per step, and plain steps for comparison")
+                         "same distribution (training seed, untimed; config4: one network per "
+                         "group count), then time network inference + solve per step, and "
+                         "plain steps for comparison")
     ap.add_argument("--tune", action="store_true",
                     help="config4: run the batch autotuner before timing")
     ap.add_argument("--train-cells", type=int, default=1 << 20)
@@ -387,20 +388,81 @@ def run_batch(args):
     with torch.cuda.stream(stream):
         b.capture(stream.cuda_stream)
     torch.cuda.synchronize()
-    for _ in range(args.warmup):
+
+    def timed(launch):
+        for _ in range(args.warmup):
+            synth.fill_patches(dps)
+            launch()
+            stream.synchronize()
+        ms = []
+        for _ in range(args.steps):
+            synth.fill_patches(dps)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            with torch.cuda.stream(stream):
+                e0.record(stream)
+                launch()
+                e1.record(stream)
+            stream.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return ms
+
+    winfo = None
+    if args.warm:
+        # one network per group count, trained on patches drawn with the
+        # training seed (untimed); the timed step is [inference of every
+        # patch -> batched solve] replayed from one graph, against the plain
+        # batched solve on the same inputs
+        from paper_2407_18304_amd import warmstart
+        nets, winfo = train_warm_patches(sorted({L.ng for L in layouts}), args)
+        plain_ms = timed(lambda: b.launch(stream.cuda_stream))
+        k_s = 64
+        plain_it = np.concatenate([d["iters"].cpu().numpy() for d in pd])
+        plain_st = np.concatenate([d["status"].cpu().numpy() for d in pd])
+        sample = [{k: dp.state[k][..., :k_s].clone() for k in ("E_g", "F_g", "e_gas", "v")}
+                  for dp in dps]
+        guesses = [torch.empty(dp.layout.n, dtype=torch.float64, device="cuda") for dp in dps]
+        bw = mgrhd.Batch([dict(d, guess=g) for d, g in zip(pd, guesses)], mean_mode=args.mode,
+                         polish=1, c=u["c"], a_rad=u["a_rad"], guess_kind=1)
+        bw.set_tuning(*b.get_tuning())
+        bw.set_item_scope(b.get_item_scope())
+        pws = warmstart.PatchWarmStart(nets)
         synth.fill_patches(dps)
-        b.launch(stream.cuda_stream)
+        with torch.cuda.stream(stream):        # eager once (builds the work list)
+            pws.guesses(dps, guesses)
+            bw.run(stream.cuda_stream)
         stream.synchronize()
-    kern_ms = []
-    for _ in range(args.steps):
-        synth.fill_patches(dps)
+        gw = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gw, stream=stream, capture_error_mode="thread_local"):
+            pws.guesses(dps, guesses)
+            bw.run(stream.cuda_stream)
+        gi = torch.cuda.CUDAGraph()            # the inference launches alone
+        with torch.cuda.graph(gi, stream=stream, capture_error_mode="thread_local"):
+            pws.guesses(dps, guesses)
         torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        b.launch(stream.cuda_stream)
-        e1.record(stream)
-        stream.synchronize()
-        kern_ms.append(e0.elapsed_time(e1))
+        infer_ms = timed(gi.replay)
+        kern_ms = timed(gw.replay)
+        dmax = 0.0
+        for dp, smp in zip(dps, sample):
+            for k in ("E_g", "e_gas"):
+                a, r = dp.state[k][..., :k_s], smp[k]
+                dmax = max(dmax, float(((a - r).abs() / r.abs().clamp(min=1e-300)).max()))
+        warm_it = np.concatenate([d["iters"].cpu().numpy() for d in pd])
+        warm_st = np.concatenate([d["status"].cpu().numpy() for d in pd])
+        ok = (plain_st == 0) & ((warm_st & ~4) == 0)
+        winfo.update({
+            "ms_per_step_with_network": float(np.mean(kern_ms)),
+            "ms_per_step_plain": float(np.mean(plain_ms)),
+            "ms_inference_alone": float(np.mean(infer_ms)),
+            "speedup": float(np.mean(plain_ms) / np.mean(kern_ms)),
+            "newton_iters_plain": float(plain_it[ok].mean()),
+            "newton_iters_warm": float(warm_it[ok].mean()),
+            "fallbacks": int(((warm_st & 4) != 0).sum()),
+            "max_rel_diff_vs_plain_E_sampled": dmax,
+            "sample": f"first {k_s} cells of every patch",
+        })
+    else:
+        kern_ms = timed(lambda: b.launch(stream.cuda_stream))
     kern_s = float(np.mean(kern_ms)) * 1e-3
     # per-cell work of the last step
     flop = flop1 = 0.0
@@ -458,7 +520,44 @@ def run_batch(args):
         "roofline": roof,
         "roofline_other": other,
     }
+    if winfo is not None:
+        result["warm_start"] = winfo
+        result["config"]["warm_start"] = ("one network per group count, temperature guess "
+                                          "(guess kind 1); inference of every patch and the "
+                                          "batched solve replayed from one graph")
+        result["config"]["timing"] = "HIP events around each graph launch (inference + solve)"
     print(json.dumps(result), flush=True)
+
+
+def train_warm_patches(ngs, args):
+    """One warm-start network per group count, trained on solver pairs of
+    patches of that group count drawn with the training seed (their own
+    random tables; untimed)."""
+    import torch
+
+    from paper_2407_18304_amd import synth, warmstart
+    from paper_2407_18304_amd import workloads as W
+
+    nets, info = {}, {"train_pairs_per_group_count": args.train_cells, "epochs": args.epochs}
+    for ng in ngs:
+        t0 = time.perf_counter()
+        side = 32
+        layouts = W.patch_layouts(n_patches=max(1, args.train_cells // side ** 3),
+                                  seed=W.TRAIN_SEED, sides=(side,), ngs=(ng,))
+        dps = synth.device_patches(layouts, seed=W.TRAIN_SEED)
+        Xr, Yr, ok = warmstart.make_training_data_patches(dps)
+        t1 = time.perf_counter()
+        ws = warmstart.train(Xr, Yr, ok, epochs=args.epochs, batch=4096,
+                             holdout=min(1 << 16, int(ok.sum()) // 8),
+                             log=lambda m: print(f"N_g={ng} {m}", file=sys.stderr, flush=True))
+        torch.cuda.synchronize()
+        nets[ng] = ws
+        info[f"N_g={ng}"] = {"heldout_loss_first_last": [ws.history[0], ws.history[-1]],
+                             "pair_generation_s": t1 - t0,
+                             "training_s": time.perf_counter() - t1}
+        del dps, Xr, Yr, ok
+        torch.cuda.empty_cache()
+    return nets, info
 
 
 def cpu_baseline(dw, mode, target_s):

@@ -134,11 +134,18 @@ class DevicePatch:
     tables: dict         # device tensors edges, chi_lo, alpha
     dt: float
     c_hat: float
+    seed: int = None     # state seed (None: the patch workload's)
+
+    def consts(self):
+        u = W.UNITS["patches"]
+        return dict(c=u["c"], a_rad=u["a_rad"], h_over_k=1.0, c_v=1.5, dt=self.dt,
+                    c_hat=self.c_hat)
 
 
-def device_patches(layouts, dev="cuda", stream=None):
+def device_patches(layouts, dev="cuda", stream=None, seed=None):
     """Allocate and fill every patch of ``layouts`` in HBM (state as config2,
-    units of the patch family); cell numbers are the layouts' global ones."""
+    units of the patch family); cell numbers are the layouts' global ones.
+    seed: the state seed (default: the patch workload's)."""
     u = W.UNITS["patches"]
     dt = 1.0 / u["c"]
     f64 = dict(dtype=torch.float64, device=dev)
@@ -151,7 +158,7 @@ def device_patches(layouts, dev="cuda", stream=None):
               "v": torch.empty((3, n), **f64)}
         kap, T = torch.empty(n, **f64), torch.empty(n, **f64)
         tabs = {"edges": t(L.edges), "chi_lo": t(L.chi_lo), "alpha": t(L.alpha_chi)}
-        out.append(DevicePatch(L, st, kap, T, tabs, dt, u["c"]))
+        out.append(DevicePatch(L, st, kap, T, tabs, dt, u["c"], seed))
     fill_patches(out, stream)
     return out
 
@@ -172,7 +179,7 @@ def fill_patches(dps, stream=None):
             st["E_g"].data_ptr(), st["F_g"].data_ptr(), st["rho"].data_ptr(),
             st["e_gas"].data_ptr(), st["v"].data_ptr(), dp.kappa.data_ptr(), dp.T.data_ptr(),
             dp.tables["edges"].data_ptr(), gl.data_ptr(), L.n, L.cell0,
-            np.uint64(W.PATCH_SPEC["seed"]).item(), L.ng, len(W._GL_X), sp["t_kind"],
+            np.uint64(W.PATCH_SPEC["seed"] if dp.seed is None else dp.seed).item(), L.ng, len(W._GL_X), sp["t_kind"],
             sp["t_p"][0], sp["t_p"][1], sp["k_kind"], sp["k_p"][0], sp["k_p"][1],
             1.0 / (dp.dt * u["c"]), W.TRAD_RANGE[0], W.TRAD_RANGE[1], sp["vmax"], u["c"],
             u["a_rad"], 1.5, stream)

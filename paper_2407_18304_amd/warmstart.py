@@ -14,6 +14,7 @@ import ctypes as C
 import dataclasses
 import json
 import math
+import types
 import os
 
 import numpy as np
@@ -220,10 +221,11 @@ class WarmStart:
     y_std: torch.Tensor
     history: list
 
-    def guess(self, state, tables, kappa, consts, S_g=None, kind=1, fused=True):
+    def guess(self, state, tables, kappa, consts, S_g=None, kind=1, fused=True, out=None):
         """Newton guess for the cells of `state`: kind 1 E_gas [n], kind 0
-        [N_g+1, n].  fused: one kernel (mgrhd_mlp_infer); else features,
-        forward and guess as three steps."""
+        [N_g+1, n].  fused: one kernel (mgrhd_mlp_infer), written into `out`
+        when given (nothing is allocated then); else features, forward and
+        guess as three steps."""
         if not fused:
             X = features(state, tables, kappa, consts, self.x_mean, self.x_istd)
             Yn = self.net.forward(X)
@@ -231,7 +233,12 @@ class WarmStart:
                               kind)
         ng, n = state["E_g"].shape
         shape = (n,) if kind == 1 else (ng + 1, n)
-        g = torch.empty(shape, dtype=torch.float64, device=state["E_g"].device)
+        if out is not None:
+            if tuple(out.shape) != shape or out.dtype != torch.float64 or not out.is_contiguous():
+                raise ValueError(f"guess buffer must be contiguous float64 {shape}")
+            g = out
+        else:
+            g = torch.empty(shape, dtype=torch.float64, device=state["E_g"].device)
         args, keep = _phys(state, tables, kappa, consts, S_g)
         _check(_lib().mgrhd_mlp_infer(self.net._h, *args, _f32(self.x_mean, "x_mean"),
                                       _f32(self.x_istd, "x_istd"), _f32(self.y_mean, "y_mean"),
@@ -255,6 +262,21 @@ class WarmStart:
         t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
         return WarmStart(net, t(d["x_mean"]), t(d["x_istd"]), t(d["y_mean"]), t(d["y_std"]),
                          list(d["history"]))
+
+
+@dataclasses.dataclass
+class PatchWarmStart:
+    """Warm starts for batches of patches: one network per group count."""
+    nets: dict           # N_g -> WarmStart
+
+    def guesses(self, dps, outs, kind=1):
+        """Write the Newton guess of every patch (synth.DevicePatch-like:
+        state, tables, kappa, layout.ng, consts()) into its buffer in `outs`
+        with one fused inference launch per patch on the current stream;
+        allocates nothing, so the launches can be captured in a graph."""
+        for dp, out in zip(dps, outs):
+            self.nets[dp.layout.ng].guess(dp.state, dp.tables, dp.kappa, dp.consts(), kind=kind,
+                                          out=out)
 
 
 def _stats(M, axis):
@@ -281,6 +303,22 @@ def make_training_data(dw, consts, mean_mode=mgrhd.MEAN_PPL_FIXED):
     torch.cuda.synchronize()
     ok = status == 0
     return Xraw, Yraw, ok
+
+
+def make_training_data_patches(dps, mean_mode=mgrhd.MEAN_PPL_FIXED):
+    """Solver pairs from device patches (synth.DevicePatch) that share one
+    group count, each with its own edges, opacity table, dt and c_hat: raw
+    features [F x n], targets [n x O] and the converged mask over all their
+    cells.  The patches' states are overwritten by the solve."""
+    Xs, Ys, oks = [], [], []
+    for dp in dps:
+        shim = types.SimpleNamespace(state=dp.state, tables=dp.tables, kappa=dp.kappa,
+                                     n=dp.layout.n, ng=dp.layout.ng)
+        X, Y, ok = make_training_data(shim, dp.consts(), mean_mode)
+        Xs.append(X)
+        Ys.append(Y)
+        oks.append(ok)
+    return torch.cat(Xs, 1).contiguous(), torch.cat(Ys, 0).contiguous(), torch.cat(oks)
 
 
 def train(Xraw, Yraw, ok, *, epochs=8, batch=4096, lr=2e-3, n_hidden=128, seed=20240718,

@@ -192,3 +192,74 @@ def test_batch_bad_table_patch(gpl, scope):
                 assert np.array_equal(d[k].cpu().numpy(), w.state[k]), k
         else:
             assert (st >= 0).all() and (st != mgrhd.ST_BAD_TABLE).all()
+
+
+def test_batch_warm_start_matches_plain():
+    """One network per group count, trained on solver pairs of patches drawn
+    with the training seed; the warm-started batch (temperature guess, one
+    fused inference launch per patch) gives the plain batch's results, eagerly
+    and replayed from one graph holding the inference launches and the batched
+    solve.  (Networks this small, trained on other patches' tables, need not
+    save Newton steps: the step counts are printed, and the benchmark measures
+    the gain of fully trained networks.)"""
+    from paper_2407_18304_amd import warmstart
+    ngs = (8, 16)
+    nets = {}
+    for ng in ngs:
+        tl = W.patch_layouts(n_patches=4, seed=W.TRAIN_SEED, sides=(16,), ngs=(ng,))
+        tdps = synth.device_patches(tl, seed=W.TRAIN_SEED)
+        X, Y, ok = warmstart.make_training_data_patches(tdps)
+        nets[ng] = warmstart.train(X, Y, ok, epochs=6, batch=1024, holdout=2048)
+        assert nets[ng].history[-1] < nets[ng].history[0]
+        del tdps, X, Y, ok
+    layouts = W.patch_layouts(n_patches=8, sides=(6, 8, 10), ngs=ngs)
+    dps = synth.device_patches(layouts)
+    inputs = [synth.patch_to_host(dp) for dp in dps]
+    pd = _patch_dicts(dps)
+    b = mgrhd.Batch(pd, mean_mode=1, polish=1, **_consts())
+    b.run()
+    torch.cuda.synchronize()
+    keys = ("E_g", "F_g", "e_gas", "v")
+    plain = [({k: d[k].cpu().numpy() for k in keys}, d["iters"].cpu().numpy(),
+              d["status"].cpu().numpy()) for d in pd]
+    guesses = [torch.empty(dp.layout.n, dtype=torch.float64, device="cuda") for dp in dps]
+    bw = mgrhd.Batch([dict(d, guess=g) for d, g in zip(pd, guesses)], mean_mode=1, polish=1,
+                     guess_kind=1, **_consts())
+    pws = warmstart.PatchWarmStart(nets)
+    stream = torch.cuda.Stream()
+
+    def check(label):
+        it_p, it_w = [], []
+        for w, d, (gp, ip, sp) in zip(inputs, pd, plain):
+            gw = {k: d[k].cpu().numpy() for k in keys}
+            iw, sw = d["iters"].cpu().numpy(), d["status"].cpu().numpy()
+            ok = (sp == 0) & ((sw & ~4) == 0)
+            assert ok.mean() > 0.95, label
+            for k, e in U.field_errors(w, gw, gp, ok).items():
+                assert e < U.TOL_COUNT_FLIP, (label, k, e)
+            it_p.append(ip[ok])
+            it_w.append(iw[ok])
+        ip, iw = np.concatenate(it_p), np.concatenate(it_w)
+        print(f"{label}: Newton steps per cell plain {ip.mean():.3f}, warm {iw.mean():.3f}")
+
+    synth.fill_patches(dps)                   # the same inputs again
+    with torch.cuda.stream(stream):
+        pws.guesses(dps, guesses)
+        bw.run(stream.cuda_stream)
+    stream.synchronize()
+    check("eager")
+    g = torch.cuda.CUDAGraph()
+    synth.fill_patches(dps)
+    with torch.cuda.graph(g, stream=stream, capture_error_mode="thread_local"):
+        pws.guesses(dps, guesses)
+        bw.run(stream.cuda_stream)
+    torch.cuda.synchronize()
+    for rep in range(2):
+        synth.fill_patches(dps)
+        x = torch.randn(1000, device="cuda").sum()      # eager work between replays
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            g.replay()
+        stream.synchronize()
+        check(f"graph replay {rep}")
+        del x
