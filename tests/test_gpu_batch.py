@@ -263,3 +263,47 @@ def test_batch_warm_start_matches_plain():
         stream.synchronize()
         check(f"graph replay {rep}")
         del x
+
+
+def test_batch_full_size_sampled():
+    """The benchmark's 2000-patch workload at full size (1.44e8 cells, about
+    155 GB of state), drawn on the device and solved in the benchmark's
+    launch configuration (the library's default tuning, captured in a graph
+    and launched); sampled cells of sampled patches against the oracle on the
+    same inputs."""
+    layouts = W.patch_layouts()
+    assert len(layouts) == 2000
+    rng = np.random.default_rng(11)
+    pick = np.sort(rng.choice(len(layouts), 24, replace=False))
+    dps = synth.device_patches(layouts)
+    try:
+        samples = {}
+        for p in pick:
+            n = layouts[p].n
+            idx = np.sort(rng.choice(n, min(32, n), replace=False))
+            samples[p] = (idx, synth.patch_to_host(dps[p], idx))    # pristine inputs
+        pd = _patch_dicts(dps)
+        b = mgrhd.Batch(pd, mean_mode=1, polish=1, **_consts())
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            b.capture(stream.cuda_stream)
+        b.launch(stream.cuda_stream)
+        stream.synchronize()
+        res = {}
+        for p, (idx, w) in samples.items():
+            it = torch.as_tensor(idx, device="cuda")
+            d = pd[p]
+            res[p] = ({"E_g": d["E_g"][:, it].cpu().numpy(), "F_g": d["F_g"][:, :, it].cpu().numpy(),
+                       "e_gas": d["e_gas"][it].cpu().numpy(), "v": d["v"][:, it].cpu().numpy()},
+                      d["iters"][it].cpu().numpy(), d["outer"][it].cpu().numpy(),
+                      d["status"][it].cpu().numpy())
+        assert all(bool((d["status"] >= 0).all()) for d in pd)
+        b.close()
+    finally:
+        del dps
+        pd = None
+        torch.cuda.empty_cache()
+    # the oracle on all sampled cells at once per patch
+    for p, (idx, w) in samples.items():
+        U.compare(w, res[p], U.run_oracle(w, 1),
+                  label=f"full-size batch: patch {p} (N_g={w.ng}), {len(idx)} sampled cells")
