@@ -242,8 +242,11 @@ int mgrhd_transport1d_stage(double* E_out, double* F_out, double* e_gas_out, dou
  * captured in a hipGraph) and run the per-cell solver of mgrhd_source_update
  * with lanes per cell = next power of two >= N_g / groups_per_lane.
  * A batch owns a small device work list and counter (allocated by
- * mgrhd_batch_create, freed by mgrhd_batch_destroy); runs of one batch on
- * several streams at once race on that counter. */
+ * mgrhd_batch_create, freed by mgrhd_batch_destroy; the work list is rebuilt
+ * by mgrhd_batch_set_tuning when the cells per item change, which must not
+ * overlap a run of the batch); mgrhd_batch_run, _capture and _launch
+ * allocate nothing.  Runs of one batch on several streams at once race on
+ * that counter. */
 typedef struct {
   double* E_g;                /* [N_g][n] in/out */
   double* F_g;                /* [3][N_g][n] in/out */
@@ -275,7 +278,9 @@ int mgrhd_batch_create(const mgrhd_patch* patches, int32_t n_patches, int32_t me
                        const mgrhd_options* opt, mgrhd_batch** out);
 /* Tuning knobs (see the autotuner): groups per lane (2 or 4), resident
  * workgroups per CU (0 = as many as fit), cells per work item.  Defaults:
- * 2, 0, 256 (with work items taken per workgroup, item scope 1).  The
+ * 2, 0, 256 (with work items taken per workgroup, item scope 1).  A new
+ * cells-per-item value rebuilds the device work list here (MGRHD_E_DEVICE if
+ * that fails; the batch then refuses to run until a rebuild succeeds).  The
  * per-cell state machine is compiled for every lane count per cell (a wave
  * dispatches on its item's patch). */
 int mgrhd_batch_set_tuning(mgrhd_batch* b, int32_t groups_per_lane, int32_t blocks_per_cu,

@@ -377,13 +377,15 @@ int mgrhd_batch_set_tuning(mgrhd_batch* bt, int32_t groups_per_lane, int32_t blo
   if (bt->max_groups > groups_per_lane * 64) return MGRHD_E_OPTION;
   const bool changed = groups_per_lane != bt->groups_per_lane ||
                        blocks_per_cu != bt->blocks_per_cu || chunk_cells != bt->chunk;
+  if (changed) drop_graph(bt);
   bt->groups_per_lane = groups_per_lane;
   bt->blocks_per_cu = blocks_per_cu;
   if (chunk_cells != bt->chunk) {
+    // the work list is rebuilt here, never inside run / capture / launch
     bt->chunk = chunk_cells;
     bt->items_dirty = true;
+    return build_items(bt);
   }
-  if (changed) drop_graph(bt);
   return 0;
 }
 
@@ -411,20 +413,18 @@ int mgrhd_batch_get_tuning(const mgrhd_batch* bt, int32_t* groups_per_lane,
 }
 
 static int enqueue(mgrhd_batch* bt, hipStream_t stream) {
-  if (bt->items_dirty) {
-    const int rc = build_items(bt);
-    if (rc) return rc;
-  }
+  if (bt->items_dirty) return MGRHD_E_DEVICE;  // the last rebuild of the work list failed
   if (bt->n_items == 0) return 0;
   BatchFn fn = batch_fn(bt->groups_per_lane, bt->mode, bt->scope);
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kBlock, 0) != hipSuccess || nb < 1)
     nb = 1;
   if (bt->blocks_per_cu > 0 && bt->blocks_per_cu < nb) nb = bt->blocks_per_cu;
-  int dev = 0, cus = 256;
-  hipDeviceProp_t prop;
-  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-    cus = prop.multiProcessorCount;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus < 1)
+    cus = 256;
   int64_t blocks = (int64_t)cus * nb;
   // never more takers than items: waves (scope 0) or workgroups (scope 1)
   if (bt->scope) {
@@ -447,10 +447,7 @@ int mgrhd_batch_run(mgrhd_batch* bt, mgrhd_stream_t stream) {
 int mgrhd_batch_capture(mgrhd_batch* bt, mgrhd_stream_t stream) {
   if (!bt) return MGRHD_E_NULL;
   drop_graph(bt);
-  if (bt->items_dirty) {
-    const int rc = build_items(bt);
-    if (rc) return rc;
-  }
+  if (bt->items_dirty) return MGRHD_E_DEVICE;
   hipStream_t st = (hipStream_t)stream;
   hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return (int)e;

@@ -15,6 +15,8 @@
 // B[8(l/16) .. +7][l%16], and accumulators C[4(l/16) .. +3][l%16].
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -928,17 +930,20 @@ int mgrhd_mlp_infer(mgrhd_mlp* m, const double* E_g, const double* F_g, const do
   const int ldx = m->k_pad[0] + 8;
   const size_t lds = sizeof(__bf16) * (size_t)kTile * ((ldx > kHPad ? ldx : kHPad) + kHPad) +
                      sizeof(float) * (size_t)p.ng;
-  static int cus = 0;
-  if (cus == 0) {
-    int dev = 0;
-    hipDeviceProp_t prop;
-    cus = (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-              ? prop.multiProcessorCount : 256;
-    // the input tile of 138 groups needs more than the default 64 KB of LDS
-    if (hipFuncSetAttribute((const void*)k_infer, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            96 * 1024) != hipSuccess)
-      return MGRHD_E_DEVICE;
-  }
+  // once per process: the input tile of the widest networks needs more than
+  // the default 64 KB of dynamic LDS
+  static std::once_flag once;
+  static bool lds_ok = false;
+  std::call_once(once, [] {
+    lds_ok = hipFuncSetAttribute((const void*)k_infer, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 96 * 1024) == hipSuccess;
+  });
+  if (!lds_ok) return MGRHD_E_DEVICE;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus < 1)
+    cus = 256;
   const int64_t tiles = (n + kTile - 1) / kTile;
   const int64_t blocks = tiles < (int64_t)cus * 4 ? tiles : (int64_t)cus * 4;
   hipLaunchKernelGGL(k_infer, dim3((unsigned)blocks), dim3(256), lds, s, q);
