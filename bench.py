@@ -36,8 +36,8 @@ PEAK_HBM = 8.0e12            # bytes/s
 PEAK_FP64 = 78.6e12          # FP64 vector FLOP/s
 
 
-SOLVER_SOURCES = ("source_update.hip", "solver_kernel.hpp", "solver_device.hpp",
-                  "planck_device.hpp", "planck_poly.inc")
+SOLVER_SOURCES = ("source_update.hip", "source_update_full.hip", "solver_kernel.hpp",
+                  "solver_device.hpp", "planck_device.hpp", "planck_poly.inc")
 
 
 def kernel_source_sha() -> str:
@@ -200,7 +200,8 @@ def main():
     ceil_hbm = PEAK_HBM / bpc
     lpc_, g_, w_ = mgrhd.get_variant(ng, args.mode)
     td = "true" if (dw.t_exp != 0.0 or dw.stim) else "false"
-    kname = f"k_source_update<{g_}, {lpc_}, {args.mode}, {w_}, {td}>"
+    full = "true" if lpc_ * g_ == ng else "false"
+    kname = f"k_source_update<{g_}, {lpc_}, {args.mode}, {w_}, {td}, {full}>"
     traffic = None if (args.warm or args.cells or args.mode != 1) else measured_traffic(name, kname)
     roof_alu = {"bound": "alu", "achieved": achieved_fl / 1e12, "peak": PEAK_FP64 / 1e12,
                 "unit": "TFLOP/s", "frac": achieved_fl / PEAK_FP64, "traffic": traffic,

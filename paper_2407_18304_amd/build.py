@@ -25,8 +25,9 @@ HIPCC_FLAGS = [
 ]
 
 LIBS = {
-    "libmgrhd.so": ["source_update.hip", "source_update_tdep.hip", "batch.hip", "mlp.hip",
-                    "imex.hip", "transport1d.hip"],
+    "libmgrhd.so": ["source_update.hip", "source_update_tdep.hip", "source_update_full.hip",
+                    "source_update_tdep_full.hip", "batch.hip", "mlp.hip", "imex.hip",
+                    "transport1d.hip"],
     "libmgrhd_synth.so": ["synth.hip"],
 }
 

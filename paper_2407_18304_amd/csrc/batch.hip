@@ -86,22 +86,33 @@ __device__ __forceinline__ T load_uniform(const T* p) {
 
 // Lanes per cell for N_g groups at G groups per lane: the next power of two
 // >= N_g / G.  The state machine is compiled for each.
-template <int G, int MODE, int NGM, class LS, class Q>
+template <int G, int MODE, int NGM, bool FULL, class LS, class Q>
+__device__ __forceinline__ void run_item_lpc(const KArgs& a, const Tables<NGM>& tab,
+                                             const LS& ls, int lane, Q q, int lpc) {
+  switch (lpc) {
+    case 1: run_cells<G, 1, MODE, NGM, false, FULL>(a, tab, ls, lane, q); break;
+    case 2: run_cells<G, 2, MODE, NGM, false, FULL>(a, tab, ls, lane, q); break;
+    case 4: run_cells<G, 4, MODE, NGM, false, FULL>(a, tab, ls, lane, q); break;
+    case 8: run_cells<G, 8, MODE, NGM, false, FULL>(a, tab, ls, lane, q); break;
+    case 16: run_cells<G, 16, MODE, NGM, false, FULL>(a, tab, ls, lane, q); break;
+    case 32: run_cells<G, 32, MODE, NGM, false, FULL>(a, tab, ls, lane, q); break;
+    default:  // a patch wider than 32 lanes of G groups
+      if constexpr (G * 32 < NGM) run_cells<G, kWave, MODE, NGM, false, FULL>(a, tab, ls, lane, q);
+      break;
+  }
+}
+
+// TRY_FULL: items whose N_g fills every slot (N_g = lanes per cell x G) run
+// the state machine compiled for that case (no per-slot group checks).
+template <int G, int MODE, int NGM, bool TRY_FULL, class LS, class Q>
 __device__ __forceinline__ void run_item(const KArgs& a, const Tables<NGM>& tab, const LS& ls,
                                          int lane, Q q) {
   int lpc = 1;
   while (lpc * G < a.ng) lpc <<= 1;
-  switch (lpc) {
-    case 1: run_cells<G, 1, MODE, NGM>(a, tab, ls, lane, q); break;
-    case 2: run_cells<G, 2, MODE, NGM>(a, tab, ls, lane, q); break;
-    case 4: run_cells<G, 4, MODE, NGM>(a, tab, ls, lane, q); break;
-    case 8: run_cells<G, 8, MODE, NGM>(a, tab, ls, lane, q); break;
-    case 16: run_cells<G, 16, MODE, NGM>(a, tab, ls, lane, q); break;
-    case 32: run_cells<G, 32, MODE, NGM>(a, tab, ls, lane, q); break;
-    default:  // a patch wider than 32 lanes of G groups
-      if constexpr (G * 32 < NGM) run_cells<G, kWave, MODE, NGM>(a, tab, ls, lane, q);
-      break;
-  }
+  if (TRY_FULL && lpc * G == a.ng)
+    run_item_lpc<G, MODE, NGM, true>(a, tab, ls, lane, q, lpc);
+  else
+    run_item_lpc<G, MODE, NGM, false>(a, tab, ls, lane, q, lpc);
 }
 
 // 2 groups per lane leave room in LDS for the old-time fluxes and velocity
@@ -139,7 +150,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_batch(BatchArgs b) {
       }
       continue;
     }
-    run_item<G, MODE>(a, tab, ls, lane, WaveRange{item.c0, item.c1});
+    run_item<G, MODE, NGM, false>(a, tab, ls, lane, WaveRange{item.c0, item.c1});
   }
 }
 
@@ -182,7 +193,7 @@ __global__ __launch_bounds__(kBlock, WPE) void k_batch_wg(BatchArgs b) {
         if (a.outer) a.outer[i] = 0;
       }
     } else {
-      run_item<G, MODE>(a, tab, ls, lane, BlockQueue{&taken, item.c0, item.c1});
+      run_item<G, MODE, NGM, true>(a, tab, ls, lane, BlockQueue{&taken, item.c0, item.c1});
     }
     __syncthreads();  // the item is done before the next one resets the counter
   }

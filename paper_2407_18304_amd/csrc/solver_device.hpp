@@ -487,13 +487,24 @@ struct CellState {
   double vF[G];        // v_k . F_g,k of the current outer pass
 };
 
-template <int G, int LPC, int MODE, int NGM, bool TD = false, class LS>
+// N_g as the state machine sees it.  FULL: every slot of every lane holds a
+// group (N_g = LPC * G), so the count is a compile-time constant and the
+// per-slot checks g >= N_g compile away (fewer registers, branches and
+// execution-mask changes).
+template <int G, int LPC, bool FULL>
+__device__ __forceinline__ int group_count(const KArgs& a) {
+  static_assert(!FULL || LPC > 0, "FULL needs a compile-time lane count");
+  return FULL ? LPC * G : a.ng;
+}
+
+template <int G, int LPC, int MODE, int NGM, bool TD = false, bool FULL = false,
+          class LS>
 __device__ __forceinline__ void load_cell(const KArgs& a, const Tables<NGM>& t, int j, int64_t i,
                                           CellState<G>& s, const LS& ls) {
   // 1/tau_g and 1/J_gg are constants of the cell unless the means depend on T
   constexpr bool kFixedTau = MODE != MGRHD_MEAN_PPL_FREE && !TD;
   const int64_t n = a.n;
-  const int ng = a.ng;
+  const int ng = group_count<G, LPC, FULL>(a);
   s.i = i;
   s.st = MGRHD_ST_OK;
   s.steps = 0;
@@ -581,11 +592,11 @@ __device__ __forceinline__ void load_cell(const KArgs& a, const Tables<NGM>& t, 
   }
 }
 
-template <int G, int LPC, class LS>
+template <int G, int LPC, bool FULL = false, class LS>
 __device__ __forceinline__ void finish_cell(const KArgs& a, int j, CellState<G>& s,
                                             const LS& ls, bool store) {
   const int64_t n = a.n, i = s.i;
-  const int ng = a.ng;
+  const int ng = group_count<G, LPC, FULL>(a);
   if (store) {
     double bad = (isfinite(s.egas_new) && isfinite(s.v[0]) && isfinite(s.v[1]) && isfinite(s.v[2]))
                      ? 0.0 : 1.0;
@@ -626,7 +637,7 @@ __device__ __forceinline__ void finish_cell(const KArgs& a, int j, CellState<G>&
 }
 
 // End of an inner pass with result rc (0 converged, 1 max_newton, 2 T <= 0).
-template <int G, int LPC, class LS>
+template <int G, int LPC, bool FULL = false, class LS>
 __device__ __forceinline__ void newton_done(const KArgs& a, int j, CellState<G>& s,
                                             const LS& ls, int rc) {
   if (s.k_out == 0 && s.warm && rc != 0 && !s.fell_back) {
@@ -643,7 +654,7 @@ __device__ __forceinline__ void newton_done(const KArgs& a, int j, CellState<G>&
   if (rc == 1) s.st |= MGRHD_ST_NEWTON_MAXIT;
   if (rc == 2) {
     s.st |= MGRHD_ST_INVALID;
-    finish_cell<G, LPC>(a, j, s, ls, false);
+    finish_cell<G, LPC, FULL>(a, j, s, ls, false);
     return;
   }
   // conservative energy update (Sec. 3)
@@ -657,11 +668,12 @@ __device__ __forceinline__ void newton_done(const KArgs& a, int j, CellState<G>&
 
 // Temperature-only start: at the cached material state, eq. Rnew inverted for
 // E_g and F_R,g = 0 (eq. FGFR) are linear in R_g alone; take that R_g.
-template <int G, int LPC, int MODE, int NGM, bool TD = false, class LS>
+template <int G, int LPC, int MODE, int NGM, bool TD = false, bool FULL = false,
+          class LS>
 __device__ __forceinline__ void group_balance(const KArgs& a, const Tables<NGM>& t, int j,
                                               CellState<G>& s, const LS& ls,
                                               const Cache<G>& c) {
-  const int ng = a.ng;
+  const int ng = group_count<G, LPC, FULL>(a);
   const double cdt = a.cdt;
   const double ic2 = a.ic2;
 #pragma unroll
@@ -684,11 +696,12 @@ __device__ __forceinline__ void group_balance(const KArgs& a, const Tables<NGM>&
 
 // Newton consumer: residual of eq. FGFR at the cached material state, the
 // elimination of eq. matrix, and the step.
-template <int G, int LPC, int MODE, int NGM, bool TD = false, class LS>
+template <int G, int LPC, int MODE, int NGM, bool TD = false, bool FULL = false,
+          class LS>
 __device__ __forceinline__ void newton_step(const KArgs& a, const Tables<NGM>& t, int j,
                                             CellState<G>& s, const LS& ls,
                                             const Cache<G>& c) {
-  const int ng = a.ng;
+  const int ng = group_count<G, LPC, FULL>(a);
   const double cc = a.cc;
   const double cdt = a.cdt;
   const double ic2 = a.ic2;
@@ -730,11 +743,11 @@ __device__ __forceinline__ void newton_step(const KArgs& a, const Tables<NGM>& t
   const bool conv = fabs(FG) * s.ietot < a.eps && cc * sumAbs * s.ietot < a.eps;
   if (s.polish_left < 0 && conv) s.polish_left = a.polish;
   if (s.polish_left == 0) {
-    newton_done<G, LPC>(a, j, s, ls, 0);
+    newton_done<G, LPC, FULL>(a, j, s, ls, 0);
     return;
   }
   if (s.polish_left < 0 && s.steps >= a.max_newton) {
-    newton_done<G, LPC>(a, j, s, ls, 1);
+    newton_done<G, LPC, FULL>(a, j, s, ls, 1);
     return;
   }
   // eq. matrix eliminated: dx0, then dx_g = -a_g - b_g dx0
@@ -747,7 +760,7 @@ __device__ __forceinline__ void newton_step(const KArgs& a, const Tables<NGM>& t
   double lam = 1.0;
   for (int h = 0; h < 30 && !(s.egv + lam * dx0 - s.ke > 0.0); ++h) lam *= 0.5;
   if (!(s.egv + lam * dx0 - s.ke > 0.0)) {
-    newton_done<G, LPC>(a, j, s, ls, 2);
+    newton_done<G, LPC, FULL>(a, j, s, ls, 2);
     return;
   }
   s.egv += lam * dx0;
@@ -757,17 +770,18 @@ __device__ __forceinline__ void newton_step(const KArgs& a, const Tables<NGM>& t
     --s.polish_left;
   else
     ++s.steps;
-  if (s.polish_left == 0) newton_done<G, LPC>(a, j, s, ls, 0);
+  if (s.polish_left == 0) newton_done<G, LPC, FULL>(a, j, s, ls, 0);
 }
 
 // Outer-stage consumer: flux update eq. numF1 with the outdated velocity,
 // momentum update, outer test.  Returns true when the next inner pass starts
 // (at the same temperature, so the caller reuses this evaluation).
-template <int G, int LPC, int MODE, int NGM, bool TD = false, class LS>
+template <int G, int LPC, int MODE, int NGM, bool TD = false, bool FULL = false,
+          class LS>
 __device__ __forceinline__ bool flux_step(const KArgs& a, const Tables<NGM>& t, int j,
                                           CellState<G>& s, const LS& ls,
                                           const Cache<G>& c) {
-  const int ng = a.ng;
+  const int ng = group_count<G, LPC, FULL>(a);
   const int64_t n = a.n, i = s.i;
   const double cdt = a.cdt;
   double dmom[3] = {0.0, 0.0, 0.0};
@@ -816,12 +830,12 @@ __device__ __forceinline__ bool flux_step(const KArgs& a, const Tables<NGM>& t, 
 #pragma unroll
   for (int d = 0; d < 3; ++d) s.v[d] = vn[d];
   if (dW < a.eps_out * s.etot) {
-    finish_cell<G, LPC>(a, j, s, ls, true);
+    finish_cell<G, LPC, FULL>(a, j, s, ls, true);
     return false;
   }
   if (s.k_out + 1 >= a.max_outer) {
     s.st |= MGRHD_ST_OUTER_MAXIT;
-    finish_cell<G, LPC>(a, j, s, ls, true);
+    finish_cell<G, LPC, FULL>(a, j, s, ls, true);
     return false;
   }
   ++s.k_out;
@@ -861,7 +875,8 @@ struct BlockQueue {
   }
 };
 
-template <int G, int LPC, int MODE, int NGM, bool TD = false, class LS, class Q>
+template <int G, int LPC, int MODE, int NGM, bool TD = false, bool FULL = false, class LS,
+          class Q>
 __device__ __forceinline__ void run_cells(const KArgs& a, const Tables<NGM>& tab, const LS& ls,
                                           int lane, Q q) {
   static_assert(LPC >= 1 && LPC <= kWave && (LPC & (LPC - 1)) == 0, "lanes per cell");
@@ -883,8 +898,8 @@ __device__ __forceinline__ void run_cells(const KArgs& a, const Tables<NGM>& tab
       mine = __shfl(mine, lane - j, kWave);
       if (need) {
         if (mine < hi) {
-          load_cell<G, LPC, MODE, NGM, TD>(a, tab, j, mine, s, ls);
-          if (s.phase == P_EMPTY) finish_cell<G, LPC>(a, j, s, ls, false);
+          load_cell<G, LPC, MODE, NGM, TD, FULL>(a, tab, j, mine, s, ls);
+          if (s.phase == P_EMPTY) finish_cell<G, LPC, FULL>(a, j, s, ls, false);
         } else {
           s.phase = P_IDLE;
         }
@@ -900,10 +915,10 @@ __device__ __forceinline__ void run_cells(const KArgs& a, const Tables<NGM>& tab
     const double T = ((s.phase == P_FLUX ? s.egas_new : s.egv) - s.ke) * s.ircv;
     if (!(T > 0.0) || !isfinite(T)) {
       if (s.phase == P_NEWTON)
-        newton_done<G, LPC>(a, j, s, ls, 2);
+        newton_done<G, LPC, FULL>(a, j, s, ls, 2);
       else {
         s.st |= MGRHD_ST_INVALID;
-        finish_cell<G, LPC>(a, j, s, ls, false);
+        finish_cell<G, LPC, FULL>(a, j, s, ls, false);
       }
       continue;
     }
@@ -916,14 +931,15 @@ __device__ __forceinline__ void run_cells(const KArgs& a, const Tables<NGM>& tab
       ot.fT = a.t_exp != 0.0 ? exp(a.t_exp * log(T * a.itref)) : 1.0;
       ot.stim = a.stim != 0;
     }
-    evaluate<G, LPC, MODE, NGM, TD>(tab, a.ng, j, s.lpc, T, aT4, a.hk, s.rho_kappa, Ecur, c, ot);
+    evaluate<G, LPC, MODE, NGM, TD>(tab, group_count<G, LPC, FULL>(a), j, s.lpc, T, aT4, a.hk,
+                                    s.rho_kappa, Ecur, c, ot);
 
     if (s.phase == P_FLUX) {
-      if (!flux_step<G, LPC, MODE, NGM, TD>(a, tab, j, s, ls, c)) continue;
+      if (!flux_step<G, LPC, MODE, NGM, TD, FULL>(a, tab, j, s, ls, c)) continue;
       // the next inner pass starts at this temperature: fall through
     }
-    if (s.elim) group_balance<G, LPC, MODE, NGM, TD>(a, tab, j, s, ls, c);
-    newton_step<G, LPC, MODE, NGM, TD>(a, tab, j, s, ls, c);
+    if (s.elim) group_balance<G, LPC, MODE, NGM, TD, FULL>(a, tab, j, s, ls, c);
+    newton_step<G, LPC, MODE, NGM, TD, FULL>(a, tab, j, s, ls, c);
   }
 }
 

@@ -1,7 +1,8 @@
 // solver_kernel.hpp -- the single-table source-update kernel and the list of
-// its compiled variants, shared by the two translation units that instantiate
-// it (T-independent opacity in source_update.hip, T-dependent opacity in
-// source_update_tdep.hip, so the two compile in parallel).
+// its compiled variants, shared by the four translation units that
+// instantiate it (T-independent or T-dependent opacity, any N_g or
+// N_g = LPC * G: source_update.hip, source_update_tdep.hip,
+// source_update_full.hip, source_update_tdep_full.hip, compiled in parallel).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -9,8 +10,9 @@
 
 namespace mgrhd {
 
-// TD: the opacity depends on temperature (evaluated at every iterate)
-template <int G, int LPC, int MODE, int WPE, bool TD>
+// TD: the opacity depends on temperature (evaluated at every iterate).
+// FULL: N_g = LPC * G (the launcher checks), every slot holds a group.
+template <int G, int LPC, int MODE, int WPE, bool TD, bool FULL>
 __global__ __launch_bounds__(kBlock, WPE) void k_source_update(KArgs a) {
   constexpr int NGM = G * LPC;
   __shared__ Tables<NGM> tab;
@@ -35,7 +37,7 @@ __global__ __launch_bounds__(kBlock, WPE) void k_source_update(KArgs a) {
     return;
   }
 
-  run_cells<G, LPC, MODE, NGM, TD>(a, tab, ls, lane, BlockQueue{&taken, lo, hi});
+  run_cells<G, LPC, MODE, NGM, TD, FULL>(a, tab, ls, lane, BlockQueue{&taken, lo, hi});
 }
 
 using KernelFn = void (*)(KArgs);
@@ -50,15 +52,26 @@ using KernelFn = void (*)(KArgs);
   X(2, 8, 4) X(2, 32, 4)
 
 // the three mean modes of one variant
-#define MGRHD_VARIANT_MODES(G_, LPC_, WPE_, TD_)                                   \
+#define MGRHD_VARIANT_MODES(G_, LPC_, WPE_, TD_, FULL_)                            \
   {                                                                               \
-    k_source_update<G_, LPC_, MGRHD_MEAN_PC, WPE_, TD_>,                          \
-        k_source_update<G_, LPC_, MGRHD_MEAN_PPL_FIXED, WPE_, TD_>,               \
-        k_source_update<G_, LPC_, MGRHD_MEAN_PPL_FREE, WPE_, TD_>                 \
+    k_source_update<G_, LPC_, MGRHD_MEAN_PC, WPE_, TD_, FULL_>,                   \
+        k_source_update<G_, LPC_, MGRHD_MEAN_PPL_FIXED, WPE_, TD_, FULL_>,        \
+        k_source_update<G_, LPC_, MGRHD_MEAN_PPL_FREE, WPE_, TD_, FULL_>          \
   }
 
-// The kernels of variant k (in MGRHD_FOR_EACH_VARIANT order) for a
-// T-dependent opacity, by mean mode (source_update_tdep.hip).
-KernelFn tdep_kernel(int k, int mode);
+// A kernel table: the kernel of variant k (in MGRHD_FOR_EACH_VARIANT order)
+// and mean mode, or nullptr; the including file defines MGRHD_TABLE_ROW.
+#define MGRHD_DEFINE_KERNEL_TABLE(NAME)                                            \
+  KernelFn NAME(int k, int mode) {                                                \
+    static const KernelFn fns[][3] = {MGRHD_FOR_EACH_VARIANT(MGRHD_TABLE_ROW)};   \
+    constexpr int n = (int)(sizeof(fns) / sizeof(fns[0]));                        \
+    if (k < 0 || k >= n || mode < 0 || mode > 2) return nullptr;                  \
+    return fns[k][mode];                                                          \
+  }
+
+// The kernels of the other three translation units, by variant and mode.
+KernelFn tdep_kernel(int k, int mode);       // TD, any N_g (source_update_tdep.hip)
+KernelFn full_kernel(int k, int mode);       // N_g = LPC * G (source_update_full.hip)
+KernelFn tdep_full_kernel(int k, int mode);  // both (source_update_tdep_full.hip)
 
 }  // namespace mgrhd

@@ -6,14 +6,15 @@
 // j holding group k*LPC + j (G slots per lane), so that at each slot a wave
 // evaluates Planck edges in a narrow band of x and mostly takes one branch.
 // Registers hold the Newton unknowns R_g, E_g^(t)+S_g and v.F_g of the
-// current outer pass; the fluxes F_g of the pass and the per-cell constants
-// 1/tau_g, 1/J_gg sit in per-lane LDS slots; F_g^(t) and v^(t) stay in HBM.
+// current outer pass; the fluxes F_g of the pass, the per-cell constants
+// 1/tau_g, 1/J_gg and the old-time F_g^(t), v^(t) sit in per-lane LDS slots.
 // Group sums (sum R_g, sum |F_R,g|, the two sums of the arrowhead
 // elimination, the momentum change, the outer test) are butterflies inside
 // the LPC lanes (DPP where the distance fits a row), so every lane of a cell
 // holds bit-identical scalars and takes the same branches.
 //
-// Persistent state machine.  Each wave owns a contiguous chunk of cells.  One
+// Persistent state machine.  Each workgroup owns a contiguous range of cells,
+// which its waves take through a counter in LDS.  One
 // trip of the main loop performs exactly one material evaluation (G Planck
 // edges, one edge handed over from a neighbour lane, and G group means per
 // lane) for every active cell group, followed by
@@ -21,9 +22,14 @@
 // update of the outer stage.  The flux-stage evaluation is also the first
 // evaluation of the next inner pass (the pass restarts at the same
 // temperature).  A cell group whose cell has finished takes the next cell of
-// the wave's chunk at the top of the next trip, so cells that converge early
-// free their lanes instead of idling until the slowest cell of the wave is
-// done.
+// the workgroup's range at the top of the next trip, so cells that converge
+// early free their lanes instead of idling until the slowest cell of the wave
+// is done.
+//
+// Kernel tables.  Each variant is compiled four times: for a T-independent or
+// T-dependent opacity, and for any N_g or N_g = LPC * G (every slot holds a
+// group, so the per-slot group checks compile away); the launcher picks the
+// N_g = LPC * G kernel whenever the group count fills the variant exactly.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -42,22 +48,27 @@ namespace mgrhd {
 // Variant table
 struct Variant {
   int lpc, g, wpe;  // lanes per cell, groups per lane, minimum waves per SIMD
-  KernelFn fn[2][3];  // [temperature-dependent opacity][mean mode]
-  int blocks_per_cu[2][3];
+  // [temperature-dependent opacity][N_g = lpc * g][mean mode]
+  KernelFn fn[2][2][3];
+  int blocks_per_cu[2][2][3];
 };
 
 #define MGRHD_VARIANT(G_, LPC_, WPE_) \
-  {LPC_, G_, WPE_, {MGRHD_VARIANT_MODES(G_, LPC_, WPE_, false), {}}, {}},
+  {LPC_, G_, WPE_, {{MGRHD_VARIANT_MODES(G_, LPC_, WPE_, false, false), {}}, {}}, {}},
 static Variant kVariants[] = {MGRHD_FOR_EACH_VARIANT(MGRHD_VARIANT)};
 #undef MGRHD_VARIANT
 constexpr int kNumVariants = (int)(sizeof(kVariants) / sizeof(kVariants[0]));
 
-// the T-dependent kernels come from their own translation unit
-static void link_tdep_kernels() {
+// the other kernels come from their own translation units
+static void link_kernels() {
   static std::once_flag once;
   std::call_once(once, [] {
     for (int k = 0; k < kNumVariants; ++k)
-      for (int m = 0; m < 3; ++m) kVariants[k].fn[1][m] = tdep_kernel(k, m);
+      for (int m = 0; m < 3; ++m) {
+        kVariants[k].fn[1][0][m] = tdep_kernel(k, m);
+        kVariants[k].fn[0][1][m] = full_kernel(k, m);
+        kVariants[k].fn[1][1][m] = tdep_full_kernel(k, m);
+      }
   });
 }
 
@@ -91,17 +102,16 @@ static Variant* choose_variant(int ng) {
 }
 
 // resident workgroups per CU of a variant (queried once)
-static int resident_blocks(Variant* v, int td, int mode) {
+static int resident_blocks(Variant* v, int td, int full, int mode) {
   std::lock_guard<std::mutex> lk(g_mutex);
-  if (v->blocks_per_cu[td][mode] == 0) {
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, v->fn[td][mode], kBlock, 0) !=
+  int& nb = v->blocks_per_cu[td][full][mode];
+  if (nb == 0) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, v->fn[td][full][mode], kBlock, 0) !=
             hipSuccess ||
         nb < 1)
       nb = 1;
-    v->blocks_per_cu[td][mode] = nb;
   }
-  return v->blocks_per_cu[td][mode];
+  return nb;
 }
 
 static int num_cus() {
@@ -221,7 +231,7 @@ int mgrhd_source_update(double* E_g, double* F_g, const double* rho, double* e_g
 
   Variant* var = choose_variant(ng);
   if (!var) return MGRHD_E_OPTION;
-  link_tdep_kernels();
+  link_kernels();
 
   KArgs a;
   std::memset(&a, 0, sizeof(a));
@@ -263,9 +273,11 @@ int mgrhd_source_update(double* E_g, double* F_g, const double* rho, double* e_g
   // persistent grid: one resident wave of workgroups, never more workgroups
   // than there are cell groups to fill them
   const int64_t needed = (n_cells * var->lpc + kBlock - 1) / kBlock;
-  const int64_t resident = (int64_t)num_cus() * resident_blocks(var, td, op->mean_mode);
+  const int full = var->lpc * var->g == ng ? 1 : 0;  // every slot holds a group
+  const int64_t resident =
+      (int64_t)num_cus() * resident_blocks(var, td, full, op->mean_mode);
   const int64_t blocks = needed < resident ? needed : resident;
-  hipLaunchKernelGGL(var->fn[td][op->mean_mode], dim3((unsigned)blocks), dim3(kBlock), 0,
+  hipLaunchKernelGGL(var->fn[td][full][op->mean_mode], dim3((unsigned)blocks), dim3(kBlock), 0,
                      (hipStream_t)stream, a);
   const hipError_t err = hipGetLastError();
   return err == hipSuccess ? 0 : (int)err;

@@ -5,13 +5,8 @@
 
 namespace mgrhd {
 
-KernelFn tdep_kernel(int k, int mode) {
-#define MGRHD_TDEP_VARIANT(G_, LPC_, WPE_) MGRHD_VARIANT_MODES(G_, LPC_, WPE_, true),
-  static const KernelFn fns[][3] = {MGRHD_FOR_EACH_VARIANT(MGRHD_TDEP_VARIANT)};
-#undef MGRHD_TDEP_VARIANT
-  constexpr int n = (int)(sizeof(fns) / sizeof(fns[0]));
-  if (k < 0 || k >= n || mode < 0 || mode > 2) return nullptr;
-  return fns[k][mode];
-}
+#define MGRHD_TABLE_ROW(G_, LPC_, WPE_) MGRHD_VARIANT_MODES(G_, LPC_, WPE_, true, false),
+MGRHD_DEFINE_KERNEL_TABLE(tdep_kernel)
+#undef MGRHD_TABLE_ROW
 
 }  // namespace mgrhd
