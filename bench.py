@@ -590,7 +590,19 @@ def cpu_baseline(dw, mode, target_s):
         dt = time.perf_counter() - t0
         m = m2
     return {"value": m / dt, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
-            "sample": f"{m} random cells of the same workload, {dt:.1f} s on {cores} threads"}
+            "sample": f"{m} random cells of the same workload, {dt:.1f} s on {cores} threads",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 if __name__ == "__main__":

@@ -73,6 +73,9 @@ def test_host_argument_errors_need_no_device(lib):
     op = mgrhd.OpacityParams(0, 1, None, None, None, None)
     assert lib.mgrhd_source_update(None, None, None, None, None, 10, None, C.byref(op), 1.0,
                                    1.0, None, C.byref(o)) == mgrhd.E_SIZE
+    op = mgrhd.OpacityParams(mgrhd.MAX_GROUPS + 1, 1, None, None, None, None)   # above the maximum
+    assert lib.mgrhd_source_update(None, None, None, None, None, 10, None, C.byref(op), 1.0,
+                                   1.0, None, C.byref(o)) == mgrhd.E_SIZE
     op = mgrhd.OpacityParams(4, 7, None, None, None, None)
     assert lib.mgrhd_source_update(None, None, None, None, None, 10, None, C.byref(op), 1.0,
                                    1.0, None, C.byref(o)) == mgrhd.E_MODE

@@ -62,6 +62,17 @@ def test_parity_ragged_group_counts(ng):
     _check(w, 2)
 
 
+@pytest.mark.parametrize("ng", [128, 255, 256])
+def test_parity_maximum_group_counts(ng):
+    """Up to the ABI's maximum of 256 groups (4 groups per lane on all 64
+    lanes of a wave; 255 leaves the last slot empty)."""
+    w = W.config1(cells=np.arange(300), ng=ng)
+    lpc, g, _ = mgrhd.get_variant(ng)
+    assert lpc * g >= ng
+    _check(w, 1)
+    _check(w, 2)
+
+
 @pytest.mark.parametrize("n", [1, 63, 65, 257, 1000])
 def test_parity_ragged_cell_counts(n):
     w = W.config1(cells=np.arange(n))
