@@ -383,7 +383,6 @@ def run_batch(args):
     elif args.tune:
         from paper_2407_18304_amd import autotune
         autotune.tune_batch(b, lambda: synth.fill_patches(dps), reps=1,
-                            path=os.path.join(ROOT, "gpurun_out", "tuning_batch.json"),
                             log=lambda m: print(m, file=sys.stderr, flush=True))
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
