@@ -480,8 +480,9 @@ struct CellState {
   int lpc;  // lanes per cell (run-time copy of the template value)
   int phase, st, steps, passes, k_out, polish_left;
   bool warm, fell_back, elim;
-  double rho, rho_kappa, egas0, etot, ke, egv, egas_new;
-  double ircv, ietot;  // 1/(rho c_v), 1/E_tot
+  double rho, rho_kappa, egas0, etot, ke;
+  double egv;  // the E_gas iterate; in the outer stage the updated E_gas of the pass
+  double ircv;  // 1/(rho c_v)
   double v[3];
   double R[G], E0[G];  // F_g^(t) and v^(t) stay in global memory, F_k in LDS
   double vF[G];        // v_k . F_g,k of the current outer pass
@@ -566,12 +567,10 @@ __device__ __forceinline__ void load_cell(const KArgs& a, const Tables<NGM>& t, 
   const double bad = cell_sum<LPC>(ok ? 0.0 : 1.0, s.lpc);
   s.ke = 0.5 * s.rho * (s.v[0] * s.v[0] + s.v[1] * s.v[1] + s.v[2] * s.v[2]);
   s.etot = s.egas0 + a.icc * sumE;  // E_tot of Sec. 3
-  s.ietot = 1.0 / s.etot;
   ok = bad == 0.0 && (s.egas0 - s.ke) > 0.0 && s.etot > 0.0;
   s.warm = a.guess != nullptr;
   s.elim = false;
   s.egv = s.egas0;
-  s.egas_new = s.egas0;
   if (ok && s.warm) {
     s.egv = a.guess[i];
     if (a.guess_kind == 1) {
@@ -594,11 +593,11 @@ __device__ __forceinline__ void load_cell(const KArgs& a, const Tables<NGM>& t, 
 
 template <int G, int LPC, bool FULL = false, class LS>
 __device__ __forceinline__ void finish_cell(const KArgs& a, int j, CellState<G>& s,
-                                            const LS& ls, bool store) {
+                                            const LS& ls, bool store, double egas_new = 0.0) {
   const int64_t n = a.n, i = s.i;
   const int ng = group_count<G, LPC, FULL>(a);
   if (store) {
-    double bad = (isfinite(s.egas_new) && isfinite(s.v[0]) && isfinite(s.v[1]) && isfinite(s.v[2]))
+    double bad = (isfinite(egas_new) && isfinite(s.v[0]) && isfinite(s.v[1]) && isfinite(s.v[2]))
                      ? 0.0 : 1.0;
 #pragma unroll
     for (int k = 0; k < G; ++k) {
@@ -621,7 +620,7 @@ __device__ __forceinline__ void finish_cell(const KArgs& a, int j, CellState<G>&
         for (int d = 0; d < 3; ++d) a.F[((int64_t)d * ng + g) * n + i] = ls.F(d, k);
       }
       if (j == 0) {
-        a.egas[i] = s.egas_new;
+        a.egas[i] = egas_new;
         a.v[i] = s.v[0];
         a.v[n + i] = s.v[1];
         a.v[2 * n + i] = s.v[2];
@@ -662,7 +661,7 @@ __device__ __forceinline__ void newton_done(const KArgs& a, int j, CellState<G>&
 #pragma unroll
   for (int k = 0; k < G; ++k) sumR += s.R[k];
   sumR = cell_sum<LPC>(sumR, s.lpc);
-  s.egas_new = s.egas0 - a.cc * sumR;
+  s.egv = s.egas0 - a.cc * sumR;  // E_gas^(t+1) of this pass
   s.phase = P_FLUX;
 }
 
@@ -740,7 +739,9 @@ __device__ __forceinline__ void newton_step(const KArgs& a, const Tables<NGM>& t
   sumA = cell_sum<LPC>(sumA, s.lpc);
   sumB = cell_sum<LPC>(sumB, s.lpc);
   const double FG = s.egv - s.egas0 + cc * sumR;
-  const bool conv = fabs(FG) * s.ietot < a.eps && cc * sumAbs * s.ietot < a.eps;
+  // the stop test of Sec. 3, |F_G| / E_tot < eps and (c/c_hat) sum |F_R,g| / E_tot < eps
+  const double tol = a.eps * s.etot;
+  const bool conv = fabs(FG) < tol && cc * sumAbs < tol;
   if (s.polish_left < 0 && conv) s.polish_left = a.polish;
   if (s.polish_left == 0) {
     newton_done<G, LPC, FULL>(a, j, s, ls, 0);
@@ -825,17 +826,18 @@ __device__ __forceinline__ bool flux_step(const KArgs& a, const Tables<NGM>& t, 
   }
   dW = cell_sum<LPC>(dW, s.lpc) * a.cdt_ic2;
   const double ke_new = 0.5 * s.rho * (vn[0] * vn[0] + vn[1] * vn[1] + vn[2] * vn[2]);
-  s.egv = s.egas_new + (ke_new - s.ke);
+  const double egas_new = s.egv;
+  s.egv = egas_new + (ke_new - s.ke);
   s.ke = ke_new;
 #pragma unroll
   for (int d = 0; d < 3; ++d) s.v[d] = vn[d];
   if (dW < a.eps_out * s.etot) {
-    finish_cell<G, LPC, FULL>(a, j, s, ls, true);
+    finish_cell<G, LPC, FULL>(a, j, s, ls, true, egas_new);
     return false;
   }
   if (s.k_out + 1 >= a.max_outer) {
     s.st |= MGRHD_ST_OUTER_MAXIT;
-    finish_cell<G, LPC, FULL>(a, j, s, ls, true);
+    finish_cell<G, LPC, FULL>(a, j, s, ls, true, egas_new);
     return false;
   }
   ++s.k_out;
@@ -912,7 +914,7 @@ __device__ __forceinline__ void run_cells(const KArgs& a, const Tables<NGM>& tab
     if (s.phase != P_NEWTON && s.phase != P_FLUX) continue;
 
     // one material evaluation at this cell's current temperature
-    const double T = ((s.phase == P_FLUX ? s.egas_new : s.egv) - s.ke) * s.ircv;
+    const double T = (s.egv - s.ke) * s.ircv;
     if (!(T > 0.0) || !isfinite(T)) {
       if (s.phase == P_NEWTON)
         newton_done<G, LPC, FULL>(a, j, s, ls, 2);
