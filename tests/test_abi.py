@@ -114,3 +114,34 @@ def test_recommended_mean_mode():
         mgrhd.recommend_mean_mode([1.0, 0.5, 2.0])
     with pytest.raises(mgrhd.MgrhdError):
         mgrhd.recommend_mean_mode([1.0])
+
+
+def test_transport_and_batch_host_checks(lib):
+    """Argument checks of the transport stage and the batch handle that return
+    before anything touches the device (the pointers are never dereferenced)."""
+    f = C.c_void_p(64)
+    L = lib
+    L.mgrhd_transport1d_stage.restype = C.c_int
+    L.mgrhd_transport1d_stage.argtypes = ([C.c_void_p] * 12 + [C.c_double, C.c_double, C.c_int64,
+                                          C.c_int32] + [C.c_double] * 4 + [C.c_void_p] * 5)
+    g = C.c_void_p(128)
+
+    def stage(E_out=f, E1=g, a=0.0, n=10, ng=4, dx=1.0, dt=1.0, E0=None, rho=f):
+        return L.mgrhd_transport1d_stage(E_out, f, f, f, E1, g, g, g, E0, E0, E0, E0, a, 1.0, n,
+                                         ng, dx, dt, 1.0, 1.0, rho, f, f, f, None)
+
+    assert stage(n=0) == 0                          # empty column: nothing to do
+    assert stage(ng=0) == mgrhd.E_SIZE
+    assert stage(ng=mgrhd.MAX_GROUPS + 1) == mgrhd.E_SIZE
+    assert stage(n=-1) == mgrhd.E_SIZE
+    assert stage(rho=None) == mgrhd.E_NULL
+    assert stage(a=0.5) == mgrhd.E_NULL             # U0 needed when a != 0
+    assert stage(dx=0.0) == mgrhd.E_SCALAR
+    assert stage(dt=-1.0) == mgrhd.E_SCALAR
+    assert stage(E_out=g, E1=g) == mgrhd.E_OPTION   # output over the stencil's input
+    L.mgrhd_batch_set_item_scope.restype = C.c_int
+    L.mgrhd_batch_set_item_scope.argtypes = [C.c_void_p, C.c_int32]
+    L.mgrhd_batch_get_item_scope.restype = C.c_int32
+    L.mgrhd_batch_get_item_scope.argtypes = [C.c_void_p]
+    assert L.mgrhd_batch_set_item_scope(None, 1) == mgrhd.E_NULL
+    assert L.mgrhd_batch_get_item_scope(None) == mgrhd.E_NULL
