@@ -173,6 +173,31 @@ def main():
         plain_it = iters.cpu().numpy().copy()
         plain_st = status.cpu().numpy().copy()
         plain_state = {k: st[k].clone() for k in ("E_g", "F_g", "e_gas", "v")}
+        # the fused inference kernel alone, on pristine inputs, against the
+        # matrix-core peak: the products it computes (temperature output only)
+        restore()
+        gbuf = torch.empty(n, dtype=torch.float64, device=dev)
+        ws.guess(st, tab, dw.kappa, dw.consts(), out=gbuf)
+        inf_ms = []
+        for _ in range(args.steps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            ws.guess(st, tab, dw.kappa, dw.consts(), out=gbuf)
+            e1.record(stream)
+            stream.synchronize()
+            inf_ms.append(e0.elapsed_time(e1))
+        del gbuf
+        n_in, n_h = 2 + 3 * ng, ws.net.n_hidden
+        mlp_flop = 2.0 * (n_in * n_h + 2 * n_h * n_h + n_h * 1) * n
+        mlp_bytes = (8 * (4 * ng + 5) + 8) * n     # state read, guess written
+        inf_s = float(np.mean(inf_ms)) * 1e-3
+        winfo["inference"] = {
+            "ms": inf_s * 1e3,
+            "roofline": {"bound": "mfma", "achieved": mlp_flop / inf_s / 1e12, "peak": 2500.0,
+                         "unit": "TFLOP/s", "frac": mlp_flop / inf_s / 2.5e15,
+                         "flop_per_cell": mlp_flop / n, "dtype": "bf16 products, fp32 accumulation"},
+            "hbm": {"achieved": mlp_bytes / inf_s / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                    "frac": mlp_bytes / inf_s / PEAK_HBM, "bytes_per_cell": mlp_bytes / n}}
     t0, t1, kern_ms = timed(args.warm)
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = n * args.steps / (t1 - t0)
