@@ -301,6 +301,16 @@ int mgrhd_batch_run(mgrhd_batch* b, mgrhd_stream_t stream);
 /* Capture mgrhd_batch_run into a hipGraph kept by the batch; launch replays
  * it (capturing on first use). */
 int mgrhd_batch_capture(mgrhd_batch* b, mgrhd_stream_t stream);
+/* Autotuner of the batch's launch shape: times a fixed list of candidate
+ * tunings (groups per lane 2 or 4, items per wave or per workgroup, 256 or
+ * 1024 cells per item) on copies of the first min(n, 1024) cells of every
+ * patch, restored before each run, with HIP events on `stream`, and keeps the
+ * fastest (as mgrhd_batch_set_tuning and mgrhd_batch_set_item_scope would).
+ * The patches' own arrays are only read.  The copies and the sample's work
+ * list are allocated for the call and freed before it returns (device memory
+ * of about twice the sampled state); synchronous; drops a captured graph if
+ * the tuning changes.  Returns 0 or MGRHD_E_*. */
+int mgrhd_batch_tune(mgrhd_batch* b, mgrhd_stream_t stream);
 int mgrhd_batch_launch(mgrhd_batch* b, mgrhd_stream_t stream);
 /* Total cells of the batch. */
 int64_t mgrhd_batch_cells(const mgrhd_batch* b);
@@ -331,6 +341,15 @@ int64_t mgrhd_mlp_num_params(const mgrhd_mlp* m);
  * row-major) then b1..b4 */
 int mgrhd_mlp_get_params(const mgrhd_mlp* m, float* host, int32_t which);
 int mgrhd_mlp_set_params(mgrhd_mlp* m, const float* host);
+/* Save / load the network's parameters (FP32, the order of
+ * mgrhd_mlp_get_params) with its dimensions, in a small binary file: an
+ * 8-byte tag "MGRHDMLP", int32 version 1, int32 n_in, n_hidden, n_out, int64
+ * n_params, then the parameters, in host byte order.  load accepts only a
+ * file of this network's dimensions (MGRHD_E_SIZE otherwise); an unreadable
+ * or unwritable file is MGRHD_E_OPTION.  The input/output normalisation
+ * statistics belong to the caller.  Synchronous. */
+int mgrhd_mlp_save(const mgrhd_mlp* m, const char* path);
+int mgrhd_mlp_load(mgrhd_mlp* m, const char* path);
 int mgrhd_mlp_forward(mgrhd_mlp* m, const float* X_fm, int64_t ld_x, int64_t rows, float* Y,
                       mgrhd_stream_t stream);
 /* gradients of mean((Y - Y_target)^2) into the handle; loss_out (device, may

@@ -500,4 +500,149 @@ void mgrhd_batch_destroy(mgrhd_batch* bt) {
   delete bt;
 }
 
+// ---------------------------------------------------------------------------
+// Autotuner: every candidate launch shape runs on copies of the first
+// kTuneCells cells of every patch (restored before each run), timed with HIP
+// events; the fastest is kept.  The caller's arrays are only read.
+static constexpr int64_t kTuneCells = 1024;
+
+namespace {
+struct TuneCandidate {
+  int32_t groups_per_lane, scope;
+  int64_t chunk;
+};
+constexpr TuneCandidate kTuneCandidates[] = {
+    {2, 0, 1024}, {4, 0, 1024}, {2, 1, 256}, {2, 1, 1024}, {2, 2, 256}, {4, 2, 1024}};
+
+struct TuneBuffers {
+  double* pristine = nullptr;
+  double* work = nullptr;
+  int32_t* ints = nullptr;
+  ~TuneBuffers() {
+    if (pristine) (void)hipFree(pristine);
+    if (work) (void)hipFree(work);
+    if (ints) (void)hipFree(ints);
+  }
+};
+}  // namespace
+
+int mgrhd_batch_tune(mgrhd_batch* bt, mgrhd_stream_t stream) {
+  if (!bt) return MGRHD_E_NULL;
+  if (bt->items_dirty) return MGRHD_E_DEVICE;
+  if (bt->n_cells == 0) return 0;
+  hipStream_t st = (hipStream_t)stream;
+  // sample layout: per patch the first ns cells of every row of every field
+  const int32_t np = bt->n_patches;
+  std::vector<int64_t> ns(np), off(np);
+  int64_t nd = 0, ni = 0;
+  auto doubles_of = [&](const KArgs& a, int64_t m) {
+    int64_t d = (int64_t)a.ng * m * 4 + m * 5;  // E_g, F_g, rho, e_gas, v
+    if (a.kappa) d += m;
+    if (a.S) d += (int64_t)a.ng * m;
+    if (a.guess) d += a.guess_kind == 1 ? m : (int64_t)(a.ng + 1) * m;
+    return d;
+  };
+  for (int32_t p = 0; p < np; ++p) {
+    const KArgs& a = bt->h_patches[p];
+    ns[p] = std::min<int64_t>(a.n, kTuneCells);
+    off[p] = nd;
+    nd += doubles_of(a, ns[p]);
+    ni += 3 * ns[p];
+  }
+  TuneBuffers buf;
+  if (hipMalloc(&buf.pristine, sizeof(double) * nd) != hipSuccess ||
+      hipMalloc(&buf.work, sizeof(double) * nd) != hipSuccess ||
+      hipMalloc(&buf.ints, sizeof(int32_t) * ni) != hipSuccess)
+    return MGRHD_E_DEVICE;
+  // the sample batch: the same patches over the work copies
+  mgrhd_batch tmp;
+  tmp.n_patches = np;
+  tmp.mode = bt->mode;
+  tmp.max_groups = bt->max_groups;
+  tmp.h_patches = bt->h_patches;
+  int64_t io = 0;
+  hipError_t e = hipSuccess;
+  for (int32_t p = 0; p < np && e == hipSuccess; ++p) {
+    const KArgs& a = bt->h_patches[p];
+    KArgs& t = tmp.h_patches[p];
+    const int64_t m = ns[p];
+    double* w = buf.work + off[p];
+    double* q = buf.pristine + off[p];
+    // copy `rows` rows of m cells (row pitch a.n) of field src into the sample
+    auto take = [&](const double* src, int64_t rows) -> double* {
+      if (e == hipSuccess && m > 0)
+        e = hipMemcpy2DAsync(q, sizeof(double) * m, src, sizeof(double) * a.n,
+                             sizeof(double) * m, rows, hipMemcpyDeviceToDevice, st);
+      double* here = w;
+      w += rows * m;
+      q += rows * m;
+      return here;
+    };
+    t.n = m;
+    t.E = take(a.E, a.ng);
+    t.F = take(a.F, 3 * (int64_t)a.ng);
+    t.rho = take(a.rho, 1);
+    t.egas = take(a.egas, 1);
+    t.v = take(a.v, 3);
+    t.kappa = a.kappa ? take(a.kappa, 1) : nullptr;
+    t.S = a.S ? take(a.S, a.ng) : nullptr;
+    t.guess = a.guess ? take(a.guess, a.guess_kind == 1 ? 1 : a.ng + 1) : nullptr;
+    t.iters = buf.ints + io;
+    t.outer = buf.ints + io + m;
+    t.status = buf.ints + io + 2 * m;
+    io += 3 * m;
+    tmp.n_cells += m;
+  }
+  if (e != hipSuccess) return MGRHD_E_DEVICE;
+  int rc = 0;
+  if (hipMalloc(&tmp.d_patches, sizeof(KArgs) * np) != hipSuccess ||
+      hipMemcpyAsync(tmp.d_patches, tmp.h_patches.data(), sizeof(KArgs) * np,
+                     hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMalloc(&tmp.d_counter, sizeof(int32_t)) != hipSuccess)
+    rc = MGRHD_E_DEVICE;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+    rc = MGRHD_E_DEVICE;
+  float best_ms = 0.f;
+  const TuneCandidate* best = nullptr;
+  for (const TuneCandidate& c : kTuneCandidates) {
+    if (rc) break;
+    if (bt->max_groups > c.groups_per_lane * 64) continue;
+    tmp.groups_per_lane = c.groups_per_lane;
+    tmp.scope = c.scope;
+    tmp.blocks_per_cu = bt->blocks_per_cu;
+    if (c.chunk != tmp.chunk || tmp.items_dirty) {
+      tmp.chunk = c.chunk;
+      if (hipStreamSynchronize(st) != hipSuccess) { rc = MGRHD_E_DEVICE; break; }
+      if ((rc = build_items(&tmp)) != 0) break;
+    }
+    float ms = 0.f;
+    for (int rep = 0; rep < 2 && !rc; ++rep) {  // the first run warms up
+      if (hipMemcpyAsync(buf.work, buf.pristine, sizeof(double) * nd, hipMemcpyDeviceToDevice,
+                         st) != hipSuccess ||
+          hipEventRecord(e0, st) != hipSuccess)
+        rc = MGRHD_E_DEVICE;
+      if (!rc) rc = enqueue(&tmp, st);
+      if (!rc && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                  hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        rc = MGRHD_E_DEVICE;
+    }
+    if (!rc && (!best || ms < best_ms)) {
+      best = &c;
+      best_ms = ms;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(st);
+  if (tmp.d_patches) (void)hipFree(tmp.d_patches);
+  if (tmp.d_items) (void)hipFree(tmp.d_items);
+  if (tmp.d_counter) (void)hipFree(tmp.d_counter);
+  if (rc) return rc;
+  if (!best) return MGRHD_E_OPTION;
+  rc = mgrhd_batch_set_tuning(bt, best->groups_per_lane, bt->blocks_per_cu, best->chunk);
+  if (!rc) rc = mgrhd_batch_set_item_scope(bt, best->scope);
+  return rc;
+}
+
 }  // extern "C"

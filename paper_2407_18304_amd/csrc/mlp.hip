@@ -18,6 +18,7 @@
 #include <mutex>
 
 #include <cmath>
+#include <cstdio>
 #include <cstdint>
 #include <cstring>
 #include <new>
@@ -758,6 +759,46 @@ int mgrhd_mlp_set_params(mgrhd_mlp* m, const float* host) {
   return hipMemcpy(m->params, host, sizeof(float) * m->n_params, hipMemcpyHostToDevice) ==
                  hipSuccess
              ? 0 : MGRHD_E_DEVICE;
+}
+
+// File layout: 8-byte magic "MGRHDMLP", int32 version (1), int32 n_in,
+// n_hidden, n_out, int64 n_params, then n_params float32 parameters (the
+// order of mgrhd_mlp_get_params), little-endian as the host writes them.
+static const char kMlpMagic[8] = {'M', 'G', 'R', 'H', 'D', 'M', 'L', 'P'};
+
+int mgrhd_mlp_save(const mgrhd_mlp* m, const char* path) {
+  if (!m || !path) return MGRHD_E_NULL;
+  std::vector<float> p((size_t)m->n_params);
+  if (hipMemcpy(p.data(), m->params, sizeof(float) * p.size(), hipMemcpyDeviceToHost) !=
+      hipSuccess)
+    return MGRHD_E_DEVICE;
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return MGRHD_E_OPTION;
+  const int32_t head[4] = {1, m->n_in, m->n_hidden, m->n_out};
+  const int64_t np = m->n_params;
+  const bool ok = std::fwrite(kMlpMagic, 1, 8, f) == 8 && std::fwrite(head, 4, 4, f) == 4 &&
+                  std::fwrite(&np, 8, 1, f) == 1 &&
+                  std::fwrite(p.data(), sizeof(float), p.size(), f) == p.size();
+  return (std::fclose(f) == 0 && ok) ? 0 : MGRHD_E_OPTION;
+}
+
+int mgrhd_mlp_load(mgrhd_mlp* m, const char* path) {
+  if (!m || !path) return MGRHD_E_NULL;
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return MGRHD_E_OPTION;
+  char magic[8];
+  int32_t head[4];
+  int64_t np = -1;
+  bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, kMlpMagic, 8) == 0 &&
+            std::fread(head, 4, 4, f) == 4 && std::fread(&np, 8, 1, f) == 1;
+  // the file must describe this network exactly
+  ok = ok && head[0] == 1 && head[1] == m->n_in && head[2] == m->n_hidden &&
+       head[3] == m->n_out && np == m->n_params;
+  std::vector<float> p(ok ? (size_t)np : 0);
+  ok = ok && std::fread(p.data(), sizeof(float), p.size(), f) == p.size();
+  std::fclose(f);
+  if (!ok) return MGRHD_E_SIZE;
+  return mgrhd_mlp_set_params(m, p.data());
 }
 
 int mgrhd_mlp_forward(mgrhd_mlp* m, const float* X_fm, int64_t ld_x, int64_t rows, float* Y,

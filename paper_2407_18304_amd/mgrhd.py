@@ -244,7 +244,7 @@ class Patch(C.Structure):
                 ("dt", C.c_double), ("c_hat", C.c_double)]
 
 
-SYMBOLS += ["mgrhd_batch_set_item_scope", "mgrhd_batch_get_item_scope"]
+SYMBOLS += ["mgrhd_batch_set_item_scope", "mgrhd_batch_get_item_scope", "mgrhd_batch_tune"]
 SYMBOLS += ["mgrhd_batch_create", "mgrhd_batch_set_tuning", "mgrhd_batch_get_tuning",
             "mgrhd_batch_run", "mgrhd_batch_capture", "mgrhd_batch_launch", "mgrhd_batch_cells",
             "mgrhd_batch_destroy"]
@@ -333,6 +333,17 @@ class Batch:
         L.mgrhd_batch_get_item_scope.restype = C.c_int32
         L.mgrhd_batch_get_item_scope.argtypes = [C.c_void_p]
         return int(L.mgrhd_batch_get_item_scope(self._h))
+
+    def tune(self, stream=None):
+        """The library's own autotuner (mgrhd_batch_tune): candidate launch
+        shapes timed on copies of a sample of every patch; keeps the fastest."""
+        L = _batch_lib()
+        L.mgrhd_batch_tune.restype = C.c_int
+        L.mgrhd_batch_tune.argtypes = [C.c_void_p, C.c_void_p]
+        rc = L.mgrhd_batch_tune(self._h, self._stream(stream))
+        if rc != 0:
+            raise MgrhdError(rc, "mgrhd_batch_tune")
+        torch.cuda.synchronize()
 
     def set_tuning(self, groups_per_lane, blocks_per_cu, chunk_cells):
         rc = _batch_lib().mgrhd_batch_set_tuning(self._h, groups_per_lane, blocks_per_cu,

@@ -58,6 +58,10 @@ def _lib():
         L.mgrhd_mlp_infer.argtypes = [vp] + phys + [vp, vp, vp, vp, i32, vp, vp]
         L.mgrhd_mlp_gemm.restype = C.c_int
         L.mgrhd_mlp_gemm.argtypes = [vp, i32, i32, vp, i32, i32, vp, i32, i64, i32, i32, vp]
+        L.mgrhd_mlp_save.restype = C.c_int
+        L.mgrhd_mlp_save.argtypes = [vp, C.c_char_p]
+        L.mgrhd_mlp_load.restype = C.c_int
+        L.mgrhd_mlp_load.argtypes = [vp, C.c_char_p]
         L.mgrhd_mlp_destroy.restype = None
         L.mgrhd_mlp_destroy.argtypes = [vp]
         _ready = True
@@ -127,6 +131,15 @@ class MLP:
             bs.append(flat[o:o + dims[l + 1]])
             o += dims[l + 1]
         return Ws, bs
+
+    def save_params(self, path):
+        """The network's parameters and dimensions to a file (mgrhd_mlp_save)."""
+        _check(_lib().mgrhd_mlp_save(self._h, os.fsencode(path)), "mgrhd_mlp_save")
+
+    def load_params(self, path):
+        """Parameters from a file written by save_params for a network of the
+        same dimensions (mgrhd_mlp_load)."""
+        _check(_lib().mgrhd_mlp_load(self._h, os.fsencode(path)), "mgrhd_mlp_load")
 
     def forward(self, X_fm, rows=None):
         """X_fm: feature-major [n_in x ld] float32 device tensor -> [rows x n_out]."""

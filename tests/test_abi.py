@@ -145,3 +145,10 @@ def test_transport_and_batch_host_checks(lib):
     L.mgrhd_batch_get_item_scope.argtypes = [C.c_void_p]
     assert L.mgrhd_batch_set_item_scope(None, 1) == mgrhd.E_NULL
     assert L.mgrhd_batch_get_item_scope(None) == mgrhd.E_NULL
+    L.mgrhd_batch_tune.restype = C.c_int
+    L.mgrhd_batch_tune.argtypes = [C.c_void_p, C.c_void_p]
+    assert L.mgrhd_batch_tune(None, None) == mgrhd.E_NULL
+    for fn in ("mgrhd_mlp_save", "mgrhd_mlp_load"):
+        getattr(L, fn).restype = C.c_int
+        getattr(L, fn).argtypes = [C.c_void_p, C.c_char_p]
+        assert getattr(L, fn)(None, b"/nonexistent/net.bin") == mgrhd.E_NULL

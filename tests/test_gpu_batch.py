@@ -307,3 +307,29 @@ def test_batch_full_size_sampled():
     for p, (idx, w) in samples.items():
         U.compare(w, res[p], U.run_oracle(w, 1),
                   label=f"full-size batch: patch {p} (N_g={w.ng}), {len(idx)} sampled cells")
+
+
+def test_batch_library_autotuner_reads_only():
+    """mgrhd_batch_tune times its candidates on copies of a sample of every
+    patch: the patches' arrays are unchanged, the chosen tuning is one of the
+    candidates, and a run with it matches the oracle."""
+    layouts = W.patch_layouts(n_patches=10, seed=33, sides=(8, 12, 16), ngs=(8, 16, 64))
+    dps = synth.device_patches(layouts)
+    inputs = [synth.patch_to_host(dp) for dp in dps]
+    pd = _patch_dicts(dps)
+    before = [{k: d[k].clone() for k in ("E_g", "F_g", "e_gas", "v", "iters", "status")}
+              for d in pd]
+    b = mgrhd.Batch(pd, mean_mode=1, polish=1, **_consts())
+    b.tune()
+    for d, ref in zip(pd, before):
+        for k, v in ref.items():
+            assert torch.equal(d[k], v), k
+    g, blocks, chunk = b.get_tuning()
+    assert (g, b.get_item_scope(), chunk) in {(2, 0, 1024), (4, 0, 1024), (2, 1, 256),
+                                              (2, 1, 1024), (2, 2, 256), (4, 2, 1024)}
+    b.run()
+    torch.cuda.synchronize()
+    for w, d in zip(inputs, pd):
+        res = ({k: d[k].cpu().numpy() for k in ("E_g", "F_g", "e_gas", "v")},
+               d["iters"].cpu().numpy(), d["outer"].cpu().numpy(), d["status"].cpu().numpy())
+        U.compare(w, res, U.run_oracle(w, 1), label=f"tuned batch, patch N_g={w.ng} n={w.n}")

@@ -151,3 +151,23 @@ def test_warm_start_same_result_fewer_iterations():
     print(f"held-out loss {ws.history[0]:.3e} -> {ws.history[-1]:.3e}; Newton steps per cell: "
           f"plain {ip[ok].mean():.3f}, warm {iw[ok].mean():.3f}; fallbacks {((sw & 4) != 0).mean():.4f}")
     assert iw[ok].mean() < ip[ok].mean()
+
+
+def test_parameters_save_and_load(tmp_path):
+    """mgrhd_mlp_save / mgrhd_mlp_load: the parameters come back bit for bit;
+    a file of other dimensions is refused."""
+    a = warmstart.MLP(26, 9)
+    p = a.get_params().copy()
+    path = tmp_path / "net.bin"
+    a.save_params(path)
+    b = warmstart.MLP(26, 9, seed=5)
+    assert not np.array_equal(b.get_params(), p)
+    b.load_params(path)
+    assert np.array_equal(b.get_params(), p)
+    c = warmstart.MLP(30, 9)
+    with pytest.raises(mgrhd.MgrhdError) as e:
+        c.load_params(path)
+    assert e.value.code == mgrhd.E_SIZE
+    with pytest.raises(mgrhd.MgrhdError) as e:
+        b.load_params(tmp_path / "missing.bin")
+    assert e.value.code == mgrhd.E_OPTION
