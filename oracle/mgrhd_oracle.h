@@ -95,6 +95,13 @@ int ora_source_update(double* E_g, double* F_g, const double* rho, double* e_gas
                       const ora_opacity* op, double dt, double c_hat,
                       const ora_options* opt, int32_t n_threads);
 
+/* The same entry point under the name the GPU library's callers look for
+ * beside mgrhd_source_update (host arrays, no stream, a thread count). */
+int mgrhd_oracle_source_update(double* E_g, double* F_g, const double* rho, double* e_gas,
+                               double* v, int64_t n, const double* group_edges,
+                               const ora_opacity* op, double dt, double c_hat,
+                               const ora_options* opt, int32_t n_threads);
+
 /* ---- building blocks, exported so that tests can pin each one ---------- */
 
 /* Planck fraction P(x) = (15/pi^4) int_0^x t^3/(e^t-1) dt and its complement

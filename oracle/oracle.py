@@ -83,10 +83,11 @@ def lib():
         L.ora_arrowhead_solve.argtypes = [C.c_int32, C.c_double, dp, dp, C.c_double, dp, dp]
         L.ora_default_options.restype = None
         L.ora_default_options.argtypes = [C.POINTER(OraOptions)]
-        L.ora_source_update.restype = C.c_int
-        L.ora_source_update.argtypes = [dp, dp, dp, dp, dp, C.c_int64, dp,
-                                        C.POINTER(OraOpacity), C.c_double, C.c_double,
-                                        C.POINTER(OraOptions), C.c_int32]
+        for name in ("ora_source_update", "mgrhd_oracle_source_update"):
+            f = getattr(L, name)
+            f.restype = C.c_int
+            f.argtypes = [dp, dp, dp, dp, dp, C.c_int64, dp, C.POINTER(OraOpacity), C.c_double,
+                          C.c_double, C.POINTER(OraOptions), C.c_int32]
         _lib = L
     return _lib
 

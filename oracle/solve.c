@@ -516,3 +516,11 @@ int ora_source_update(double* E_g, double* F_g, const double* rho, double* e_gas
   free(tab);
   return rc;
 }
+
+int mgrhd_oracle_source_update(double* E_g, double* F_g, const double* rho, double* e_gas,
+                               double* v, int64_t n, const double* group_edges,
+                               const ora_opacity* op, double dt, double c_hat,
+                               const ora_options* opt, int32_t n_threads) {
+  return ora_source_update(E_g, F_g, rho, e_gas, v, n, group_edges, op, dt, c_hat, opt,
+                           n_threads);
+}

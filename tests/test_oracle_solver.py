@@ -393,3 +393,28 @@ def test_doppler_test_equilibrium_temperature(ora, ng):
     Fdiff = vx * (4.0 / 3.0 * B - (nuB[1:] - nuB[:-1]) / 3.0)
     big = B > 1e-6 * B.max()
     assert np.abs(st["F_g"][0, big, 0] / Fdiff[big] - 1).max() < gold["flux_rel_err_max"]
+
+
+def test_oracle_entry_point_alias(ora):
+    """mgrhd_oracle_source_update is the oracle's source update under the
+    GPU entry point's name: same arguments, same results."""
+    import ctypes as C
+    w = W.config0(cells=np.arange(50))
+    L = ora.lib()
+    res = []
+    for name in ("ora_source_update", "mgrhd_oracle_source_update"):
+        st = {k: np.ascontiguousarray(v, dtype=np.float64).copy() for k, v in w.state.items()}
+        op = ora.OraOpacity(w.ng, 1, ora._dp(np.ascontiguousarray(w.chi_lo)),
+                            ora._dp(np.ascontiguousarray(w.alpha_chi)), None,
+                            ora._dp(np.ascontiguousarray(w.kappa)), 0.0, 1.0, 0, 0)
+        o = ora.OraOptions()
+        L.ora_default_options(C.byref(o))
+        o.polish = 1
+        rc = getattr(L, name)(ora._dp(st["E_g"]), ora._dp(st["F_g"]), ora._dp(st["rho"]),
+                              ora._dp(st["e_gas"]), ora._dp(st["v"]), w.n,
+                              ora._dp(np.ascontiguousarray(w.edges)), C.byref(op), w.dt,
+                              w.c_hat, C.byref(o), 1)
+        assert rc == 0
+        res.append(st)
+    for k in ("E_g", "F_g", "e_gas", "v"):
+        assert np.array_equal(res[0][k], res[1][k]), k
