@@ -296,11 +296,6 @@ int mgrhd_batch_get_tuning(const mgrhd_batch* b, int32_t* groups_per_lane,
  * get returns the scope or MGRHD_E_NULL. */
 int mgrhd_batch_set_item_scope(mgrhd_batch* b, int32_t per_workgroup);
 int32_t mgrhd_batch_get_item_scope(const mgrhd_batch* b);
-/* Enqueue the counter reset and the persistent solver on `stream`. */
-int mgrhd_batch_run(mgrhd_batch* b, mgrhd_stream_t stream);
-/* Capture mgrhd_batch_run into a hipGraph kept by the batch; launch replays
- * it (capturing on first use). */
-int mgrhd_batch_capture(mgrhd_batch* b, mgrhd_stream_t stream);
 /* Autotuner of the batch's launch shape: times a fixed list of candidate
  * tunings (groups per lane 2 or 4, items per wave or per workgroup, 256 or
  * 1024 cells per item) on copies of the first min(n, 1024) cells of every
@@ -311,6 +306,11 @@ int mgrhd_batch_capture(mgrhd_batch* b, mgrhd_stream_t stream);
  * of about twice the sampled state); synchronous; drops a captured graph if
  * the tuning changes.  Returns 0 or MGRHD_E_*. */
 int mgrhd_batch_tune(mgrhd_batch* b, mgrhd_stream_t stream);
+/* Enqueue the counter reset and the persistent solver on `stream`. */
+int mgrhd_batch_run(mgrhd_batch* b, mgrhd_stream_t stream);
+/* Capture mgrhd_batch_run into a hipGraph kept by the batch; launch replays
+ * it (capturing on first use). */
+int mgrhd_batch_capture(mgrhd_batch* b, mgrhd_stream_t stream);
 int mgrhd_batch_launch(mgrhd_batch* b, mgrhd_stream_t stream);
 /* Total cells of the batch. */
 int64_t mgrhd_batch_cells(const mgrhd_batch* b);
