@@ -65,6 +65,27 @@ def measured_traffic(workload: str, kernel: str):
     return rec["traffic_bytes"]
 
 
+def copy_bandwidth(gib=4, reps=3):
+    """Achievable HBM bandwidth of a plain device-to-device copy of `gib` GiB
+    (bytes read + written per second, best of `reps`), the practical ceiling
+    beside the 8 TB/s peak."""
+    import torch
+    n = (gib << 30) // 8
+    a = torch.empty(n, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    best = 0.0
+    for _ in range(reps + 1):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        best = max(best, 2.0 * 8 * n / (e0.elapsed_time(e1) * 1e-3))
+    del a, b
+    torch.cuda.empty_cache()
+    return {"GB/s": best / 1e9, "bytes": 2 * 8 * n, "kind": "device-to-device copy"}
+
+
 def bytes_per_cell(ng: int) -> int:
     """Algorithmic HBM bytes per cell-update: E_g, F_g, E_gas, v read and
     written (8(4 N_g + 4) each way), rho and the opacity scale read (16), and
@@ -262,6 +283,7 @@ def main():
         "kernel_ms": {"mean": float(np.mean(kern_ms)), "min": float(np.min(kern_ms))},
         "roofline": roof,
         "roofline_other": other,
+        "hbm_copy_ceiling": copy_bandwidth(),
     }
     if args.warm:
         ok = (plain_st == 0) & ((stt & ~4) == 0)
