@@ -189,3 +189,22 @@ def test_deterministic_and_variant_independent():
     finally:
         mgrhd.set_variant(w.ng, 0, 0)
     assert mgrhd.get_variant(w.ng) == default
+
+
+def test_parity_random_combinations():
+    """Seeded random combinations of workload, group count (1 ... 128), cell
+    count, mean mode and closure, each against the oracle."""
+    rng = np.random.default_rng(8)
+    full = {"config0": 16 ** 3, "config1": 128 ** 3, "config2": 256 ** 3, "config5": 128 ** 3}
+    for case in range(40):
+        name = str(rng.choice(list(full)))
+        ng = int(rng.choice([1, 2, 3, 4, 5, 8, 9, 15, 16, 17, 31, 32, 33, 48, 63, 64, 65, 100,
+                             128]))
+        n = int(rng.integers(1, 1500))
+        mode = int(rng.integers(0, 3))
+        closure = int(rng.integers(0, 2))
+        cells = np.sort(rng.choice(full[name], n, replace=False))
+        w = (getattr(W, name)(cells=cells, ng=ng) if name in ("config1", "config2")
+             else getattr(W, name)(cells=cells))
+        U.compare(w, U.run_gpu(w, mode, closure=closure), U.run_oracle(w, mode, closure=closure),
+                  label=f"random case {case}: {name} N_g={w.ng} n={n} mode {mode} closure {closure}")
