@@ -333,3 +333,34 @@ def test_batch_library_autotuner_reads_only():
         res = ({k: d[k].cpu().numpy() for k in ("E_g", "F_g", "e_gas", "v")},
                d["iters"].cpu().numpy(), d["outer"].cpu().numpy(), d["status"].cpu().numpy())
         U.compare(w, res, U.run_oracle(w, 1), label=f"tuned batch, patch N_g={w.ng} n={w.n}")
+
+
+def test_batch_random_combinations():
+    """Seeded random batches (patch counts, sides 1 ... 12, group counts
+    1 ... 128, mean modes, groups per lane, item scopes, cells per item down
+    to 7), every patch against the oracle."""
+    rng = np.random.default_rng(3)
+    for case in range(15):
+        npat = int(rng.integers(2, 9))
+        sides = tuple(int(x) for x in rng.choice([1, 2, 3, 5, 7, 9, 12], 3))
+        ngs = tuple(int(x) for x in rng.choice([1, 2, 5, 8, 13, 16, 31, 32, 64, 65, 100, 128], 3))
+        mode = int(rng.integers(0, 3))
+        g = int(rng.choice([2, 4]))
+        scope = int(rng.integers(0, 3))
+        chunk = int(rng.choice([7, 64, 256, 1000]))
+        layouts = W.patch_layouts(n_patches=npat, seed=1000 + case, sides=sides, ngs=ngs)
+        dps = synth.device_patches(layouts)
+        inputs = [synth.patch_to_host(dp) for dp in dps]
+        pd = _patch_dicts(dps)
+        b = mgrhd.Batch(pd, mean_mode=mode, polish=1, **_consts())
+        b.set_tuning(g, 0, chunk)
+        b.set_item_scope(scope)
+        b.run()
+        torch.cuda.synchronize()
+        for w, d in zip(inputs, pd):
+            res = ({k: d[k].cpu().numpy() for k in ("E_g", "F_g", "e_gas", "v")},
+                   d["iters"].cpu().numpy(), d["outer"].cpu().numpy(), d["status"].cpu().numpy())
+            assert (res[3] >= 0).all()
+            U.compare(w, res, U.run_oracle(w, mode),
+                      label=f"random batch {case} ({g},{scope},{chunk}): patch N_g={w.ng} n={w.n}")
+        b.close()
