@@ -34,7 +34,7 @@ enum { ORA_CLOSURE_M1 = 0, ORA_CLOSURE_EDDINGTON = 1 };
 /* per-cell status bits */
 enum {
   ORA_ST_OK = 0,
-  ORA_ST_NEWTON_MAXIT = 1, /* an inner Newton pass hit max_newton            */
+  ORA_ST_NEWTON_MAXIT = 1, /* the cell's Newton steps (all passes) hit max_newton */
   ORA_ST_OUTER_MAXIT = 2,  /* the outer flux/momentum loop hit max_outer     */
   ORA_ST_FALLBACK = 4,     /* warm start failed; plain Newton restarted       */
   ORA_ST_INVALID = 8,      /* invalid input or T <= 0; cell left unchanged    */
@@ -80,10 +80,24 @@ typedef struct {
   int32_t guess_kind;             /* 0: guess holds (E_gas, R_g); 1: only row 0
                                      (E_gas) is read and each R_g solves its own
                                      group balance at that temperature        */
+  int32_t reserved;
+  /* [max_outer][n] out, or NULL: trace[k*n + i] = Newton steps of cell i
+   * counted up to the end of inner pass k (cumulative, as iters), written
+   * when pass k reaches its outer stage; -1 for every pass that did not. */
+  int32_t* trace;
+  /* [max_outer][n] in, or NULL: a schedule in the layout of trace.  Pass k of
+   * cell i then stops its Newton iteration when the cumulative step count
+   * reaches force[k*n + i] (instead of at the stop test; polish steps follow
+   * as usual), and the outer loop stops after pass k when force[(k+1)*n + i]
+   * is negative or k + 1 = max_outer (instead of at the outer test).  This
+   * replays the iteration counts of another implementation, so that two
+   * implementations can be compared value by value where a stop test sits on
+   * its threshold.  Status bits are still those of the stop tests. */
+  const int32_t* force;
 } ora_options;
 
 /* Fill *o with the paper's defaults: eps 1e-11 / 1e-13, M1 closure,
- * max_newton 100, max_outer 10, polish 0, unit constants, c_v = 3/2. */
+ * max_newton 100, max_outer 20, polish 0, unit constants, c_v = 3/2. */
 void ora_default_options(ora_options* o);
 
 /* The full source update for n cells, in place, on host arrays.

@@ -54,7 +54,9 @@ class OraOptions(C.Structure):
                 ("closure", C.c_int32), ("polish", C.c_int32),
                 ("S_g", C.POINTER(C.c_double)), ("guess", C.POINTER(C.c_double)),
                 ("iters", C.POINTER(C.c_int32)), ("outer", C.POINTER(C.c_int32)),
-                ("status", C.POINTER(C.c_int32)), ("guess_kind", C.c_int32)]
+                ("status", C.POINTER(C.c_int32)), ("guess_kind", C.c_int32),
+                ("reserved", C.c_int32), ("trace", C.POINTER(C.c_int32)),
+                ("force", C.POINTER(C.c_int32))]
 
 
 _lib = None
@@ -150,12 +152,16 @@ def arrowhead_solve(c_over_chat, Jg0, Jgg, FG, FR):
 def source_update(state: dict, edges, chi_lo, *, mean_mode=MEAN_PPL_FIXED, alpha_chi=None,
                   chi_hi=None, kappa_scale=None, dt=1.0, c_hat=1.0, c=1.0, a_rad=1.0,
                   h_over_k=1.0, c_v=1.5, eps_newton=1e-11, eps_outer=1e-13,
-                  max_newton=100, max_outer=10, closure=CLOSURE_M1, polish=0, S_g=None,
-                  guess=None, guess_kind=0, t_exp=0.0, t_ref=1.0, stim=0, n_threads=0):
+                  max_newton=100, max_outer=20, closure=CLOSURE_M1, polish=0, S_g=None,
+                  guess=None, guess_kind=0, t_exp=0.0, t_ref=1.0, stim=0, n_threads=0,
+                  trace=None, force=None):
     """Run the oracle on a copy of ``state`` (dict of E_g [N_g,n], F_g [3,N_g,n],
     rho [n], e_gas [n], v [3,n]).  Returns (new_state, iters, outer, status).
     t_exp, t_ref, stim: temperature dependence of the opacity,
-    chi_0 x (T/t_ref)^t_exp [1 - exp(-h nu / k T)]^stim."""
+    chi_0 x (T/t_ref)^t_exp [1 - exp(-h nu / k T)]^stim.
+    trace: an int32 array [max_outer, n] that receives the cumulative Newton
+    steps at the end of every inner pass (-1 for passes not run); force: a
+    schedule in the same layout to replay (see ora_options.force)."""
     E = np.array(state["E_g"], dtype=np.float64, order="C", copy=True)
     F = np.array(state["F_g"], dtype=np.float64, order="C", copy=True)
     rho = np.ascontiguousarray(state["rho"], dtype=np.float64)
@@ -185,6 +191,12 @@ def source_update(state: dict, edges, chi_lo, *, mean_mode=MEAN_PPL_FIXED, alpha
     opt.S_g, opt.guess = _dp(S_g), _dp(guess)
     opt.guess_kind = guess_kind
     opt.iters, opt.outer, opt.status = _ip(iters), _ip(outer), _ip(status)
+    if trace is not None:
+        assert trace.dtype == np.int32 and trace.shape == (max_outer, n) and trace.flags.c_contiguous
+    if force is not None:
+        force = np.ascontiguousarray(force, dtype=np.int32)
+        assert force.shape == (max_outer, n)
+    opt.trace, opt.force = _ip(trace), _ip(force)
     rc = lib().ora_source_update(_dp(E), _dp(F), _dp(rho), _dp(eg), _dp(v), n, _dp(edges),
                                  C.byref(op), float(dt), float(c_hat), C.byref(opt),
                                  int(n_threads))

@@ -36,7 +36,8 @@ void ora_default_options(ora_options* o) {
   o->eps_newton = 1e-11; /* Sec. 3 */
   o->eps_outer = 1e-13;  /* Sec. 3 */
   o->max_newton = 100;   /* READING: the paper gives no cap */
-  o->max_outer = 10;     /* READING: the paper gives no cap */
+  o->max_outer = 20;     /* READING: the paper gives no cap; dynamic diffusion
+                          * (tau v/c >> 1) needs more than a handful */
   o->closure = ORA_CLOSURE_M1;
   o->polish = 0;
 }
@@ -56,7 +57,8 @@ typedef struct {
   double *E_g, *F_g, *e_gas, *v;
   const double *rho, *S, *guess;
   int32_t guess_kind;
-  int32_t *iters, *outer, *status;
+  int32_t *iters, *outer, *status, *trace;
+  const int32_t* force;
 } problem;
 
 typedef struct {
@@ -153,10 +155,12 @@ static void pressure_dot_v(int closure, double c, double E, const double F[3],
     Pv[d] = E * (0.5 * (1.0 - chi) * v[d] + 0.5 * (3.0 * chi - 1.0) * n[d] * nv);
 }
 
-/* One inner stage.  Returns 0 converged, 1 hit max_newton, 2 T <= 0. */
+/* One inner stage.  Returns 0 converged, 1 hit max_newton, 2 T <= 0.
+ * target >= 0: the iteration counts as converged when the cumulative step
+ * count reaches target (a replayed schedule) instead of at the stop test. */
 static int newton(const problem* p, work* w, double rho, double rho_kappa,
                   double egas0, double etot, const double v[3], double* egv,
-                  int32_t* steps, int elim) {
+                  int32_t* steps, int elim, int32_t target) {
   const int32_t ng = p->ng;
   const double cc = p->c / p->chat;
   const double ke = 0.5 * rho * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
@@ -192,6 +196,8 @@ static int newton(const problem* p, work* w, double rho, double rho_kappa,
       sumabs += fabs(w->FR[g]);
     }
     int conv = fabs(FG) / etot < p->eps && cc * sumabs / etot < p->eps;
+    /* a replayed pass ends at its step count, or at the cap as the run did */
+    if (target >= 0) conv = *steps >= target && (conv || *steps < p->max_newton);
     if (polish_left < 0 && conv) polish_left = p->polish;
     if (polish_left == 0) return 0;
     if (polish_left < 0 && *steps >= p->max_newton) return 1;
@@ -265,17 +271,20 @@ static void solve_cell(const problem* p, work* w, int64_t i) {
   memcpy(w->Fk, w->F0, sizeof(double) * 3 * (size_t)ng);
   double egas_new = egas0;
 
+  if (p->trace)
+    for (int32_t k = 0; k < p->max_outer; ++k) p->trace[(int64_t)k * n + i] = -1;
   for (int32_t k = 0;; ++k) {
     ++passes;
+    const int32_t target = p->force ? p->force[(int64_t)k * n + i] : -1;
     for (int32_t g = 0; g < ng; ++g)
       w->vF[g] = v[0] * w->Fk[3 * g] + v[1] * w->Fk[3 * g + 1] + v[2] * w->Fk[3 * g + 2];
     int rc = newton(p, w, rho, rho_kappa, egas0, etot, v, &egv, &steps,
-                    k == 0 && warm && p->guess_kind == 1);
+                    k == 0 && warm && p->guess_kind == 1, target);
     if (k == 0 && warm && rc != 0) {
       st |= ORA_ST_FALLBACK;
       egv = egas0;
       for (int32_t g = 0; g < ng; ++g) w->R[g] = 0.0;
-      rc = newton(p, w, rho, rho_kappa, egas0, etot, v, &egv, &steps, 0);
+      rc = newton(p, w, rho, rho_kappa, egas0, etot, v, &egv, &steps, 0, target);
     }
     if (rc == 1) st |= ORA_ST_NEWTON_MAXIT;
     if (rc == 2) {
@@ -297,6 +306,7 @@ static void solve_cell(const problem* p, work* w, int64_t i) {
       st |= ORA_ST_INVALID;
       goto done;
     }
+    if (p->trace) p->trace[(int64_t)k * n + i] = steps;
     material(p, w, T, rho_kappa, w->Ecur);
     double mom[3] = {rho * v0[0], rho * v0[1], rho * v0[2]};
     for (int32_t g = 0; g < ng; ++g) {
@@ -314,14 +324,15 @@ static void solve_cell(const problem* p, work* w, int64_t i) {
       }
     }
     double vn[3] = {mom[0] / rho, mom[1] / rho, mom[2] / rho};
-    /* change of the velocity/flux terms of eq. Rnew (READING: measured
-     * against E_tot only) */
-    double dW = 0.0;
+    /* change of the velocity/flux terms of eq. Rnew from this pass to the
+     * next, and their size (READING: measured against E_tot only) */
+    double dW = 0.0, sW = 0.0;
     for (int32_t g = 0; g < ng; ++g) {
       double vf_new = vn[0] * w->Fn[3 * g] + vn[1] * w->Fn[3 * g + 1] + vn[2] * w->Fn[3 * g + 2];
       double vf_old = v[0] * w->Fk[3 * g] + v[1] * w->Fk[3 * g + 1] + v[2] * w->Fk[3 * g + 2];
-      dW += fabs(p->chat * p->dt * (1.0 + w->ac[g]) * w->chiF[g] * (vf_new - vf_old)) /
-            (p->c * p->c);
+      double kW = fabs(p->chat * p->dt * (1.0 + w->ac[g]) * w->chiF[g]) / (p->c * p->c);
+      dW += kW * fabs(vf_new - vf_old);
+      sW += kW * fabs(vf_new);
     }
     /* READING: the next inner pass starts from the temperature of this
      * outer stage, i.e. from the conservatively updated E_gas carrying the
@@ -332,9 +343,14 @@ static void solve_cell(const problem* p, work* w, int64_t i) {
     v[1] = vn[1];
     v[2] = vn[2];
     memcpy(w->Fk, w->Fn, sizeof(double) * 3 * (size_t)ng);
-    if (dW < p->eps_out * etot) break;
-    if (k + 1 >= p->max_outer) {
-      st |= ORA_ST_OUTER_MAXIT;
+    /* READING: where the velocity terms are large against E_tot (tau v/c >> 1)
+     * their change cannot be resolved below their own rounding; the test then
+     * accepts a change within 2^-46 (64 roundings) of their size */
+    int done_outer = dW < p->eps_out * etot + 0x1p-46 * sW;
+    if (!done_outer && k + 1 >= p->max_outer) st |= ORA_ST_OUTER_MAXIT;
+    if (p->force) {
+      if (k + 1 >= p->max_outer || p->force[(int64_t)(k + 1) * n + i] < 0) break;
+    } else if (done_outer || k + 1 >= p->max_outer) {
       break;
     }
   }
@@ -470,6 +486,8 @@ int ora_source_update(double* E_g, double* F_g, const double* rho, double* e_gas
   p.iters = opt->iters;
   p.outer = opt->outer;
   p.status = opt->status;
+  p.trace = opt->trace;
+  p.force = opt->force;
   double* tab = (double*)malloc(sizeof(double) * 3 * (size_t)ng);
   if (!tab) return -7;
   p.lnr = tab;

@@ -221,6 +221,114 @@ def test_linear_relaxation_rate(ora):
         assert abs(u1 / u0 - 1 / (1 + lam * dt)) < 1e-4
 
 
+def _boosted_isotropic_moments(beta):
+    """Flux factor f and Eddington factor chi = P_nn/E of an intensity that is
+    isotropic in a frame moving at beta along n (I ~ (1 - beta mu)^-4 in the
+    lab frame), by mpmath quadrature over mu.  This field is what the M1
+    closure of Levermore (1984) reproduces exactly, so it pins the closure
+    without restating its algebraic form."""
+    mp.mp.dps = 30
+    I = lambda mu: (1 - beta * mu) ** -4
+    E = mp.quad(I, [-1, 1])
+    F = mp.quad(lambda mu: I(mu) * mu, [-1, 1])
+    P = mp.quad(lambda mu: I(mu) * mu * mu, [-1, 1])
+    return float(F / E), float(P / E)
+
+
+def _closure_from_flux_update(ora, E0, F0, v, c):
+    """One grey PC group over all frequencies (Delta_g terms vanish), gas at
+    the radiation temperature, tau = c_hat dt chi = 1, one outer pass: eq.
+    numF1 reads F(1 + tau) = F0 + tau (v a T^4 + P.v), so P.v follows from the
+    output exactly (T from the updated E_gas and the outdated velocity).
+    Returns (P.v, E^new)."""
+    T = E0 ** 0.25
+    st = make_state([[E0]], F0, [1.0], [T], v)
+    out, it, ou, stt = ora.source_update(st, [0.0, np.inf], [1.0], mean_mode=0, dt=1.0 / c,
+                                         c_hat=c, c=c, a_rad=1.0, closure=0, max_outer=1,
+                                         polish=1)
+    assert (stt[0] & ~2) == 0          # one outer pass by request
+    Tn = (out["e_gas"][0] - 0.5 * (np.asarray(v) ** 2).sum()) / 1.5
+    Pv = (out["F_g"][:, 0, 0] * 2.0 - np.asarray(F0)) - np.asarray(v) * Tn ** 4
+    return Pv, out["E_g"][0, 0]
+
+
+@pytest.mark.parametrize("beta", [0.0, 0.25, 0.5, 0.75, 0.9, 0.99])
+def test_m1_closure_against_boosted_isotropic_field(ora, beta):
+    """Sec. 2.1 (the per-group M1 closure inside eq. numF1): at every flux
+    factor f the oracle's P.v equals E [(1 - chi)/2 v + (3 chi - 1)/2 n (n.v)]
+    with (f, chi) the moments of a boosted isotropic intensity computed by
+    quadrature; f -> 0 gives P.v = E v/3."""
+    f, chi = _boosted_isotropic_moments(beta)
+    c, E0 = 1.0e3, 1.3
+    rng = np.random.default_rng(int(beta * 100))
+    n = rng.normal(size=3)
+    n /= np.linalg.norm(n)
+    v = 1e-6 * c * rng.normal(size=3)
+    Pv, E = _closure_from_flux_update(ora, E0, f * c * E0 * n, v, c)
+    want = E * ((1 - chi) / 2 * v + (3 * chi - 1) / 2 * n * (n @ v))
+    # f is taken with the updated E (E/E0 - 1 ~ 1e-9 here), hence the bound
+    assert np.abs(Pv - want).max() < 1e-6 * E * np.abs(v).max(), (beta, Pv, want)
+    if beta == 0.0:
+        assert np.abs(Pv - E * v / 3).max() < 1e-9 * E * np.abs(v).max()
+
+
+def test_m1_closure_free_streaming_and_trace(ora):
+    """f >= 1 (clamped to 1): P = E n n, so P.v = E n (n.v): zero for v
+    perpendicular to n, E v for v along n.  At an intermediate f the diagonal
+    elements P.e_d . e_d over three orthogonal directions sum to trace P = E."""
+    c, E0 = 1.0e3, 0.8
+    n = np.array([0.6, 0.0, 0.8])
+    s = 1e-6 * c
+    Pv, E = _closure_from_flux_update(ora, E0, 3.0 * c * E0 * n, s * np.array([0.8, 0.0, -0.6]), c)
+    assert np.abs(Pv).max() < 1e-8 * E * s
+    Pv, E = _closure_from_flux_update(ora, E0, 3.0 * c * E0 * n, s * n, c)
+    assert np.abs(Pv - E * s * n).max() < 1e-8 * E * s
+    F0 = 0.55 * c * E0 * np.array([0.36, 0.48, 0.8])
+    tr = 0.0
+    for d in range(3):
+        e = np.zeros(3)
+        e[d] = s
+        Pv, E = _closure_from_flux_update(ora, E0, F0, e, c)
+        tr += Pv[d] / (s * E)
+    assert abs(tr - 1.0) < 1e-7
+
+
+def _relaxation_time(T0, T, rho_cv, chi_c, a, E_tot):
+    """t(T) of rho c_v dT/dt = -c chi (a T^4 + rho c_v T - E_tot) by mpmath
+    quadrature (constant opacity, gas at rest, no transport)."""
+    mp.mp.dps = 30
+    f = lambda u: -rho_cv / (chi_c * (a * u ** 4 + rho_cv * u - E_tot))
+    return mp.quad(f, [T0, T])
+
+
+def test_nonlinear_thermal_relaxation_first_order(ora):
+    """Constant grey opacity, v = F = 0, hot gas and cold radiation: the oracle
+    stepped with dt reaches, at t = 0.3, the temperature of the exact nonlinear
+    relaxation curve (the ODE solved by quadrature and root finding) with an
+    error that halves when dt halves (backward Euler, first order)."""
+    T0, E0, chi, c, a, rho_cv = 2.0, 0.05, 0.8, 1.0, 1.0, 1.5
+    E_tot = rho_cv * T0 + E0
+    t_end = 0.3
+    mp.mp.dps = 30
+    T_eq = mp.findroot(lambda T: a * T ** 4 + rho_cv * T - E_tot, 1.0)
+    T_exact = float(mp.findroot(lambda T: _relaxation_time(T0, T, rho_cv, chi * c, a, E_tot)
+                                - t_end, (T_eq * (1 + 1e-6), T0), solver="illinois"))
+    assert T_exact - float(T_eq) > 0.1 * (T0 - float(T_eq))      # still far from equilibrium
+    errs = []
+    for steps in (15, 30, 60, 120):
+        st = make_state([[E0]], np.zeros(3), [1.0], [T0], [0, 0, 0])
+        for _ in range(steps):
+            st, it, ou, stt = ora.source_update(st, [0.0, np.inf], [chi], mean_mode=0,
+                                                dt=t_end / steps, c_hat=c, c=c, a_rad=a,
+                                                polish=1)
+            assert stt[0] == 0
+        errs.append(temperature(st)[0] - T_exact)
+    errs = np.array(errs)
+    assert abs(errs[-1]) < 5e-3 * abs(T0 - T_exact)
+    ratios = errs[:-1] / errs[1:]
+    assert np.all(np.abs(ratios - 2.0) < 0.1), (errs, ratios)
+
+
 def test_order_v_over_c_equilibrium_is_stationary(ora):
     """Grey chi, Eddington closure: E = a T^4 (1 + 4 v^2/3c^2), F = (4/3) v a T^4
     (the equilibrium of Sec. 2.1) is stationary to O(v^3)."""
@@ -239,10 +347,12 @@ def test_order_v_over_c_equilibrium_is_stationary(ora):
     assert np.abs(out["v"][:, 0] - v).max() < 10 * beta ** 3 * beta * c
 
 
+@pytest.mark.parametrize("closure", [0, 1])
 @pytest.mark.parametrize("mode", [0, 1])
-def test_diffusion_flux_is_a_fixed_point(ora, mode):
+def test_diffusion_flux_is_a_fixed_point(ora, mode, closure):
     """eq. Fdiff is a fixed point of eq. numF1 with P = E/3 exactly when the
-    flux mean is eq. chiDiff (a wrong flux mean moves it at O(1))."""
+    flux mean is eq. chiDiff (a wrong flux mean moves it at O(1)).  With the
+    M1 closure (closure 0) P = E/3 + O(f^2), and f ~ 1e-8 here."""
     edges = np.array([0.2, 0.5, 1.3, 3.0, 8.0])
     chi_lo = np.array([50.0, 80.0, 20.0, 60.0])
     a_chi = np.array([-2.0, 1.5, -0.5, 1.0])
@@ -254,7 +364,7 @@ def test_diffusion_flux_is_a_fixed_point(ora, mode):
     Fdiff = np.outer(v, 4.0 / 3.0 * B - (nuB[1:] - nuB[:-1]) / 3.0)   # eq. Fdiff
     st = make_state(B[:, None], Fdiff[:, :, None], [1.0], [T], v)
     out, *_ = ora.source_update(st, edges, chi_lo, alpha_chi=a_chi, mean_mode=mode, dt=1.0,
-                                c_hat=c, c=c, a_rad=1.0, closure=1, max_outer=1, polish=1)
+                                c_hat=c, c=c, a_rad=1.0, closure=closure, max_outer=1, polish=1)
     assert np.allclose(out["F_g"][0, :, 0], Fdiff[0], rtol=1e-7)
 
 
