@@ -98,7 +98,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="config1", choices=list(WORKLOADS))
+    ap.add_argument("--workload", default="config2", choices=list(WORKLOADS))
+    ap.add_argument("--no-ng16", action="store_true",
+                    help="default workload only: skip the 128^3 x 16-group figures reported "
+                         "beside it")
     ap.add_argument("--mode", type=int, default=1, help="0 PC, 1 PPL-fixed, 2 PPL-free")
     ap.add_argument("--cells", type=int, default=0, help="override the cell count")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -127,6 +130,22 @@ def main():
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
+    import torch
+
+    if args.workload == "config4":
+        return run_batch(args)
+    if args.workload == "column":
+        return run_column(args)
+    result = run_single(args.workload, args)
+    if args.workload == "config2" and not (args.cells or args.warm or args.no_ng16):
+        torch.cuda.empty_cache()
+        result["n_g16"] = run_single("config1", args, extra=True)
+    print(json.dumps(result), flush=True)
+
+
+def run_single(name, args, extra=False):
+    """Time the single-table source update on workload `name`; returns the
+    result dict (extra: the figures reported beside the main workload)."""
     import numpy as np
     import torch
 
@@ -134,13 +153,8 @@ def main():
     from paper_2407_18304_amd import mgrhd, synth
     from paper_2407_18304_amd import workloads as W
 
-    if args.workload == "config4":
-        return run_batch(args)
-    if args.workload == "column":
-        return run_column(args)
     dev = torch.device("cuda:0")
-    name = args.workload
-    n = args.cells or W.SPECS[name]["n"]
+    n = (0 if extra else args.cells) or W.SPECS[name]["n"]
     dw = synth.device_workload(name, n=n)
     ng = dw.ng
     if args.variant:
@@ -161,7 +175,7 @@ def main():
             st[k].copy_(pristine[k])
 
     ws, winfo = None, None
-    if args.warm:
+    if args.warm and not extra:
         ws, winfo = train_warm(name, args)
 
     def solve(warm=False):
@@ -189,7 +203,8 @@ def main():
         t1 = time.perf_counter()
         return t0, t1, [a.elapsed_time(b) for a, b in ev]
 
-    if args.warm:
+    warm = args.warm and not extra
+    if warm:
         _, _, plain_ms = timed(False)
         plain_it = iters.cpu().numpy().copy()
         plain_st = status.cpu().numpy().copy()
@@ -219,7 +234,7 @@ def main():
                          "flop_per_cell": mlp_flop / n, "dtype": "bf16 products, fp32 accumulation"},
             "hbm": {"achieved": mlp_bytes / inf_s / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
                     "frac": mlp_bytes / inf_s / PEAK_HBM, "bytes_per_cell": mlp_bytes / n}}
-    t0, t1, kern_ms = timed(args.warm)
+    t0, t1, kern_ms = timed(warm)
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = n * args.steps / (t1 - t0)
 
@@ -248,12 +263,18 @@ def main():
     td = "true" if (dw.t_exp != 0.0 or dw.stim) else "false"
     full = "true" if lpc_ * g_ == ng else "false"
     kname = f"k_source_update<{g_}, {lpc_}, {args.mode}, {w_}, {td}, {full}>"
-    traffic = None if (args.warm or args.cells or args.mode != 1) else measured_traffic(name, kname)
-    roof_alu = {"bound": "alu", "achieved": achieved_fl / 1e12, "peak": PEAK_FP64 / 1e12,
-                "unit": "TFLOP/s", "frac": achieved_fl / PEAK_FP64, "traffic": traffic,
-                "flop_per_cell": flop / n, "ceiling_cells_per_s": ceil_alu,
-                "flop_per_cell_div_sqrt_as_1": flop1 / n,
-                "frac_div_sqrt_as_1": flop1 / kern_s / PEAK_FP64}
+    traffic = None if (warm or args.cells or args.mode != 1) else measured_traffic(name, kname)
+    # headline pricing: +, -, x = 1, FMA = 2, division and square root = 1,
+    # exp/expm1/log by their gfx950 instruction counts; beside it, the same
+    # count with divisions and square roots also priced by their instruction
+    # sequences
+    ceil_alu = PEAK_FP64 / (flop1 / n)
+    roof_alu = {"bound": "alu", "achieved": flop1 / kern_s / 1e12, "peak": PEAK_FP64 / 1e12,
+                "unit": "TFLOP/s", "frac": flop1 / kern_s / PEAK_FP64, "traffic": traffic,
+                "flop_per_cell": flop1 / n, "ceiling_cells_per_s": ceil_alu,
+                "pricing": "div and sqrt = 1 FLOP; exp, expm1, log by instruction count",
+                "flop_per_cell_div_sqrt_by_instructions": flop / n,
+                "frac_div_sqrt_by_instructions": achieved_fl / PEAK_FP64}
     roof_hbm = {"bound": "hbm", "achieved": achieved_bw / 1e9, "peak": PEAK_HBM / 1e9,
                 "unit": "GB/s", "frac": achieved_bw / PEAK_HBM, "traffic": traffic,
                 "bytes_per_cell": bpc, "ceiling_cells_per_s": ceil_hbm}
@@ -283,9 +304,17 @@ def main():
         "kernel_ms": {"mean": float(np.mean(kern_ms)), "min": float(np.min(kern_ms))},
         "roofline": roof,
         "roofline_other": other,
-        "hbm_copy_ceiling": copy_bandwidth(),
     }
-    if args.warm:
+    if not extra:
+        result["hbm_copy_ceiling"] = copy_bandwidth()
+    if extra:
+        return {"workload": WORKLOADS[name], "cells": n, "n_groups": ng, "value": value,
+                "ms_per_step": ms_per_step, "config": result["config"],
+                "newton_iters_per_cell": result["newton_iters_per_cell"],
+                "outer_passes_per_cell": result["outer_passes_per_cell"],
+                "status_counts": result["status_counts"], "kernel_ms": result["kernel_ms"],
+                "roofline": roof, "roofline_other": other}
+    if warm:
         ok = (plain_st == 0) & ((stt & ~4) == 0)
         dev_max = 0.0
         for k in ("E_g", "e_gas"):
@@ -308,7 +337,7 @@ def main():
         restore()
         torch.cuda.synchronize()
         result["cpu_baseline"] = cpu_baseline(dw, args.mode, args.cpu_seconds)
-    print(json.dumps(result), flush=True)
+    return result
 
 
 def train_warm(name, args):

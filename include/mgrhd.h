@@ -11,7 +11,10 @@
  *   energy       E_g <- E_g + R_g + S_g, E_gas <- E_gas - (c/c_hat) sum_g R_g;
  *   outer stage  flux update eq. numF1 with the outdated velocity, momentum
  *                update, repeated until the velocity/flux terms of eq. Rnew
- *                change by less than eps_outer E_tot (default 1e-13).
+ *                change by less than eps_outer E_tot (default 1e-13) plus
+ *                2^-46 of their own size (the change cannot be resolved
+ *                below the rounding of the terms where they are large
+ *                against E_tot, tau v/c >> 1), at most max_outer times.
  * Group-mean opacities: piecewise constant (eq. m1e1), piecewise powerlaw
  * with fixed slopes alpha_Q = -1 (eq. equality) or with the slope fit of
  * Appendix A (eqs. sg, minmod); eq. chiQg for chi_0B and chi_0E, eq. chiDiff
@@ -57,7 +60,8 @@ enum { MGRHD_CLOSURE_M1 = 0, MGRHD_CLOSURE_EDDINGTON = 1 };
 /* per-cell status bits (int32 array, optional) */
 enum {
   MGRHD_ST_OK = 0,
-  MGRHD_ST_NEWTON_MAXIT = 1, /* an inner Newton pass reached max_newton          */
+  MGRHD_ST_NEWTON_MAXIT = 1, /* the cell's Newton steps (all passes) reached
+                                max_newton                                       */
   MGRHD_ST_OUTER_MAXIT = 2,  /* the outer flux/momentum loop reached max_outer   */
   MGRHD_ST_FALLBACK = 4,     /* the warm start failed; plain Newton was rerun     */
   MGRHD_ST_INVALID = 8,      /* invalid cell input or T <= 0: cell untouched      */
@@ -114,8 +118,9 @@ typedef struct {
   double c, a_rad, h_over_k, c_v; /* c_v per unit mass (C_v = rho c_v)            */
   double eps_newton;              /* inner stop tolerance, default 1e-11 (Sec. 3)  */
   double eps_outer;               /* outer stop tolerance, default 1e-13 (Sec. 3)  */
-  int32_t max_newton;             /* default 100                                   */
-  int32_t max_outer;              /* default 10                                    */
+  int32_t max_newton;             /* cap on a cell's Newton steps summed over its
+                                     outer passes; default 100                    */
+  int32_t max_outer;              /* default 20                                    */
   int32_t closure;                /* MGRHD_CLOSURE_*                               */
   int32_t polish;                 /* extra Newton steps after convergence, 0..4    */
   const double* S_g;              /* [N_g][n] optional source term (eq. FGFR), or NULL */
@@ -130,10 +135,17 @@ typedef struct {
                                      with F_R,g = 0, eq. FGFR), so the first Newton
                                      step corrects the temperature alone       */
   int32_t reserved;
+  int32_t* trace;                 /* [max_outer][n] out, or NULL: trace[k*n + i] =
+                                     Newton steps of cell i counted up to the end
+                                     of inner pass k (cumulative, as iters),
+                                     written when pass k reaches its outer stage;
+                                     -1 for every pass that did not.  A record of
+                                     where the stop tests ended each pass (a
+                                     checker can replay it)                      */
 } mgrhd_options;
 
 /* Fill *opt with the defaults: c = a_rad = h_over_k = 1, c_v = 3/2,
- * eps_newton = 1e-11, eps_outer = 1e-13, max_newton = 100, max_outer = 10,
+ * eps_newton = 1e-11, eps_outer = 1e-13, max_newton = 100, max_outer = 20,
  * M1 closure, polish = 0, all optional arrays NULL. */
 void mgrhd_default_options(mgrhd_options* opt);
 
@@ -268,6 +280,7 @@ typedef struct {
   int32_t reserved;
   double dt;
   double c_hat;
+  int32_t* trace;             /* [max_outer][n] out or NULL (as mgrhd_options.trace) */
 } mgrhd_patch;
 
 typedef struct mgrhd_batch mgrhd_batch;

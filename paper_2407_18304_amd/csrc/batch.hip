@@ -147,6 +147,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_batch(BatchArgs b) {
         if (a.status) a.status[i] = MGRHD_ST_BAD_TABLE;
         if (a.iters) a.iters[i] = 0;
         if (a.outer) a.outer[i] = 0;
+        if (a.trace)
+          for (int k = 0; k < a.max_outer; ++k) a.trace[(int64_t)k * a.n + i] = -1;
       }
       continue;
     }
@@ -191,6 +193,8 @@ __global__ __launch_bounds__(kBlock, WPE) void k_batch_wg(BatchArgs b) {
         if (a.status) a.status[i] = MGRHD_ST_BAD_TABLE;
         if (a.iters) a.iters[i] = 0;
         if (a.outer) a.outer[i] = 0;
+        if (a.trace)
+          for (int k = 0; k < a.max_outer; ++k) a.trace[(int64_t)k * a.n + i] = -1;
       }
     } else {
       run_item<G, MODE, NGM, true>(a, tab, ls, lane, BlockQueue{&taken, item.c0, item.c1});
@@ -337,6 +341,7 @@ int mgrhd_batch_create(const mgrhd_patch* patches, int32_t n_patches, int32_t me
     a.iters = q.iters;
     a.outer = q.outer;
     a.status = q.status;
+    a.trace = q.trace;
     a.edges = q.group_edges;
     a.chi_lo = q.chi_lo;
     a.alpha = q.alpha_chi;
@@ -590,6 +595,7 @@ int mgrhd_batch_tune(mgrhd_batch* bt, mgrhd_stream_t stream) {
     t.iters = buf.ints + io;
     t.outer = buf.ints + io + m;
     t.status = buf.ints + io + 2 * m;
+    t.trace = nullptr;
     io += 3 * m;
     tmp.n_cells += m;
   }

@@ -32,6 +32,7 @@ struct KArgs {
   int32_t* iters;
   int32_t* outer;
   int32_t* status;
+  int32_t* trace;  // [max_outer][n] cumulative Newton steps per inner pass, or NULL
   const double* edges;
   const double* chi_lo;
   const double* alpha;
@@ -631,6 +632,8 @@ __device__ __forceinline__ void finish_cell(const KArgs& a, int j, CellState<G>&
     if (a.status) a.status[i] = s.st;
     if (a.iters) a.iters[i] = s.steps;
     if (a.outer) a.outer[i] = s.passes;
+    if (a.trace)  // passes whose outer stage did not run (the last one's did if stored)
+      for (int k = store ? s.k_out + 1 : s.k_out; k < a.max_outer; ++k) a.trace[(int64_t)k * n + i] = -1;
   }
   s.phase = P_EMPTY;
 }
@@ -785,6 +788,7 @@ __device__ __forceinline__ bool flux_step(const KArgs& a, const Tables<NGM>& t, 
   const int ng = group_count<G, LPC, FULL>(a);
   const int64_t n = a.n, i = s.i;
   const double cdt = a.cdt;
+  if (a.trace && j == 0) a.trace[(int64_t)s.k_out * n + i] = s.steps;
   double dmom[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int k = 0; k < G; ++k) {
@@ -815,13 +819,17 @@ __device__ __forceinline__ bool flux_step(const KArgs& a, const Tables<NGM>& t, 
     const double v0 = LS::kKeep0 ? ls.v0(d) : a.v[(int64_t)d * n + i];  // v^(t)
     vn[d] = (s.rho * v0 - dmom[d] * ccc) * irho;  // momentum update
   }
+  // change of the velocity terms of eq. Rnew less 2^-46 of their size: the
+  // change cannot be resolved below the terms' own rounding where they are
+  // large against E_tot (tau v/c >> 1)
   double dW = 0.0;
 #pragma unroll
   for (int k = 0; k < G; ++k) {
     const int g = gidx<LPC>(j, k, s.lpc);
     if (g >= ng) continue;
     const double vf_new = vn[0] * ls.F(0, k) + vn[1] * ls.F(1, k) + vn[2] * ls.F(2, k);
-    dW += fabs((1.0 + (TD ? c.ac[k] : t.achi[g])) * c.chiF[k] * (vf_new - s.vF[k]));
+    const double kw = fabs((1.0 + (TD ? c.ac[k] : t.achi[g])) * c.chiF[k]);
+    dW += kw * fma(-0x1p-46, fabs(vf_new), fabs(vf_new - s.vF[k]));
     s.vF[k] = vf_new;
   }
   dW = cell_sum<LPC>(dW, s.lpc) * a.cdt_ic2;

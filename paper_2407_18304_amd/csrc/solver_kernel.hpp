@@ -33,6 +33,8 @@ __global__ __launch_bounds__(kBlock, WPE) void k_source_update(KArgs a) {
       if (a.status) a.status[i] = MGRHD_ST_BAD_TABLE;
       if (a.iters) a.iters[i] = 0;
       if (a.outer) a.outer[i] = 0;
+      if (a.trace)
+        for (int k = 0; k < a.max_outer; ++k) a.trace[(int64_t)k * a.n + i] = -1;
     }
     return;
   }

@@ -145,7 +145,7 @@ void mgrhd_default_options(mgrhd_options* o) {
   o->eps_newton = 1e-11;
   o->eps_outer = 1e-13;
   o->max_newton = 100;
-  o->max_outer = 10;
+  o->max_outer = 20;
   o->closure = MGRHD_CLOSURE_M1;
   o->polish = 0;
 }
@@ -247,6 +247,7 @@ int mgrhd_source_update(double* E_g, double* F_g, const double* rho, double* e_g
   a.iters = opt->iters;
   a.outer = opt->outer;
   a.status = opt->status;
+  a.trace = opt->trace;
   a.edges = group_edges;
   a.chi_lo = op->chi_lo;
   a.alpha = op->alpha_chi;

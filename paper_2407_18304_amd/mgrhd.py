@@ -49,7 +49,7 @@ class Options(C.Structure):
                 ("max_newton", C.c_int32), ("max_outer", C.c_int32), ("closure", C.c_int32),
                 ("polish", C.c_int32), ("S_g", C.c_void_p), ("guess", C.c_void_p),
                 ("iters", C.c_void_p), ("outer", C.c_void_p), ("status", C.c_void_p),
-                ("guess_kind", C.c_int32), ("reserved", C.c_int32)]
+                ("guess_kind", C.c_int32), ("reserved", C.c_int32), ("trace", C.c_void_p)]
 
 
 _lib = None
@@ -189,15 +189,17 @@ def set_variant(n_groups: int, lanes_per_cell: int, groups_per_lane: int,
 def source_update(E_g, F_g, rho, e_gas, v, group_edges, chi_lo, *, dt, c_hat,
                   mean_mode=MEAN_PPL_FIXED, alpha_chi=None, chi_hi=None, kappa_scale=None,
                   c=1.0, a_rad=1.0, h_over_k=1.0, c_v=1.5, eps_newton=1e-11, eps_outer=1e-13,
-                  max_newton=100, max_outer=10, closure=CLOSURE_M1, polish=0, S_g=None,
+                  max_newton=100, max_outer=20, closure=CLOSURE_M1, polish=0, S_g=None,
                   guess=None, guess_kind=0, iters=None, outer=None, status=None, stream=None,
-                  imex_work=None, t_exp=0.0, t_ref=1.0, stim=0):
+                  imex_work=None, t_exp=0.0, t_ref=1.0, stim=0, trace=None):
     """In-place source update of the device state (see include/mgrhd.h).
     guess_kind 0: guess is [N_g+1, n] (E_gas, R_g); 1: guess is [n] (E_gas).
     imex_work: a device tensor of at least imex_workspace_bytes(n, N_g) bytes
     turns the call into one two-stage IMEX step (mgrhd_imex_step).
     t_exp, t_ref, stim: temperature dependence of the opacity,
-    (T/t_ref)^t_exp [1 - exp(-h nu / k T)]^stim."""
+    (T/t_ref)^t_exp [1 - exp(-h nu / k T)]^stim.
+    trace: optional int32 device tensor [max_outer, n] receiving the
+    cumulative Newton steps at the end of every inner pass (-1: not run)."""
     ng, n = E_g.shape
     o = default_options()
     o.c, o.a_rad, o.h_over_k, o.c_v = c, a_rad, h_over_k, c_v
@@ -209,6 +211,7 @@ def source_update(E_g, F_g, rho, e_gas, v, group_edges, chi_lo, *, dt, c_hat,
     o.iters = _ptr(iters, (n,), torch.int32, "iters")
     o.outer = _ptr(outer, (n,), torch.int32, "outer")
     o.status = _ptr(status, (n,), torch.int32, "status")
+    o.trace = _ptr(trace, (max_outer, n), torch.int32, "trace")
     op = OpacityParams(ng, mean_mode, _ptr(chi_lo, (ng,), name="chi_lo"),
                        _ptr(alpha_chi, (ng,), name="alpha_chi"),
                        _ptr(chi_hi, (ng,), name="chi_hi"),
@@ -241,7 +244,7 @@ class Patch(C.Structure):
                 ("outer", C.c_void_p), ("status", C.c_void_p), ("group_edges", C.c_void_p),
                 ("chi_lo", C.c_void_p), ("alpha_chi", C.c_void_p), ("chi_hi", C.c_void_p),
                 ("n_cells", C.c_int64), ("n_groups", C.c_int32), ("reserved", C.c_int32),
-                ("dt", C.c_double), ("c_hat", C.c_double)]
+                ("dt", C.c_double), ("c_hat", C.c_double), ("trace", C.c_void_p)]
 
 
 SYMBOLS += ["mgrhd_batch_set_item_scope", "mgrhd_batch_get_item_scope", "mgrhd_batch_tune"]
@@ -280,7 +283,7 @@ class Batch:
     status) and its dt, c_hat."""
 
     def __init__(self, patches, *, mean_mode=MEAN_PPL_FIXED, c=1.0, a_rad=1.0, h_over_k=1.0,
-                 c_v=1.5, eps_newton=1e-11, eps_outer=1e-13, max_newton=100, max_outer=10,
+                 c_v=1.5, eps_newton=1e-11, eps_outer=1e-13, max_newton=100, max_outer=20,
                  closure=CLOSURE_M1, polish=0, guess_kind=0):
         L = _batch_lib()
         arr = (Patch * len(patches))()
@@ -300,6 +303,7 @@ class Batch:
             q.iters = _ptr(p.get("iters"), (n,), torch.int32, "iters")
             q.outer = _ptr(p.get("outer"), (n,), torch.int32, "outer")
             q.status = _ptr(p.get("status"), (n,), torch.int32, "status")
+            q.trace = _ptr(p.get("trace"), (max_outer, n), torch.int32, "trace")
             q.group_edges = _ptr(p["edges"], (ng + 1,), name="edges")
             q.chi_lo = _ptr(p["chi_lo"], (ng,), name="chi_lo")
             q.alpha_chi = _ptr(p.get("alpha_chi"), (ng,), name="alpha_chi")

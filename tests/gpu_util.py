@@ -11,11 +11,33 @@ from paper_2407_18304_amd import mgrhd
 
 FIELDS = ("E_g", "F_g", "e_gas", "v")
 
-TOL = 1e-10   # relative parity bound on every field
-# Cells where the two sides take a different number of Newton steps or outer
-# passes (a stop test sitting on its threshold, < 1% of cells) differ by the
-# last increment of a converged iteration: bounded by this instead.
-TOL_COUNT_FLIP = 1e-8
+TOL = 1e-10   # relative parity bound on every field of every compared cell
+# Share of compared cells whose iteration schedule (Newton steps per inner
+# pass, number of passes) may differ from the oracle's: a stop test sitting on
+# its threshold, decided by rounding.  Those cells are compared with the oracle
+# replaying the GPU's schedule, at the same bound TOL.
+MAX_SCHEDULE_FLIPS = 0.01
+# Share of cells whose status may differ in the outer-cap bit alone (the outer
+# test passing on the last allowed pass on one side only; same schedule).
+MAX_CAP_FLIPS = 0.002
+UNTOUCHED = 8 | 16 | 32   # invalid input, non-finite result, rejected table
+# Cells that did not converge (status bit 2, the outer-pass cap: <= 0.1% of
+# the benchmark workloads; bit 1, the Newton cap) hold the last iterate of a
+# map that did not contract, which amplifies rounding over the passes
+# (measured up to ~1e-6).  They must agree in status, be finite and conserve
+# energy and momentum (checked by the conservation tests), and are compared
+# to this bound.
+TOL_UNCONVERGED = 1e-4
+
+
+class Result(tuple):
+    """(state, iters, outer, status) of one run, with the per-pass schedule
+    (``trace``, [max_outer, n]) and what is needed to replay the oracle."""
+
+    def __new__(cls, state, iters, outer, status, trace, kind, mode, kw):
+        r = super().__new__(cls, (state, iters, outer, status))
+        r.trace, r.kind, r.mode, r.kw = trace, kind, mode, kw
+        return r
 
 
 def device_tables(w, dev="cuda"):
@@ -23,7 +45,7 @@ def device_tables(w, dev="cuda"):
     return dict(edges=t(w.edges), chi_lo=t(w.chi_lo), alpha=t(w.alpha_chi), kappa=t(w.kappa))
 
 
-def run_gpu(w, mode, *, polish=1, closure=0, max_outer=10, max_newton=100, eps_newton=1e-11,
+def run_gpu(w, mode, *, polish=1, closure=0, max_outer=20, max_newton=100, eps_newton=1e-11,
             guess=None, guess_kind=0, S_g=None, use_chi_hi=False, dev="cuda"):
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
     st = {k: t(w.state[k]) for k in ("E_g", "F_g", "rho", "e_gas", "v")}
@@ -32,7 +54,8 @@ def run_gpu(w, mode, *, polish=1, closure=0, max_outer=10, max_newton=100, eps_n
     iters = torch.zeros(n, dtype=torch.int32, device=dev)
     outer = torch.zeros(n, dtype=torch.int32, device=dev)
     status = torch.full((n,), -1, dtype=torch.int32, device=dev)
-    chi_hi = t(w.chi_lo * (w.edges[1:] / w.edges[:-1]) ** w.alpha_chi) if use_chi_hi else None
+    trace = torch.full((max_outer, n), -7, dtype=torch.int32, device=dev)
+    chi_hi = t(chi_hi_table(w)) if use_chi_hi else None
     mgrhd.source_update(st["E_g"], st["F_g"], st["rho"], st["e_gas"], st["v"], tab["edges"],
                         tab["chi_lo"], mean_mode=mode,
                         alpha_chi=None if use_chi_hi else tab["alpha"], chi_hi=chi_hi,
@@ -41,19 +64,69 @@ def run_gpu(w, mode, *, polish=1, closure=0, max_outer=10, max_newton=100, eps_n
                         max_outer=max_outer, max_newton=max_newton, eps_newton=eps_newton,
                         guess=None if guess is None else t(guess), guess_kind=guess_kind,
                         S_g=None if S_g is None else t(S_g), iters=iters, outer=outer,
-                        status=status, **w.topacity())
+                        status=status, trace=trace, **w.topacity())
     torch.cuda.synchronize()
     out = {k: st[k].cpu().numpy() for k in st}
-    return out, iters.cpu().numpy(), outer.cpu().numpy(), status.cpu().numpy()
+    kw = dict(polish=polish, closure=closure, max_outer=max_outer, max_newton=max_newton,
+              eps_newton=eps_newton, guess=guess, guess_kind=guess_kind, S_g=S_g,
+              use_chi_hi=use_chi_hi)
+    tr = trace.cpu().numpy()
+    assert (tr != -7).all(), "the kernel left trace entries unwritten"
+    return Result(out, iters.cpu().numpy(), outer.cpu().numpy(), status.cpu().numpy(), tr,
+                  "gpu", mode, kw)
 
 
-def run_oracle(w, mode, *, polish=1, closure=0, max_outer=10, max_newton=100, eps_newton=1e-11,
-               guess=None, guess_kind=0, S_g=None):
-    return oracle.source_update(w.state, w.edges, w.chi_lo, alpha_chi=w.alpha_chi,
-                                kappa_scale=w.kappa, mean_mode=mode, polish=polish,
-                                closure=closure, max_outer=max_outer, max_newton=max_newton,
-                                eps_newton=eps_newton, guess=guess, guess_kind=guess_kind,
-                                S_g=S_g, **w.consts(), **w.topacity())
+def chi_hi_table(w):
+    """The opacity at every group's upper edge (the tabulated form, Sec. 2.2.2)."""
+    return w.chi_lo * (w.edges[1:] / w.edges[:-1]) ** w.alpha_chi
+
+
+def run_oracle(w, mode, *, polish=1, closure=0, max_outer=20, max_newton=100, eps_newton=1e-11,
+               guess=None, guess_kind=0, S_g=None, use_chi_hi=False, force=None):
+    trace = np.full((max_outer, w.n), -7, np.int32)
+    r = oracle.source_update(w.state, w.edges, w.chi_lo,
+                             alpha_chi=None if use_chi_hi else w.alpha_chi,
+                             chi_hi=chi_hi_table(w) if use_chi_hi else None,
+                             kappa_scale=w.kappa, mean_mode=mode, polish=polish,
+                             closure=closure, max_outer=max_outer, max_newton=max_newton,
+                             eps_newton=eps_newton, guess=guess, guess_kind=guess_kind,
+                             S_g=S_g, trace=trace, force=force, **w.consts(), **w.topacity())
+    kw = dict(polish=polish, closure=closure, max_outer=max_outer, max_newton=max_newton,
+              eps_newton=eps_newton, guess=guess, guess_kind=guess_kind, S_g=S_g,
+              use_chi_hi=use_chi_hi)
+    return Result(*r, trace, "oracle", mode, kw)
+
+
+def patch_result(d, mode, idx=None, *, polish=1, closure=0, max_outer=20, max_newton=100,
+                 eps_newton=1e-11, guess=None, guess_kind=0):
+    """Result of one patch of a batched run from its dict of device tensors
+    (E_g, F_g, e_gas, v, iters, outer, status, trace), on cells idx or all."""
+    if idx is None:
+        idx = slice(None)
+    else:
+        idx = torch.as_tensor(np.asarray(idx), device=d["E_g"].device)
+    st = {"E_g": d["E_g"][:, idx].cpu().numpy(), "F_g": d["F_g"][:, :, idx].cpu().numpy(),
+          "e_gas": d["e_gas"][idx].cpu().numpy(), "v": d["v"][:, idx].cpu().numpy()}
+    kw = dict(polish=polish, closure=closure, max_outer=max_outer, max_newton=max_newton,
+              eps_newton=eps_newton, guess=guess, guess_kind=guess_kind, S_g=None,
+              use_chi_hi=False)
+    tr = d["trace"][:, idx].cpu().numpy()
+    assert (tr != -7).all(), "the kernel left trace entries unwritten"
+    return Result(st, d["iters"][idx].cpu().numpy(), d["outer"][idx].cpu().numpy(),
+                  d["status"][idx].cpu().numpy(), tr, "gpu", mode, kw)
+
+
+def _cols(a, idx):
+    return None if a is None else np.ascontiguousarray(np.asarray(a)[..., idx])
+
+
+def replay_oracle(w, res, idx):
+    """The oracle on cells idx of w, replaying the schedule of run ``res``
+    (Newton steps per inner pass and number of passes)."""
+    from paper_2407_18304_amd import workloads as W
+    kw = dict(res.kw)
+    kw["guess"], kw["S_g"] = _cols(kw["guess"], idx), _cols(kw["S_g"], idx)
+    return run_oracle(W.subset(w, idx), res.mode, force=res.trace[:, idx], **kw)
 
 
 def field_errors(w, gpu, ora, mask=None):
@@ -84,47 +157,65 @@ def field_errors(w, gpu, ora, mask=None):
     return out
 
 
-def compare(w, gpu, ref, label="", tol=TOL, tol_flip=TOL_COUNT_FLIP):
-    """Parity of a GPU result with a reference result (the oracle, or another
-    GPU entry point) on the same inputs w.  gpu, ref = (state, iters, outer,
-    status).  Cells whose outer iteration does not contract (status bit 2) are
-    checked for validity only: their last iterate, and whether they still
-    stop inside the pass limit, depend on rounding.  All other cells must
-    agree in status; converged cells within tol (same counts) or tol_flip
-    (Newton or outer count differs by a threshold flip)."""
+def _replayed_errors(w, res, idx):
+    """Errors of run ``res`` on cells idx against the oracle replaying its
+    schedule; the replay must reproduce the run's step counts."""
+    from paper_2407_18304_amd import workloads as W
+    o, oi, oo, os_ = replay_oracle(w, res, idx)
+    g, gi, go, gs = res
+    assert np.array_equal(oi, gi[idx]) and np.array_equal(oo, go[idx]), "replay diverged"
+    sub = {k: _cols(g[k], idx) for k in FIELDS}
+    return field_errors(W.subset(w, idx), sub, o)
+
+
+def compare(w, gpu, ref, label="", tol=TOL, max_flips=MAX_SCHEDULE_FLIPS):
+    """Parity of a GPU result with a reference run on the same inputs w (the
+    oracle, or another GPU entry point).  Every cell must agree in status
+    (except the outer-cap bit on at most MAX_CAP_FLIPS of the cells); cells
+    left untouched must equal their inputs; every other cell is compared value
+    by value within tol: directly where both runs followed the same iteration
+    schedule, and otherwise (at most MAX_SCHEDULE_FLIPS of them) each GPU run
+    against the oracle replaying that run's own schedule."""
     g, gi, go, gs = gpu
     o, oi, oo, os_ = ref
-    chaotic = ((gs | os_) & 2) != 0
-    both = (gs == os_) | (chaotic & ((gs & ~2) == 0) & ((os_ & ~2) == 0))
-    assert both.mean() > 0.99, f"{label}: status agreement {both.mean():.4f}"
-    conv = (os_ == 0) & (gs == 0)
-    same = conv & (gi == oi) & (go == oo)
-    flip = conv & ~same
+    n = w.n
+    mism = gs != os_
+    cap_only = mism & ((gs ^ os_) == 2)
+    assert not (mism & ~cap_only).any(), (
+        label, "status differs", np.unique(np.stack([gs[mism], os_[mism]]), axis=1))
+    assert cap_only.sum() <= max(MAX_CAP_FLIPS * n, 1), (label, int(cap_only.sum()))
+    untouched = ((gs | os_) & UNTOUCHED) != 0
+    for k in FIELDS:
+        a, b = g[k].reshape(-1, n)[:, untouched], w.state[k].reshape(-1, n)[:, untouched]
+        assert np.array_equal(a, b), (label, k)
+    capped = ((gs | os_) & 3) != 0
+    for k in FIELDS:
+        assert np.isfinite(g[k].reshape(-1, n)[:, capped & ~untouched]).all(), (label, k)
+    err_cap = field_errors(w, g, o, capped & ~untouched)
+    cmp_ = ~untouched & ~capped
+    same = cmp_ & (gpu.trace == ref.trace).all(0)
+    flip = cmp_ & ~same
     err = field_errors(w, g, o, same)
-    err_flip = field_errors(w, g, o, flip)
-    print(f"{label}: n={w.n} N_g={w.ng} converged {conv.mean():.4f} non-contracting "
-          f"{chaotic.mean():.4f} (gpu {((gs & 2) != 0).mean():.4f} ref {((os_ & 2) != 0).mean():.4f})"
-          f" same counts {same.mean():.4f} errors {err} count-flip cells {flip.sum()} "
-          f"(outer {(conv & (go != oo)).sum()}) {err_flip}")
+    idx = np.nonzero(flip)[0]
+    err_flip = {}
+    if idx.size:
+        # warm-start fallbacks cannot be replayed (a forced schedule never fails)
+        assert ((gs[idx] | os_[idx]) & 4).sum() == 0, (label, "fallback with a different schedule")
+        runs = [gpu] + ([ref] if ref.kind == "gpu" else [])
+        for r in runs:
+            for k, e in _replayed_errors(w, r, idx).items():
+                err_flip[k] = max(err_flip.get(k, 0.0), e)
+    print(f"{label}: n={n} N_g={w.ng} compared {cmp_.sum()} status {np.unique(gs, return_counts=True)}"
+          f" cap flips {cap_only.sum()} same schedule {same.sum()} errors {err} "
+          f"schedule flips {flip.sum()} (outer count {(cmp_ & (go != oo)).sum()}) "
+          f"replayed {err_flip} not converged {capped.sum()} {err_cap}", flush=True)
     for k, e in err.items():
         assert e < tol, (label, k, e)
+    for k, e in err_cap.items():
+        assert e < TOL_UNCONVERGED, (label, "not converged", k, e)
     for k, e in err_flip.items():
-        assert e < tol_flip, (label, k, e)
-    # The outer stop test compares the change of the velocity terms with
-    # 1e-13 E_tot, a few hundred rounding errors: which pass meets it is
-    # decided by rounding in a few percent of the cells, and in up to a tenth
-    # of them with one group spanning the whole spectrum (the results of those
-    # cells still agree within tol_flip, checked above).
-    assert flip.sum() <= max(0.25 * conv.sum(), 1), (label, int(flip.sum()))
-    assert np.abs(gi[conv] - oi[conv]).max(initial=0) <= 2
-    # non-contracting cells: finite
-    for k in FIELDS:
-        assert np.isfinite(g[k].reshape(-1, w.n)[:, chaotic]).all(), (label, k)
-    # invalid / untouched cells are left exactly as they were
-    inv = (os_ & 8) != 0
-    for k in FIELDS:
-        a, b = g[k].reshape(-1, w.n)[:, inv], w.state[k].reshape(-1, w.n)[:, inv]
-        assert np.array_equal(a, b), (label, k)
+        assert e < tol, (label, "replayed", k, e)
+    assert flip.sum() <= max(max_flips * cmp_.sum(), 1), (label, int(flip.sum()))
     return g, gs
 
 
@@ -144,18 +235,24 @@ def full_size_sampled(name, mode, n_sample, seed):
         iters = torch.zeros(n, dtype=torch.int32, device="cuda")
         outer = torch.zeros(n, dtype=torch.int32, device="cuda")
         status = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+        trace = torch.full((20, n), -7, dtype=torch.int32, device="cuda")
         s = dw.state
         mgrhd.source_update(s["E_g"], s["F_g"], s["rho"], s["e_gas"], s["v"],
                             dw.tables["edges"], dw.tables["chi_lo"], mean_mode=mode,
                             alpha_chi=dw.tables["alpha"], kappa_scale=dw.kappa, polish=1,
-                            iters=iters, outer=outer, status=status, **dw.consts(),
-                            **dw.topacity())
+                            iters=iters, outer=outer, status=status, trace=trace,
+                            **dw.consts(), **dw.topacity())
         torch.cuda.synchronize()
         assert bool((status >= 0).all())
         it = torch.as_tensor(idx, device="cuda")
-        gpu = ({"E_g": s["E_g"][:, it].cpu().numpy(), "F_g": s["F_g"][:, :, it].cpu().numpy(),
-                "e_gas": s["e_gas"][it].cpu().numpy(), "v": s["v"][:, it].cpu().numpy()},
-               iters[it].cpu().numpy(), outer[it].cpu().numpy(), status[it].cpu().numpy())
+        kw = dict(polish=1, closure=0, max_outer=20, max_newton=100, eps_newton=1e-11,
+                  guess=None, guess_kind=0, S_g=None, use_chi_hi=False)
+        gpu = Result({"E_g": s["E_g"][:, it].cpu().numpy(),
+                      "F_g": s["F_g"][:, :, it].cpu().numpy(),
+                      "e_gas": s["e_gas"][it].cpu().numpy(), "v": s["v"][:, it].cpu().numpy()},
+                     iters[it].cpu().numpy(), outer[it].cpu().numpy(), status[it].cpu().numpy(),
+                     trace[:, it].cpu().numpy(), "gpu", mode, kw)
+        del trace
     finally:
         for key in cache.get("single", {}):
             mgrhd.set_variant(int(key.split(":")[0]), 0, 0)

@@ -43,7 +43,7 @@ def test_binding_symbols_are_declared():
 def test_defaults_version_and_variants(lib):
     o = mgrhd.default_options()
     assert (o.c, o.a_rad, o.h_over_k, o.c_v) == (1.0, 1.0, 1.0, 1.5)
-    assert (o.eps_newton, o.eps_outer, o.max_newton, o.max_outer) == (1e-11, 1e-13, 100, 10)
+    assert (o.eps_newton, o.eps_outer, o.max_newton, o.max_outer) == (1e-11, 1e-13, 100, 20)
     assert o.polish == 0 and o.guess_kind == 0 and not o.guess and not o.S_g
     assert b"gfx950" in lib.mgrhd_version()
     vs = mgrhd.variants()
