@@ -213,6 +213,23 @@ int mgrhd_imex_step(double* E_g, double* F_g, const double* rho, double* e_gas, 
                     mgrhd_stream_t stream, const mgrhd_options* opt, void* work,
                     size_t work_bytes);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the IMEX
+ * step of mgrhd_imex_step with no workspace argument.  U^(n) is kept in an
+ * array owned by the library, MGRHD_IMEX_SCRATCH_DOUBLES doubles (32 MiB) per
+ * GPU, held from the first call on that GPU until the process ends; the call
+ * allocates nothing.  Limit: mgrhd_imex_workspace_bytes(n_cells, n_groups)
+ * <= 32 MiB (e.g. 123 361 cells at 16 groups, 31 775 at 64), else
+ * MGRHD_E_SIZE with nothing enqueued.  Every call on one GPU shares that
+ * array: calls that overlap on one GPU (other streams or threads) race and
+ * must be serialised by the caller.  Returns as mgrhd_imex_step, or a HIP
+ * error if the array's address cannot be obtained. */
+#define MGRHD_IMEX_SCRATCH_DOUBLES (4 * 1024 * 1024)
+int mgrhd_imex_step_noalloc(double* E_g, double* F_g, const double* rho, double* e_gas,
+                            double* v, int64_t n_cells, const double* group_edges,
+                            const mgrhd_opacity_params* opacity, double dt, double c_hat,
+                            mgrhd_stream_t stream, const mgrhd_options* opt);
+
 /* ---- Explicit stage of the IMEX integrator for a 1D column (Sec. 2.3) ----
  * One launch writes, for every cell i of a 1D column and every group g,
  *   out = a U0 + b U1 + dt_T T(U1)   (E_g, F_g)

@@ -6,11 +6,42 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 
 #include "../../include/mgrhd.h"
 
 namespace mgrhd {
 namespace imex {
+
+// Library-owned copy of U^(n) for mgrhd_imex_step_noalloc: a file-scope
+// device array (one per GPU the library runs on, held until the process
+// ends).  Host code never uses this name as an address: it takes the array's
+// device address per device from hipGetSymbolAddress (scratch_ptr below).
+__device__ __align__(256) double scratch[MGRHD_IMEX_SCRATCH_DOUBLES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch[kMaxDevices];
+
+// Device address of `scratch` on the current device, looked up once per
+// device; NULL if the lookup fails.
+void* scratch_ptr(hipError_t* err) {
+  int dev = 0;
+  *err = hipGetDevice(&dev);
+  if (*err != hipSuccess) return nullptr;
+  if (dev < 0 || dev >= kMaxDevices) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    *err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (*err != hipSuccess) return nullptr;
+    g_scratch[dev] = p;
+  }
+  return g_scratch[dev];
+}
 
 // x <- (x + y) / 2 over four arrays laid end to end in the workspace order
 __global__ void k_midpoint(double* __restrict__ E, double* __restrict__ F,
@@ -46,6 +77,22 @@ extern "C" {
 size_t mgrhd_imex_workspace_bytes(int64_t n_cells, int32_t n_groups) {
   if (n_cells < 0 || n_groups < 1) return 0;
   return sizeof(double) * (size_t)n_cells * (4 * (size_t)n_groups + 4);
+}
+
+int mgrhd_imex_step_noalloc(double* E_g, double* F_g, const double* rho, double* e_gas,
+                            double* v, int64_t n_cells, const double* group_edges,
+                            const mgrhd_opacity_params* opacity, double dt, double c_hat,
+                            mgrhd_stream_t stream, const mgrhd_options* opt) {
+  if (!opacity) return MGRHD_E_NULL;
+  if (n_cells < 0 || opacity->n_groups < 1 || opacity->n_groups > MGRHD_MAX_GROUPS)
+    return MGRHD_E_SIZE;
+  const size_t need = mgrhd_imex_workspace_bytes(n_cells, opacity->n_groups);
+  if (need > sizeof(double) * (size_t)MGRHD_IMEX_SCRATCH_DOUBLES) return MGRHD_E_SIZE;
+  hipError_t err = hipSuccess;
+  void* w = mgrhd::imex::scratch_ptr(&err);
+  if (!w) return err != hipSuccess ? (int)err : MGRHD_E_DEVICE;
+  return mgrhd_imex_step(E_g, F_g, rho, e_gas, v, n_cells, group_edges, opacity, dt, c_hat,
+                         stream, opt, w, sizeof(double) * (size_t)MGRHD_IMEX_SCRATCH_DOUBLES);
 }
 
 int mgrhd_imex_step(double* E_g, double* F_g, const double* rho, double* e_gas, double* v,

@@ -58,7 +58,8 @@ _lib = None
 SYMBOLS = ["mgrhd_source_update", "mgrhd_default_options", "mgrhd_get_variant",
            "mgrhd_recommend_mean_mode",
            "mgrhd_set_variant", "mgrhd_variant_count", "mgrhd_variant_info",
-           "mgrhd_imex_workspace_bytes", "mgrhd_imex_step", "mgrhd_version",
+           "mgrhd_imex_workspace_bytes", "mgrhd_imex_step", "mgrhd_imex_step_noalloc",
+           "mgrhd_version",
            "mgrhd_transport1d_stage"]
 
 
@@ -90,6 +91,8 @@ def lib():
         L.mgrhd_imex_step.restype = C.c_int
         L.mgrhd_imex_step.argtypes = (L.mgrhd_source_update.argtypes +
                                       [C.c_void_p, C.c_size_t])
+        L.mgrhd_imex_step_noalloc.restype = C.c_int
+        L.mgrhd_imex_step_noalloc.argtypes = L.mgrhd_source_update.argtypes
         L.mgrhd_version.restype = C.c_char_p
         L.mgrhd_version.argtypes = []
         _lib = L
@@ -191,11 +194,14 @@ def source_update(E_g, F_g, rho, e_gas, v, group_edges, chi_lo, *, dt, c_hat,
                   c=1.0, a_rad=1.0, h_over_k=1.0, c_v=1.5, eps_newton=1e-11, eps_outer=1e-13,
                   max_newton=100, max_outer=20, closure=CLOSURE_M1, polish=0, S_g=None,
                   guess=None, guess_kind=0, iters=None, outer=None, status=None, stream=None,
-                  imex_work=None, t_exp=0.0, t_ref=1.0, stim=0, trace=None):
+                  imex_work=None, imex_noalloc=False, t_exp=0.0, t_ref=1.0, stim=0,
+                  trace=None):
     """In-place source update of the device state (see include/mgrhd.h).
     guess_kind 0: guess is [N_g+1, n] (E_gas, R_g); 1: guess is [n] (E_gas).
     imex_work: a device tensor of at least imex_workspace_bytes(n, N_g) bytes
-    turns the call into one two-stage IMEX step (mgrhd_imex_step).
+    turns the call into one two-stage IMEX step (mgrhd_imex_step);
+    imex_noalloc=True makes it the IMEX step that keeps U^(n) in the
+    library's own array and allocates nothing (mgrhd_imex_step_noalloc).
     t_exp, t_ref, stim: temperature dependence of the opacity,
     (T/t_ref)^t_exp [1 - exp(-h nu / k T)]^stim.
     trace: optional int32 device tensor [max_outer, n] receiving the
@@ -223,7 +229,11 @@ def source_update(E_g, F_g, rho, e_gas, v, group_edges, chi_lo, *, dt, c_hat,
             _ptr(rho, (n,), name="rho"), _ptr(e_gas, (n,), name="e_gas"),
             _ptr(v, (3, n), name="v"), n, _ptr(group_edges, (ng + 1,), name="group_edges"),
             C.byref(op), float(dt), float(c_hat), stream, C.byref(o))
-    if imex_work is None:
+    if imex_noalloc:
+        if imex_work is not None:
+            raise ValueError("imex_noalloc takes no imex_work")
+        rc = lib().mgrhd_imex_step_noalloc(*args)
+    elif imex_work is None:
         rc = lib().mgrhd_source_update(*args)
     else:
         if not (isinstance(imex_work, torch.Tensor) and imex_work.is_cuda and

@@ -84,6 +84,23 @@ def test_host_argument_errors_need_no_device(lib):
                                None, C.byref(o), None, 0) == mgrhd.E_NULL
 
 
+def test_noalloc_imex_step_limits_checked_on_the_host(lib):
+    """mgrhd_imex_step_noalloc refuses, before touching a device, a state
+    whose U^(n) copy would not fit its 32 MiB array, and a NULL opacity."""
+    o = mgrhd.default_options()
+    fake = C.c_void_p(64)
+    cap = 8 * (4 * 1024 * 1024)
+    for ng in (1, 16, 64, 256):
+        n_max = cap // (8 * (4 * ng + 4))
+        op = mgrhd.OpacityParams(ng, 1, fake, fake, None, None)
+        assert mgrhd.imex_workspace_bytes(n_max, ng) <= cap < mgrhd.imex_workspace_bytes(n_max + 1, ng)
+        rc = lib.mgrhd_imex_step_noalloc(fake, fake, fake, fake, fake, n_max + 1, fake,
+                                         C.byref(op), 1.0, 1.0, None, C.byref(o))
+        assert rc == mgrhd.E_SIZE, ng
+    assert lib.mgrhd_imex_step_noalloc(None, None, None, None, None, 10, None, None, 1.0, 1.0,
+                                       None, C.byref(o)) == mgrhd.E_NULL
+
+
 def test_temperature_dependence_rejected_on_the_host(lib):
     # the temperature parameters are checked before anything touches the
     # device (the pointers below are never dereferenced)
