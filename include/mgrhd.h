@@ -425,10 +425,19 @@ int mgrhd_mlp_infer(mgrhd_mlp* m, const double* E_g, const double* F_g, const do
                     double c_hat, const mgrhd_options* opt, const float* x_mean,
                     const float* x_istd, const float* y_mean, const float* y_std,
                     int32_t guess_kind, double* guess, mgrhd_stream_t stream);
-/* C = op(A) op(B) with the BF16 matrix-core kernel (FP32 in and out) */
+/* C = op(A) op(B) with the network's matrix-core kernel (FP32 in and out):
+ * BF16 operands (fp32 = 0, v_mfma_f32_16x16x32_bf16) or FP32 operands
+ * (fp32 = 1, v_mfma_f32_16x16x4_f32); FP32 accumulation either way. */
 int mgrhd_mlp_gemm(const float* A, int32_t lda, int32_t trans_a, const float* B, int32_t ldb,
                    int32_t trans_b, float* C, int32_t ldc, int64_t M, int32_t N, int32_t K,
-                   mgrhd_stream_t stream);
+                   int32_t fp32, mgrhd_stream_t stream);
+/* Checking path of the training kernels: on = 1 keeps the operands of every
+ * forward and backward product of the handle in FP32 (the FP32 matrix-core
+ * form) instead of rounding them to BF16, so that gradients can be compared
+ * with an FP64 reference at FP32 accuracy; 0 (the default) restores BF16.
+ * The fused inference (mgrhd_mlp_infer) always uses BF16.  MGRHD_E_NULL,
+ * MGRHD_E_OPTION for other values. */
+int mgrhd_mlp_set_fp32_products(mgrhd_mlp* m, int32_t on);
 void mgrhd_mlp_destroy(mgrhd_mlp* m);
 
 /* Library version string. */

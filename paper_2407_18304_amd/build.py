@@ -39,20 +39,33 @@ def hipcc() -> str:
     return "hipcc"
 
 
-def build_lib(name: str, verbose: bool = True) -> str:
-    """Compile the library's sources to objects in parallel, then link."""
+def _headers_mtime() -> float:
+    heads = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".inc"))]
+    heads.append(os.path.join(ROOT, "include", "mgrhd.h"))
+    return max(os.path.getmtime(h) for h in heads)
+
+
+def build_lib(name: str, verbose: bool = True, force: bool = True) -> str:
+    """Compile the library's sources to objects in parallel, then link.
+    force=False recompiles only objects older than their source or any
+    header of the library (a development shortcut)."""
     srcs = [os.path.join(CSRC, s) for s in LIBS[name]]
     out = os.path.join(PKG, name)
     objdir = os.path.join(PKG, "_build")
     os.makedirs(objdir, exist_ok=True)
     procs = []
+    hdr = _headers_mtime()
     for src in srcs:
         obj = os.path.join(objdir, os.path.basename(src) + ".o")
+        if (not force and os.path.exists(obj) and
+                os.path.getmtime(obj) > max(os.path.getmtime(src), hdr)):
+            procs.append((obj, None))
+            continue
         cmd = [hipcc(), *HIPCC_FLAGS, "-c", "-o", obj, src]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((obj, subprocess.Popen(cmd)))
-    failed = [obj for obj, pr in procs if pr.wait() != 0]
+    failed = [obj for obj, pr in procs if pr is not None and pr.wait() != 0]
     if failed:
         raise subprocess.CalledProcessError(1, f"hipcc ({', '.join(failed)})")
     tmp = out + ".tmp"
@@ -65,12 +78,14 @@ def build_lib(name: str, verbose: bool = True) -> str:
     return out
 
 
-def build_all(verbose: bool = True):
-    return [build_lib(n, verbose) for n in LIBS if all(
+def build_all(verbose: bool = True, force: bool = True):
+    return [build_lib(n, verbose, force) for n in LIBS if all(
         os.path.exists(os.path.join(CSRC, s)) for s in LIBS[n])]
 
 
 if __name__ == "__main__":
-    names = sys.argv[1:] or list(LIBS)
+    args = sys.argv[1:]
+    force = "--changed" not in args
+    names = [a for a in args if not a.startswith("--")] or list(LIBS)
     for n in names:
-        build_lib(n)
+        build_lib(n, force=force)

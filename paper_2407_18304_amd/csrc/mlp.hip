@@ -22,6 +22,7 @@
 #include <cstdint>
 #include <cstring>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/mgrhd.h"
@@ -41,14 +42,18 @@ enum Epi : int { EPI_NONE = 0, EPI_BIAS = 1, EPI_BIAS_SILU = 2, EPI_ATOMIC = 3 }
 // C[M x N] = op(A)[M x K] op(B)[K x N] (+ bias[N]) (SiLU, keeping the
 // pre-activation in Z).  op(A) = A (row-major, lda) or A^T (A stored K x M);
 // op(B) = B (row-major K x N, ldb) or B^T (B stored N x K).
-template <bool TA, bool TB, int EPI>
+// F32: operands kept in FP32 and multiplied by v_mfma_f32_16x16x4_f32 (lane l
+// holds A[l%16][l/16] and B[l/16][l%16] of a 4-deep slice; same accumulator
+// layout), the checking path of the network's products.
+template <bool TA, bool TB, int EPI, bool F32 = false>
 __global__ __launch_bounds__(256) void k_gemm(const float* __restrict__ A, int lda,
                                               const float* __restrict__ B, int ldb,
                                               const float* __restrict__ bias, float* __restrict__ C,
                                               int ldc, float* __restrict__ Z, int64_t M, int N,
                                               int K) {
-  __shared__ __attribute__((aligned(16))) __bf16 As[BM][LDK];
-  __shared__ __attribute__((aligned(16))) __bf16 Bs[BN][LDK];
+  using OpT = typename std::conditional<F32, float, __bf16>::type;
+  __shared__ __attribute__((aligned(16))) OpT As[BM][LDK];
+  __shared__ __attribute__((aligned(16))) OpT Bs[BN][LDK];
   const int tid = threadIdx.x;
   const int wave = tid / 64, lane = tid % 64;
   const int64_t m0 = (int64_t)blockIdx.x * BM;
@@ -81,7 +86,7 @@ __global__ __launch_bounds__(256) void k_gemm(const float* __restrict__ A, int l
       const int gk = k0 + kk;
       float x = 0.f;
       if (gm < M && gk < kend) x = TA ? A[(int64_t)gk * lda + gm] : A[gm * lda + gk];
-      As[mm][kk] = (__bf16)x;
+      As[mm][kk] = (OpT)x;
     }
 #pragma unroll
     for (int r = 0; r < (BN * BK) / 256; ++r) {
@@ -97,20 +102,38 @@ __global__ __launch_bounds__(256) void k_gemm(const float* __restrict__ A, int l
       const int gn = n0 + nn, gk = k0 + kk;
       float x = 0.f;
       if (gn < N && gk < kend) x = TB ? B[(int64_t)gn * ldb + gk] : B[(int64_t)gk * ldb + gn];
-      Bs[nn][kk] = (__bf16)x;
+      Bs[nn][kk] = (OpT)x;
     }
     __syncthreads();
-    const int r16 = lane % 16, kq = 8 * (lane / 16);
-    bf16x8 af[2], bfr[2];
+    const int r16 = lane % 16;
+    if constexpr (F32) {
+      const int k4 = lane / 16;
 #pragma unroll
-    for (int a = 0; a < 2; ++a) af[a] = *(const bf16x8*)&As[wm + 16 * a + r16][kq];
+      for (int kk = 0; kk < BK; kk += 4) {
+        float af[2], bfr[2];
 #pragma unroll
-    for (int b = 0; b < 2; ++b) bfr[b] = *(const bf16x8*)&Bs[wn + 16 * b + r16][kq];
+        for (int a = 0; a < 2; ++a) af[a] = As[wm + 16 * a + r16][kk + k4];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) bfr[b] = Bs[wn + 16 * b + r16][kk + k4];
 #pragma unroll
-      for (int b = 0; b < 2; ++b)
-        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[a], bfr[b], acc[a][b], 0, 0, 0);
+      }
+    } else {
+      const int kq = 8 * (lane / 16);
+      bf16x8 af[2], bfr[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) af[a] = *(const bf16x8*)&As[wm + 16 * a + r16][kq];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bfr[b] = *(const bf16x8*)&Bs[wn + 16 * b + r16][kq];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
+    }
     __syncthreads();
   }
   // epilogue: lane holds C[4(l/16)+i][l%16] of each 16x16 tile
@@ -571,6 +594,7 @@ struct mgrhd_mlp {
   int k_pad[kLayers], n_pad[kLayers];
   int64_t wp_off[kLayers], bp_off[kLayers];
   bool dirty = true;
+  bool fp32 = false;  // FP32 operands in the forward and backward products
 };
 
 static inline dim3 grid1(int64_t n) {
@@ -582,10 +606,15 @@ static inline dim3 grid1(int64_t n) {
 
 template <bool TA, bool TB, int EPI>
 static void gemm(hipStream_t s, const float* A, int lda, const float* B, int ldb, const float* bias,
-                 float* C, int ldc, float* Z, int64_t M, int N, int K, int splits = 1) {
+                 float* C, int ldc, float* Z, int64_t M, int N, int K, int splits = 1,
+                 bool f32 = false) {
   dim3 grid((unsigned)((M + BM - 1) / BM), (unsigned)((N + BN - 1) / BN), (unsigned)splits);
-  hipLaunchKernelGGL((k_gemm<TA, TB, EPI>), grid, dim3(256), 0, s, A, lda, B, ldb, bias, C, ldc, Z,
-                     M, N, K);
+  if (f32)
+    hipLaunchKernelGGL((k_gemm<TA, TB, EPI, true>), grid, dim3(256), 0, s, A, lda, B, ldb, bias,
+                       C, ldc, Z, M, N, K);
+  else
+    hipLaunchKernelGGL((k_gemm<TA, TB, EPI, false>), grid, dim3(256), 0, s, A, lda, B, ldb, bias,
+                       C, ldc, Z, M, N, K);
 }
 
 // forward of `rows` rows.  X_fm: features feature-major [n_in x ld_x]; the
@@ -599,16 +628,16 @@ static void forward(mgrhd_mlp* m, hipStream_t s, const float* X_fm, int64_t ld_x
     if (l == 0)
       gemm<true, true, EPI_BIAS_SILU>(s, in, (int)ld_x, W, m->in_dim[l], b, m->H[l],
                                       m->out_dim[l], keep_z ? m->Zs[l] : nullptr, rows,
-                                      m->out_dim[l], m->in_dim[l]);
+                                      m->out_dim[l], m->in_dim[l], 1, m->fp32);
     else
       gemm<false, true, EPI_BIAS_SILU>(s, in, m->in_dim[l], W, m->in_dim[l], b, m->H[l],
                                        m->out_dim[l], keep_z ? m->Zs[l] : nullptr, rows,
-                                       m->out_dim[l], m->in_dim[l]);
+                                       m->out_dim[l], m->in_dim[l], 1, m->fp32);
     in = m->H[l];
   }
   gemm<false, true, EPI_BIAS>(s, in, m->in_dim[3], m->params + m->w_off[3], m->in_dim[3],
                               m->params + m->b_off[3], Y, m->out_dim[3], nullptr, rows,
-                              m->out_dim[3], m->in_dim[3]);
+                              m->out_dim[3], m->in_dim[3], 1, m->fp32);
 }
 
 // backward: gradients of mean((Y - T)^2) with respect to all parameters
@@ -630,17 +659,17 @@ static void backward(mgrhd_mlp* m, hipStream_t s, const float* X_fm, int64_t ld_
     // dW = dOut^T [no x rows] . input [rows x ni]
     if (l == 0)  // input X feature-major: op(B) = (X_fm)^T, stored ni x ld_x
       gemm<true, true, EPI_ATOMIC>(s, dOut, no, X_fm, (int)ld_x, nullptr, dW, ni, nullptr, no,
-                                   ni, (int)rows, splits);
+                                   ni, (int)rows, splits, m->fp32);
     else
       gemm<true, false, EPI_ATOMIC>(s, dOut, no, m->H[l - 1], ni, nullptr, dW, ni, nullptr, no,
-                                    ni, (int)rows, splits);
+                                    ni, (int)rows, splits, m->fp32);
     hipLaunchKernelGGL(k_colsum, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, dOut,
                        rows, no, db);
     if (l == 0) break;
     // dH_{l-1} = dOut [rows x no] . W_l [no x ni]; then through SiLU
     float* dH = m->dA;
     gemm<false, false, EPI_NONE>(s, dOut, no, m->params + m->w_off[l], ni, nullptr, dH, ni,
-                                 nullptr, rows, ni, no);
+                                 nullptr, rows, ni, no, 1, m->fp32);
     float* dZ = (dOut == m->dB) ? m->dA : m->dB;
     if (dZ == dH) dZ = m->dB;
     hipLaunchKernelGGL(k_silu_bwd, grid1(rows * ni), dim3(256), 0, s, dH, m->Zs[l - 1], dZ,
@@ -992,22 +1021,32 @@ int mgrhd_mlp_infer(mgrhd_mlp* m, const double* E_g, const double* F_g, const do
   return e == hipSuccess ? 0 : (int)e;
 }
 
-// plain product C = op(A) op(B) through the BF16 MFMA kernel (exposed for tests)
+int mgrhd_mlp_set_fp32_products(mgrhd_mlp* m, int32_t on) {
+  if (!m) return MGRHD_E_NULL;
+  if (on != 0 && on != 1) return MGRHD_E_OPTION;
+  m->fp32 = on != 0;
+  return 0;
+}
+
+// plain product C = op(A) op(B) through the network's matrix-core kernel
+// (BF16 operands, or FP32 operands with fp32 = 1; exposed for tests)
 int mgrhd_mlp_gemm(const float* A, int32_t lda, int32_t trans_a, const float* B, int32_t ldb,
                    int32_t trans_b, float* C, int32_t ldc, int64_t M, int32_t N, int32_t K,
-                   mgrhd_stream_t stream) {
+                   int32_t fp32, mgrhd_stream_t stream) {
   if (!A || !B || !C) return MGRHD_E_NULL;
   if (M < 0 || N < 0 || K < 0) return MGRHD_E_SIZE;
+  if (fp32 != 0 && fp32 != 1) return MGRHD_E_OPTION;
   if (M == 0 || N == 0) return 0;
   hipStream_t s = (hipStream_t)stream;
+  const bool f = fp32 != 0;
   if (trans_a && trans_b)
-    gemm<true, true, EPI_NONE>(s, A, lda, B, ldb, nullptr, C, ldc, nullptr, M, N, K);
+    gemm<true, true, EPI_NONE>(s, A, lda, B, ldb, nullptr, C, ldc, nullptr, M, N, K, 1, f);
   else if (trans_a)
-    gemm<true, false, EPI_NONE>(s, A, lda, B, ldb, nullptr, C, ldc, nullptr, M, N, K);
+    gemm<true, false, EPI_NONE>(s, A, lda, B, ldb, nullptr, C, ldc, nullptr, M, N, K, 1, f);
   else if (trans_b)
-    gemm<false, true, EPI_NONE>(s, A, lda, B, ldb, nullptr, C, ldc, nullptr, M, N, K);
+    gemm<false, true, EPI_NONE>(s, A, lda, B, ldb, nullptr, C, ldc, nullptr, M, N, K, 1, f);
   else
-    gemm<false, false, EPI_NONE>(s, A, lda, B, ldb, nullptr, C, ldc, nullptr, M, N, K);
+    gemm<false, false, EPI_NONE>(s, A, lda, B, ldb, nullptr, C, ldc, nullptr, M, N, K, 1, f);
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? 0 : (int)e;
 }

@@ -57,7 +57,10 @@ def _lib():
         L.mgrhd_mlp_infer.restype = C.c_int
         L.mgrhd_mlp_infer.argtypes = [vp] + phys + [vp, vp, vp, vp, i32, vp, vp]
         L.mgrhd_mlp_gemm.restype = C.c_int
-        L.mgrhd_mlp_gemm.argtypes = [vp, i32, i32, vp, i32, i32, vp, i32, i64, i32, i32, vp]
+        L.mgrhd_mlp_gemm.argtypes = [vp, i32, i32, vp, i32, i32, vp, i32, i64, i32, i32, i32,
+                                     vp]
+        L.mgrhd_mlp_set_fp32_products.restype = C.c_int
+        L.mgrhd_mlp_set_fp32_products.argtypes = [vp, i32]
         L.mgrhd_mlp_save.restype = C.c_int
         L.mgrhd_mlp_save.argtypes = [vp, C.c_char_p]
         L.mgrhd_mlp_load.restype = C.c_int
@@ -82,14 +85,15 @@ def _check(rc, what):
         raise mgrhd.MgrhdError(rc, what)
 
 
-def gemm(A, B, trans_a=False, trans_b=False):
-    """C = op(A) op(B) on the matrix cores (BF16 inputs, FP32 accumulation)."""
+def gemm(A, B, trans_a=False, trans_b=False, fp32=False):
+    """C = op(A) op(B) on the matrix cores (BF16 inputs, or FP32 inputs with
+    fp32=True; FP32 accumulation)."""
     M, K = (A.shape[1], A.shape[0]) if trans_a else A.shape
     K2, N = (B.shape[1], B.shape[0]) if trans_b else B.shape
     assert K == K2
     Cm = torch.empty((M, N), dtype=torch.float32, device=A.device)
     _check(_lib().mgrhd_mlp_gemm(_f32(A, "A"), A.shape[1], int(trans_a), _f32(B, "B"), B.shape[1],
-                                 int(trans_b), Cm.data_ptr(), N, M, N, K,
+                                 int(trans_b), Cm.data_ptr(), N, M, N, K, int(fp32),
                                  torch.cuda.current_stream().cuda_stream), "mgrhd_mlp_gemm")
     return Cm
 
@@ -131,6 +135,11 @@ class MLP:
             bs.append(flat[o:o + dims[l + 1]])
             o += dims[l + 1]
         return Ws, bs
+
+    def set_fp32_products(self, on=True):
+        """FP32 operands in the forward and backward products (checking path)."""
+        _check(_lib().mgrhd_mlp_set_fp32_products(self._h, int(bool(on))),
+               "mgrhd_mlp_set_fp32_products")
 
     def save_params(self, path):
         """The network's parameters and dimensions to a file (mgrhd_mlp_save)."""

@@ -41,3 +41,34 @@ def test_silu_derivative():
     h = 1e-6
     fd = (mlp_ref.silu(z + h) - mlp_ref.silu(z - h)) / (2 * h)
     assert np.allclose(fd, mlp_ref.dsilu(z), atol=1e-8)
+
+
+def test_bf16_rounding_matches_torch():
+    """The operand rounding equals torch's float32 -> bfloat16 conversion
+    (round to nearest, ties to even), including ties and subnormals."""
+    import torch
+    rng = np.random.default_rng(3)
+    x = np.concatenate([rng.normal(size=4000) * 10.0 ** rng.uniform(-30, 30, 4000),
+                        np.array([1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, -(1.0 + 2 ** -8), 0.0,
+                                  1e-40, -3e-39, 3.3e38])]).astype(np.float32)
+    want = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(mlp_ref.bf16_round(x), want)
+
+
+def test_rounded_reference_reduces_to_exact_and_rounds_operands():
+    """rnd=None is the exact network; with identity rounding the rounded
+    path is the same computation; with BF16 rounding the gradients stay
+    within the operands' relative precision (2^-8) of the exact ones."""
+    rng = np.random.default_rng(1)
+    dims = [10, 16, 16, 16, 5]
+    Ws, bs = _net(rng, dims)
+    X = rng.normal(size=(40, dims[0]))
+    T = rng.normal(size=(40, dims[-1]))
+    l0, dW0, db0 = mlp_ref.loss_and_grads(Ws, bs, X, T)
+    l1, dW1, db1 = mlp_ref.loss_and_grads(Ws, bs, X, T, rnd=lambda a: a)
+    assert l0 == l1 and all(np.array_equal(a, b) for a, b in zip(dW0 + db0, dW1 + db1))
+    l2, dW2, db2 = mlp_ref.loss_and_grads(Ws, bs, X, T, rnd=mlp_ref.bf16_round)
+    assert 0 < abs(l2 - l0) < 2 ** -7 * l0
+    for l in range(4):
+        e = np.linalg.norm(dW2[l] - dW0[l]) / np.linalg.norm(dW0[l])
+        assert 0 < e < 2 ** -6, (l, e)
