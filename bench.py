@@ -103,6 +103,8 @@ def main():
                     help="default workload only: skip the 128^3 x 16-group figures reported "
                          "beside it")
     ap.add_argument("--mode", type=int, default=1, help="0 PC, 1 PPL-fixed, 2 PPL-free")
+    ap.add_argument("--closure", type=int, default=0, help="0 M1, 1 Eddington")
+    ap.add_argument("--polish", type=int, default=1, help="extra Newton steps after convergence")
     ap.add_argument("--cells", type=int, default=0, help="override the cell count")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline sample (0 = skip)")
@@ -182,7 +184,8 @@ def run_single(name, args, extra=False):
         guess = ws.guess(st, tab, dw.kappa, dw.consts()) if warm else None
         mgrhd.source_update(st["E_g"], st["F_g"], st["rho"], st["e_gas"], st["v"], tab["edges"],
                             tab["chi_lo"], alpha_chi=tab["alpha"], kappa_scale=dw.kappa,
-                            mean_mode=args.mode, polish=1, guess=guess, guess_kind=1,
+                            mean_mode=args.mode, polish=args.polish, closure=args.closure,
+                            guess=guess, guess_kind=1,
                             iters=iters, outer=outer, status=status,
                             stream=stream.cuda_stream, **dw.consts(), **dw.topacity())
 
@@ -296,7 +299,8 @@ def run_single(name, args, extra=False):
         "config": {"workload": WORKLOADS[name], "cells": n, "n_groups": ng,
                    "mean_mode": ["PC", "PPL-fixed", "PPL-free"][args.mode],
                    "kernel_variant": "x".join(map(str, mgrhd.get_variant(ng, args.mode))),
-                   "eps_newton": 1e-11, "polish": 1, "closure": "M1"},
+                   "eps_newton": 1e-11, "polish": args.polish,
+                   "closure": ["M1", "Eddington"][args.closure]},
         "newton_iters_per_cell": {"mean": float(it.mean()), "p50": float(np.percentile(it, 50)),
                                   "p99": float(np.percentile(it, 99)), "max": int(it.max())},
         "outer_passes_per_cell": {"mean": float(ou.mean()), "max": int(ou.max())},

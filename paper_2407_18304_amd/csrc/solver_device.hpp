@@ -90,19 +90,38 @@ __device__ __forceinline__ double dpp_swap(double v) {
   return __hiloint2double(hi, lo);
 }
 
+// Exchange of a value between the 16-lane rows r and r^1 (M = 16) or r^2
+// (M = 32) of the wave, same column, by the gfx950 row swaps: with both
+// operands holding v, v_permlane16_swap leaves one of the two results holding
+// the lane's own value and the other its partner's (the even rows of the
+// first operand are swapped with the odd rows of the second; v_permlane32_swap
+// likewise for rows 0-1 and 2-3), so their sum is the pair's sum in every lane.
+template <int M>
+__device__ __forceinline__ double row_swap_sum(double v) {
+  const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
+  if (M == 16) {
+    const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    return __hiloint2double((int)h[0], (int)l[0]) + __hiloint2double((int)h[1], (int)l[1]);
+  }
+  const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  return __hiloint2double((int)h[0], (int)l[0]) + __hiloint2double((int)h[1], (int)l[1]);
+}
+
 // One butterfly level of the group sum: partner lane at distance m.  Levels
 // 1 and 2 pair lanes i and i^m (quad permutations); levels 4 and 8 pair lane
 // i with the mirror image of i in its 8- or 16-lane block, which holds the
 // same partial sum as lane i^m after the lower levels, so every lane adds the
-// same two partial sums as the xor butterfly.  Levels 16 and 32 use the LDS
-// crossbar.
+// same two partial sums as the xor butterfly.  Levels 16 and 32 swap whole
+// rows (no LDS round trip).
 template <int M>
 __device__ __forceinline__ double butterfly(double v) {
   if (M == 1) return v + dpp_swap<0xB1>(v);   // quad_perm [1,0,3,2]
   if (M == 2) return v + dpp_swap<0x4E>(v);   // quad_perm [2,3,0,1]
   if (M == 4) return v + dpp_swap<0x141>(v);  // row_half_mirror
   if (M == 8) return v + dpp_swap<0x140>(v);  // row_mirror
-  return v + __shfl_xor(v, M, kWave);
+  return row_swap_sum<M>(v);
 }
 
 // Sum over the lanes of one cell group (bit-identical in every lane).  LPC = 0:
@@ -132,7 +151,8 @@ __device__ __forceinline__ int gidx(int j, int k, int lpc) {
 // Value held by lane (j - 1) mod lpc, resp. (j + 1) mod lpc, of this lane's
 // cell group.  Every lane of the group must execute it (all are active
 // together).  DPP quad permutations and row rotations where they fit the
-// group, the LDS crossbar otherwise.
+// group, the LDS crossbar otherwise (DPP rotations fixed up at the group's
+// ends measured slower: more scalar registers for the lane masks).
 template <int LPC>
 __device__ __forceinline__ double from_left(double v, int lpc) {
   const int n = LPC > 0 ? LPC : lpc;
@@ -274,11 +294,12 @@ __device__ __forceinline__ void slopes_free(const Tables<NGM>& t, int ng, int j,
 // on lane 0, the high edge of the last lane at the previous slot (kept in
 // `prev`; edge 0 before slot 0).  The wien/inf flags follow from x.
 template <int LPC>
-__device__ __forceinline__ Edge low_edge(const Edge& hi, const Edge& prev, int j, int lpc) {
+__device__ __forceinline__ Edge low_edge(const Edge& hi, const Edge& prev, double x_lo, int j,
+                                         int lpc) {
   const int n = LPC > 0 ? LPC : lpc;
   const bool last = j == n - 1;
   Edge lo;
-  lo.x = from_left<LPC>(last ? prev.x : hi.x, lpc);
+  lo.x = x_lo;  // the same product the neighbour formed for its upper edge
   lo.u = from_left<LPC>(last ? prev.u : hi.u, lpc);
   lo.val = from_left<LPC>(last ? prev.val : hi.val, lpc);
   lo.eps = from_left<LPC>(last ? prev.eps : hi.eps, lpc);
@@ -321,7 +342,7 @@ __device__ __forceinline__ void evaluate(const Tables<NGM>& t, int ng, int j, in
     for (int k = 0; k < G; ++k) {
       const int g = gidx<LPC>(j, k, lpc);
       const Edge hi = planck_edge(hkT * t.nu[min(g + 1, ng)]);
-      const Edge lo = low_edge<LPC>(hi, prev, j, lpc);
+      const Edge lo = low_edge<LPC>(hi, prev, hkT * t.nu[min(g, ng)], j, lpc);
       prev = hi;
       double s_lo = 1.0, s_hi = 1.0;
       if (TD && ot.stim) {
@@ -384,7 +405,7 @@ __device__ __forceinline__ void evaluate(const Tables<NGM>& t, int ng, int j, in
     for (int k = 0; k < G; ++k) {
       const int g = gidx<LPC>(j, k, lpc);
       const Edge hi = planck_edge(hkT * t.nu[min(g + 1, ng)]);
-      const Edge lo = low_edge<LPC>(hi, prev, j, lpc);
+      const Edge lo = low_edge<LPC>(hi, prev, hkT * t.nu[min(g, ng)], j, lpc);
       prev = hi;
       slo[k] = sq[k] = 1.0;
       if (TD && ot.stim) {
