@@ -180,8 +180,13 @@ def run_single(name, args, extra=False):
     if args.warm and not extra:
         ws, winfo = train_warm(name, args)
 
+    exact_guess = None     # E_gas of the plain solution: the best temperature guess
+
     def solve(warm=False):
-        guess = ws.guess(st, tab, dw.kappa, dw.consts()) if warm else None
+        if warm == "exact":
+            guess = exact_guess
+        else:
+            guess = ws.guess(st, tab, dw.kappa, dw.consts()) if warm else None
         mgrhd.source_update(st["E_g"], st["F_g"], st["rho"], st["e_gas"], st["v"], tab["edges"],
                             tab["chi_lo"], alpha_chi=tab["alpha"], kappa_scale=dw.kappa,
                             mean_mode=args.mode, polish=args.polish, closure=args.closure,
@@ -212,6 +217,11 @@ def run_single(name, args, extra=False):
         plain_it = iters.cpu().numpy().copy()
         plain_st = status.cpu().numpy().copy()
         plain_state = {k: st[k].clone() for k in ("E_g", "F_g", "e_gas", "v")}
+        # the ceiling of any temperature guess: the solve started from the
+        # plain solution's own E_gas (guess kind 1), on the same inputs
+        exact_guess = plain_state["e_gas"]
+        _, _, exact_ms = timed("exact")
+        exact_it = iters.cpu().numpy().copy()
         # the fused inference kernel alone, on pristine inputs, against the
         # matrix-core peak: the products it computes (temperature output only)
         restore()
@@ -331,6 +341,12 @@ def run_single(name, args, extra=False):
             "speedup": float(np.mean(plain_ms) / np.mean(kern_ms)),
             "newton_iters_plain": float(plain_it[ok].mean()),
             "newton_iters_warm": float(it[ok].mean()),
+            "ceiling": {
+                "what": "solve started from the plain solution's own E_gas (the exact "
+                        "temperature guess, guess kind 1), no inference",
+                "ms_solve": float(np.mean(exact_ms)),
+                "newton_iters": float(exact_it[ok].mean()),
+                "break_even_inference_ms": float(np.mean(plain_ms) - np.mean(exact_ms))},
             "fallbacks": int(((stt & 4) != 0).sum()),
             "max_rel_diff_vs_plain_E": dev_max,
         })
@@ -516,6 +532,20 @@ def run_batch(args):
         with torch.cuda.graph(gw, stream=stream, capture_error_mode="thread_local"):
             pws.guesses(dps, guesses)
             bw.run(stream.cuda_stream)
+        # the ceiling of any temperature guess: each patch solved from the
+        # plain solution's own E_gas (guess kind 1), no inference
+        exact = [d["e_gas"].clone() for d in pd]
+        bx = mgrhd.Batch([dict(d, guess=g) for d, g in zip(pd, exact)], mean_mode=args.mode,
+                         polish=1, c=u["c"], a_rad=u["a_rad"], guess_kind=1)
+        bx.set_tuning(*b.get_tuning())
+        bx.set_item_scope(b.get_item_scope())
+        with torch.cuda.stream(stream):
+            bx.capture(stream.cuda_stream)
+        torch.cuda.synchronize()
+        exact_ms = timed(lambda: bx.launch(stream.cuda_stream))
+        exact_it = np.concatenate([d["iters"].cpu().numpy() for d in pd])
+        bx.close()
+        del exact
         gi = torch.cuda.CUDAGraph()            # the inference launches alone
         with torch.cuda.graph(gi, stream=stream, capture_error_mode="thread_local"):
             pws.guesses(dps, guesses)
@@ -537,6 +567,12 @@ def run_batch(args):
             "speedup": float(np.mean(plain_ms) / np.mean(kern_ms)),
             "newton_iters_plain": float(plain_it[ok].mean()),
             "newton_iters_warm": float(warm_it[ok].mean()),
+            "ceiling": {
+                "what": "batched solve started from the plain solution's own E_gas in every "
+                        "cell (the exact temperature guess, guess kind 1), no inference",
+                "ms_solve": float(np.mean(exact_ms)),
+                "newton_iters": float(exact_it[ok].mean()),
+                "break_even_inference_ms": float(np.mean(plain_ms) - np.mean(exact_ms))},
             "fallbacks": int(((warm_st & 4) != 0).sum()),
             "max_rel_diff_vs_plain_E_sampled": dmax,
             "sample": f"first {k_s} cells of every patch",
