@@ -21,14 +21,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 WORKLOADS = {
-    "config1": "128^3 cells, 16 groups, PPL-fixed, FP64 (random powerlaw opacity table)",
+    "config1": "128^3 cells, 16 groups, FP64 (random powerlaw opacity table)",
     "config4": "2000 AMR-like patches (sides 8-64, 8-64 groups, own tables), one persistent "
                "launch replayed from a hipGraph, FP64",
-    "config2": "256^3 cells, 64 groups, PPL-fixed, FP64 (T over 3 decades, tau 1e-3..1e6)",
-    "config0": "16^3 cells, 4 groups, PPL-fixed, FP64",
-    "config5": "128^3 cells, 16 groups, PPL-fixed, FP64, temperature-dependent opacity of the "
+    "config2": "256^3 cells, 64 groups, FP64 (T over 3 decades, tau 1e-3..1e6)",
+    "config0": "16^3 cells, 4 groups, FP64",
+    "config5": "128^3 cells, 16 groups, FP64, temperature-dependent opacity of the "
                "pulse test (nu^-3, T^-1/2, stimulated emission) evaluated at every iterate",
-    "column": "1D column of 2^21 cells, 16 groups, PPL-fixed, FP64: two-stage IMEX steps of the "
+    "column": "1D column of 2^21 cells, 16 groups, FP64: two-stage IMEX steps of the "
               "Marshak problem with nu^-2 opacity (explicit M1 transport + implicit source update "
               "per stage), steps replayed from a HIP graph",
 }
@@ -306,7 +306,8 @@ def run_single(name, args, extra=False):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (seeded counter-based generator, drawn in HBM)",
-        "config": {"workload": WORKLOADS[name], "cells": n, "n_groups": ng,
+        "config": {"workload": WORKLOADS[name] + ", " + ["PC", "PPL-fixed", "PPL-free"][args.mode],
+                   "cells": n, "n_groups": ng,
                    "mean_mode": ["PC", "PPL-fixed", "PPL-free"][args.mode],
                    "kernel_variant": "x".join(map(str, mgrhd.get_variant(ng, args.mode))),
                    "eps_newton": 1e-11, "polish": args.polish,
@@ -322,7 +323,8 @@ def run_single(name, args, extra=False):
     if not extra:
         result["hbm_copy_ceiling"] = copy_bandwidth()
     if extra:
-        return {"workload": WORKLOADS[name], "cells": n, "n_groups": ng, "value": value,
+        return {"workload": result["config"]["workload"], "cells": n, "n_groups": ng,
+                "value": value,
                 "ms_per_step": ms_per_step, "config": result["config"],
                 "newton_iters_per_cell": result["newton_iters_per_cell"],
                 "outer_passes_per_cell": result["outer_passes_per_cell"],
