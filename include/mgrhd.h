@@ -425,6 +425,24 @@ int mgrhd_mlp_infer(mgrhd_mlp* m, const double* E_g, const double* F_g, const do
                     double c_hat, const mgrhd_options* opt, const float* x_mean,
                     const float* x_istd, const float* y_mean, const float* y_std,
                     int32_t guess_kind, double* guess, mgrhd_stream_t stream);
+/* Warm start inside a batch (a13 with a14): attach a network to the batch's
+ * patches of n_groups groups.  Every later mgrhd_batch_run / capture /
+ * launch first runs, for each attached group count, one fused inference
+ * launch over all of that count's work items, writing each patch's guess
+ * into its own guess buffer (mgrhd_patch.guess, the layout of the batch's
+ * guess_kind), and then the batched solve, which reads it; the inference
+ * allocates nothing, so both sit in one captured graph.  The network and
+ * statistics (device arrays as for mgrhd_mlp_infer) must outlive the batch's
+ * use of them.  Re-attaching a count replaces its network; a captured graph
+ * is dropped.  MGRHD_E_NULL (a NULL argument, or a patch of that count
+ * without a guess buffer), MGRHD_E_SIZE (no patch of that count, or network
+ * dimensions other than 2 + 3 N_g inputs, 1 + N_g outputs, width 128). */
+int mgrhd_batch_attach_mlp(mgrhd_batch* b, int32_t n_groups, mgrhd_mlp* m,
+                           const float* x_mean, const float* x_istd, const float* y_mean,
+                           const float* y_std);
+/* Enqueue only the attached networks' inference launches (their guesses into
+ * the patches' guess buffers), without the solve. */
+int mgrhd_batch_infer(mgrhd_batch* b, mgrhd_stream_t stream);
 /* C = op(A) op(B) with the network's matrix-core kernel (FP32 in and out):
  * BF16 operands (fp32 = 0, v_mfma_f32_16x16x32_bf16) or FP32 operands
  * (fp32 = 1, v_mfma_f32_16x16x4_f32); FP32 accumulation either way. */

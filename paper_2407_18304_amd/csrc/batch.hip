@@ -21,17 +21,14 @@
 #include <vector>
 
 #include "../../include/mgrhd.h"
+#include "batch_infer.hpp"
 #include "solver_device.hpp"
 
 namespace mgrhd {
 
 constexpr int kBatchNGM = 128;  // group capacity of a wave's LDS table slot
 
-struct Item {
-  int32_t patch;
-  int32_t pad;
-  int64_t c0, c1;
-};
+using Item = BatchItem;
 
 struct BatchArgs {
   const KArgs* patches;  // device array, one KArgs per patch
@@ -247,6 +244,18 @@ struct mgrhd_batch {
   int32_t blocks_per_cu = 0;  // 0 = all resident
   int64_t chunk = 256;
   bool items_dirty = true;
+  // [first, last) item of each group count (the work list is sorted by
+  // decreasing N_g), rebuilt with the work list
+  std::vector<std::pair<int32_t, std::pair<int64_t, int64_t>>> ng_items;
+  // warm-start networks attached per group count (inference enqueued before
+  // the solve)
+  struct Net {
+    int32_t ng;
+    mgrhd_mlp* m;
+    const float *x_mean, *x_istd, *y_mean, *y_std;
+  };
+  std::vector<Net> nets;
+  int32_t guess_kind = 0;
   // graph
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -259,10 +268,15 @@ static int build_items(mgrhd_batch* bt) {
   std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
     return bt->h_patches[x].ng > bt->h_patches[y].ng;
   });
+  bt->ng_items.clear();
   for (int32_t p : order) {
     const int64_t n = bt->h_patches[p].n;
+    const int32_t ng = bt->h_patches[p].ng;
+    if (bt->ng_items.empty() || bt->ng_items.back().first != ng)
+      bt->ng_items.push_back({ng, {(int64_t)items.size(), (int64_t)items.size()}});
     for (int64_t c0 = 0; c0 < n; c0 += bt->chunk)
       items.push_back(Item{p, 0, c0, std::min(n, c0 + bt->chunk)});
+    bt->ng_items.back().second.second = (int64_t)items.size();
   }
   if (bt->d_items) (void)hipFree(bt->d_items);
   bt->d_items = nullptr;
@@ -307,6 +321,7 @@ int mgrhd_batch_create(const mgrhd_patch* patches, int32_t n_patches, int32_t me
   if (!bt) return MGRHD_E_DEVICE;
   bt->n_patches = n_patches;
   bt->mode = mean_mode;
+  bt->guess_kind = opt->guess_kind;
   bt->h_patches.resize(n_patches);
   for (int32_t p = 0; p < n_patches; ++p) {
     const mgrhd_patch& q = patches[p];
@@ -428,9 +443,23 @@ int mgrhd_batch_get_tuning(const mgrhd_batch* bt, int32_t* groups_per_lane,
   return 0;
 }
 
+// the attached networks' inference, one launch per group count
+static int enqueue_infer(mgrhd_batch* bt, hipStream_t stream) {
+  for (const auto& net : bt->nets)
+    for (const auto& r : bt->ng_items)
+      if (r.first == net.ng) {
+        const int rc = mlp_infer_items(net.m, bt->d_patches, bt->d_items, r.second.first,
+                                       r.second.second, net.ng, bt->guess_kind, net.x_mean,
+                                       net.x_istd, net.y_mean, net.y_std, stream);
+        if (rc) return rc;
+      }
+  return 0;
+}
+
 static int enqueue(mgrhd_batch* bt, hipStream_t stream) {
   if (bt->items_dirty) return MGRHD_E_DEVICE;  // the last rebuild of the work list failed
   if (bt->n_items == 0) return 0;
+  if (const int rc = enqueue_infer(bt, stream)) return rc;
   BatchFn fn = batch_fn(bt->groups_per_lane, bt->mode, bt->scope);
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kBlock, 0) != hipSuccess || nb < 1)
@@ -458,6 +487,35 @@ static int enqueue(mgrhd_batch* bt, hipStream_t stream) {
 int mgrhd_batch_run(mgrhd_batch* bt, mgrhd_stream_t stream) {
   if (!bt) return MGRHD_E_NULL;
   return enqueue(bt, (hipStream_t)stream);
+}
+
+int mgrhd_batch_attach_mlp(mgrhd_batch* bt, int32_t n_groups, mgrhd_mlp* m,
+                           const float* x_mean, const float* x_istd, const float* y_mean,
+                           const float* y_std) {
+  if (!bt || !m || !x_mean || !x_istd || !y_mean || !y_std) return MGRHD_E_NULL;
+  if (const int rc = mlp_check_patches(m, n_groups)) return rc;
+  bool any = false;
+  for (const KArgs& a : bt->h_patches)
+    if (a.ng == n_groups) {
+      if (!a.guess) return MGRHD_E_NULL;  // the inference writes the patch's guess buffer
+      any = true;
+    }
+  if (!any) return MGRHD_E_SIZE;
+  for (auto& net : bt->nets)
+    if (net.ng == n_groups) {
+      net = {n_groups, m, x_mean, x_istd, y_mean, y_std};
+      drop_graph(bt);
+      return 0;
+    }
+  bt->nets.push_back({n_groups, m, x_mean, x_istd, y_mean, y_std});
+  drop_graph(bt);
+  return 0;
+}
+
+int mgrhd_batch_infer(mgrhd_batch* bt, mgrhd_stream_t stream) {
+  if (!bt) return MGRHD_E_NULL;
+  if (bt->items_dirty) return MGRHD_E_DEVICE;
+  return enqueue_infer(bt, (hipStream_t)stream);
 }
 
 int mgrhd_batch_capture(mgrhd_batch* bt, mgrhd_stream_t stream) {

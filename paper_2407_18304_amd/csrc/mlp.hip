@@ -26,6 +26,7 @@
 #include <vector>
 
 #include "../../include/mgrhd.h"
+#include "batch_infer.hpp"
 #include "planck_device.hpp"
 
 namespace mgrhd {
@@ -437,114 +438,190 @@ __device__ __forceinline__ void tile_layer(const __bf16* in, int ldi, const __bf
   }
 }
 
-__global__ __launch_bounds__(256) void k_infer(InferArgs q) {
-  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  const PhysArgs& p = q.p;
+// log of each group's PPL-fixed mean opacity per unit rho kappa (a feature
+// of the network), into LDS; the caller synchronises.
+__device__ __forceinline__ void infer_lchi(const PhysArgs& p, float* lchi) {
+  for (int g = threadIdx.x; g < p.ng; g += blockDim.x) {
+    const double L = log(p.edges[g + 1] / p.edges[g]);
+    const double ac = p.alpha ? p.alpha[g] : 0.0;
+    lchi[g] = (float)log(p.chi_lo[g] * mean_ratio(ac, -1.0, L));
+  }
+}
+
+// The fused inference of the cells [i0, min(i0 + kTile, i1)) of one state:
+// features, the three hidden layers and the output on the matrix cores, and
+// the Newton guess written to `guess` (kind 1: [n]; kind 0: [N_g+1][n]).
+// Every thread of the workgroup calls it (it synchronises); smem is the
+// dynamic LDS of k_infer, lchi that state's feature table.
+__device__ __forceinline__ void infer_tile(const InferArgs& q, const PhysArgs& p, double* guess,
+                                           const double* S, const float* lchi, int64_t i0,
+                                           int64_t i1, unsigned char* smem) {
   const int ng = p.ng;
   const int64_t n = p.n;
   const int ldx = q.K_pad[0] + 8;
   __bf16* X = (__bf16*)smem;                                  // [kTile][ldx]; later H_b / out
   __bf16* Ha = X + kTile * (ldx > kHPad ? ldx : kHPad);       // [kTile][kHPad]
-  float* lchi = (float*)(Ha + kTile * kHPad);                  // [ng]
-  for (int g = threadIdx.x; g < ng; g += blockDim.x) {
-    const double L = log(p.edges[g + 1] / p.edges[g]);
-    const double ac = p.alpha ? p.alpha[g] : 0.0;
-    lchi[g] = (float)log(p.chi_lo[g] * mean_ratio(ac, -1.0, L));
-  }
-  __syncthreads();
   const int r = threadIdx.x / 4, qd = threadIdx.x % 4;
-  const int64_t tiles = (n + kTile - 1) / kTile;
-  for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
-    const int64_t i = tile * kTile + r;
-    const bool live = i < n;
-    // ---- features (normalised, bf16) ----
-    {
-      float T = 1.f, rho = 1.f, lcell = 0.f, aT4 = 1.f;
-      if (live) {
-        const double v0 = p.v[i], v1 = p.v[n + i], v2 = p.v[2 * n + i];
-        const double rh = p.rho[i];
-        const double Td = fmax((p.egas[i] - 0.5 * rh * (v0 * v0 + v1 * v1 + v2 * v2)) / (rh * p.cv),
-                               1e-300);
-        const double kap = p.kappa ? p.kappa[i] : 1.0;
-        T = (float)Td;
-        rho = (float)rh;
-        aT4 = (float)(p.a * (Td * Td) * (Td * Td));
-        lcell = (float)log(p.chat * p.dt * rh * kap);
-      }
-      __bf16* xr = X + r * ldx;
-      auto put = [&](int f, float x) { xr[f] = (__bf16)((x - q.xmean[f]) * q.xistd[f]); };
-      if (qd == 0) {
-        put(0, live ? __logf(T) : 0.f);
-        put(1, live ? __logf(rho) : 0.f);
-      }
-      // four groups per chunk: their 16 loads are in flight together
-      constexpr int kU = 4;
-      for (int g0 = qd; g0 < ng; g0 += 4 * kU) {
-        double E[kU], f0[kU], f1[kU], f2[kU];
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-          const int g = g0 + 4 * u;
-          E[u] = f0[u] = f1[u] = f2[u] = 0.0;
-          if (live && g < ng) {
-            E[u] = p.E[(int64_t)g * n + i];
-            f0[u] = p.F[((int64_t)0 * ng + g) * n + i];
-            f1[u] = p.F[((int64_t)1 * ng + g) * n + i];
-            f2[u] = p.F[((int64_t)2 * ng + g) * n + i];
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-          const int g = g0 + 4 * u;
-          if (g >= ng) break;
-          float le = -50.f, fr = 0.f;
-          if (E[u] > 0.0) {
-            le = fminf(fmaxf(__logf((float)(E[u] / (double)aT4)), -50.f), 50.f);
-            fr = fminf((float)(sqrt(f0[u] * f0[u] + f1[u] * f1[u] + f2[u] * f2[u]) /
-                               (p.c * E[u])), 2.f);
-          }
-          put(2 + g, le);
-          put(2 + ng + g, fr);
-          put(2 + 2 * ng + g, lcell + lchi[g]);
-        }
-      }
-      for (int f = q.n_in + qd; f < q.K_pad[0]; f += 4) xr[f] = (__bf16)0.f;
-    }
-    __syncthreads();
-    // ---- layers: X -> Ha -> Hb (in X's space) -> Ha -> out (fp32 in X's space) ----
-    __bf16* Hb = X;
-    tile_layer<true>(X, ldx, q.W[0], q.b[0], q.K_pad[0], q.N_pad[0] / 16, Ha, nullptr, 0);
-    __syncthreads();
-    tile_layer<true>(Ha, kHPad, q.W[1], q.b[1], q.K_pad[1], q.N_pad[1] / 16, Hb, nullptr, 0);
-    __syncthreads();
-    tile_layer<true>(Hb, kHPad, q.W[2], q.b[2], q.K_pad[2], q.N_pad[2] / 16, Ha, nullptr, 0);
-    __syncthreads();
-    float* out = (float*)X;
-    const int ldo = q.N_pad[3];
-    const int out_tiles = q.kind == 1 ? 1 : q.N_pad[3] / 16;
-    tile_layer<false>(Ha, kHPad, q.W[3], q.b[3], q.K_pad[3], out_tiles, nullptr, out, ldo);
-    __syncthreads();
-    // ---- Newton guess ----
+  const int64_t i = i0 + r;
+  const bool live = i < i1;
+  // ---- features (normalised, bf16) ----
+  {
+    float T = 1.f, rho = 1.f, lcell = 0.f, aT4 = 1.f;
     if (live) {
       const double v0 = p.v[i], v1 = p.v[n + i], v2 = p.v[2 * n + i];
       const double rh = p.rho[i];
-      const double ke = 0.5 * rh * (v0 * v0 + v1 * v1 + v2 * v2);
-      const double Tc = fmax((p.egas[i] - ke) / (rh * p.cv), 1e-300);
-      const float* o = out + r * ldo;
-      if (qd == 0) {
-        const double yT = (double)o[0] * q.ystd[0] + q.ymean[0];
-        q.guess[i] = rh * p.cv * Tc * exp(fmin(fmax(yT, -5.0), 5.0)) + ke;
-      }
-      if (q.kind == 0) {
-        const double aT4 = p.a * (Tc * Tc) * (Tc * Tc);
-        for (int g = qd; g < ng; g += 4) {
-          const double yE = (double)o[1 + g] * q.ystd[1 + g] + q.ymean[1 + g];
-          const double sg = q.S ? q.S[(int64_t)g * n + i] : 0.0;
-          q.guess[(int64_t)(g + 1) * n + i] =
-              aT4 * exp(fmin(fmax(yE, -60.0), 60.0)) - p.E[(int64_t)g * n + i] - sg;
+      const double Td = fmax((p.egas[i] - 0.5 * rh * (v0 * v0 + v1 * v1 + v2 * v2)) / (rh * p.cv),
+                             1e-300);
+      const double kap = p.kappa ? p.kappa[i] : 1.0;
+      T = (float)Td;
+      rho = (float)rh;
+      aT4 = (float)(p.a * (Td * Td) * (Td * Td));
+      lcell = (float)log(p.chat * p.dt * rh * kap);
+    }
+    __bf16* xr = X + r * ldx;
+    auto put = [&](int f, float x) { xr[f] = (__bf16)((x - q.xmean[f]) * q.xistd[f]); };
+    if (qd == 0) {
+      put(0, live ? __logf(T) : 0.f);
+      put(1, live ? __logf(rho) : 0.f);
+    }
+    // four groups per chunk: their 16 loads are in flight together
+    constexpr int kU = 4;
+    for (int g0 = qd; g0 < ng; g0 += 4 * kU) {
+      double E[kU], f0[kU], f1[kU], f2[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int g = g0 + 4 * u;
+        E[u] = f0[u] = f1[u] = f2[u] = 0.0;
+        if (live && g < ng) {
+          E[u] = p.E[(int64_t)g * n + i];
+          f0[u] = p.F[((int64_t)0 * ng + g) * n + i];
+          f1[u] = p.F[((int64_t)1 * ng + g) * n + i];
+          f2[u] = p.F[((int64_t)2 * ng + g) * n + i];
         }
       }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int g = g0 + 4 * u;
+        if (g >= ng) break;
+        float le = -50.f, fr = 0.f;
+        if (E[u] > 0.0) {
+          le = fminf(fmaxf(__logf((float)(E[u] / (double)aT4)), -50.f), 50.f);
+          fr = fminf((float)(sqrt(f0[u] * f0[u] + f1[u] * f1[u] + f2[u] * f2[u]) /
+                             (p.c * E[u])), 2.f);
+        }
+        put(2 + g, le);
+        put(2 + ng + g, fr);
+        put(2 + 2 * ng + g, lcell + lchi[g]);
+      }
     }
-    __syncthreads();
+    for (int f = q.n_in + qd; f < q.K_pad[0]; f += 4) xr[f] = (__bf16)0.f;
+  }
+  __syncthreads();
+  // ---- layers: X -> Ha -> Hb (in X's space) -> Ha -> out (fp32 in X's space) ----
+  __bf16* Hb = X;
+  tile_layer<true>(X, ldx, q.W[0], q.b[0], q.K_pad[0], q.N_pad[0] / 16, Ha, nullptr, 0);
+  __syncthreads();
+  tile_layer<true>(Ha, kHPad, q.W[1], q.b[1], q.K_pad[1], q.N_pad[1] / 16, Hb, nullptr, 0);
+  __syncthreads();
+  tile_layer<true>(Hb, kHPad, q.W[2], q.b[2], q.K_pad[2], q.N_pad[2] / 16, Ha, nullptr, 0);
+  __syncthreads();
+  float* out = (float*)X;
+  const int ldo = q.N_pad[3];
+  const int out_tiles = q.kind == 1 ? 1 : q.N_pad[3] / 16;
+  tile_layer<false>(Ha, kHPad, q.W[3], q.b[3], q.K_pad[3], out_tiles, nullptr, out, ldo);
+  __syncthreads();
+  // ---- Newton guess ----
+  if (live) {
+    const double v0 = p.v[i], v1 = p.v[n + i], v2 = p.v[2 * n + i];
+    const double rh = p.rho[i];
+    const double ke = 0.5 * rh * (v0 * v0 + v1 * v1 + v2 * v2);
+    const double Tc = fmax((p.egas[i] - ke) / (rh * p.cv), 1e-300);
+    const float* o = out + r * ldo;
+    if (qd == 0) {
+      const double yT = (double)o[0] * q.ystd[0] + q.ymean[0];
+      guess[i] = rh * p.cv * Tc * exp(fmin(fmax(yT, -5.0), 5.0)) + ke;
+    }
+    if (q.kind == 0) {
+      const double aT4 = p.a * (Tc * Tc) * (Tc * Tc);
+      for (int g = qd; g < ng; g += 4) {
+        const double yE = (double)o[1 + g] * q.ystd[1 + g] + q.ymean[1 + g];
+        const double sg = S ? S[(int64_t)g * n + i] : 0.0;
+        guess[(int64_t)(g + 1) * n + i] =
+            aT4 * exp(fmin(fmax(yE, -60.0), 60.0)) - p.E[(int64_t)g * n + i] - sg;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// LDS of the fused inference: the input tile (or a hidden tile), a hidden
+// tile, and the feature table of N_g floats.
+__host__ __device__ inline size_t infer_lds_bytes(int k_pad0, int ng) {
+  const int ldx = k_pad0 + 8;
+  return sizeof(__bf16) * (size_t)kTile * ((ldx > kHPad ? ldx : kHPad) + kHPad) +
+         sizeof(float) * (size_t)ng;
+}
+
+__global__ __launch_bounds__(256) void k_infer(InferArgs q) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const PhysArgs& p = q.p;
+  const int ldx = q.K_pad[0] + 8;
+  float* lchi = (float*)(smem + sizeof(__bf16) * (size_t)kTile *
+                                    ((ldx > kHPad ? ldx : kHPad) + kHPad));
+  infer_lchi(p, lchi);
+  __syncthreads();
+  const int64_t tiles = (p.n + kTile - 1) / kTile;
+  for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x)
+    infer_tile(q, p, q.guess, q.S, lchi, tile * kTile, p.n, smem);
+}
+
+// The fused inference over the work items [lo, hi) of a batch of patches
+// (one group count): each workgroup takes items in turn, rebuilds the
+// feature table when the patch changes, and infers the item's cells tile by
+// tile into that patch's guess buffer.
+struct InferItemsArgs {
+  InferArgs q;          // weights, statistics, kind (q.p, q.guess, q.S unused)
+  const KArgs* patches;
+  const BatchItem* items;
+  int64_t lo, hi;
+};
+
+__global__ __launch_bounds__(256) void k_infer_items(InferItemsArgs a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int ldx = a.q.K_pad[0] + 8;
+  float* lchi = (float*)(smem + sizeof(__bf16) * (size_t)kTile *
+                                    ((ldx > kHPad ? ldx : kHPad) + kHPad));
+  int cur = -1;
+  for (int64_t it = a.lo + blockIdx.x; it < a.hi; it += gridDim.x) {
+    const BatchItem item = a.items[it];
+    const KArgs& k = a.patches[item.patch];
+    PhysArgs p;
+    p.E = k.E;
+    p.F = k.F;
+    p.rho = k.rho;
+    p.egas = k.egas;
+    p.v = k.v;
+    p.kappa = k.kappa;
+    p.edges = k.edges;
+    p.chi_lo = k.chi_lo;
+    p.alpha = k.alpha;
+    p.n = k.n;
+    p.ng = k.ng;
+    p.pad = 0;
+    p.dt = k.dt;
+    p.chat = k.chat;
+    p.c = k.c;
+    p.a = k.a;
+    p.cv = k.cv;
+    if (item.patch != cur) {  // uniform over the workgroup
+      __syncthreads();        // the previous patch's table is no longer read
+      infer_lchi(p, lchi);
+      __syncthreads();
+      cur = item.patch;
+    }
+    double* guess = const_cast<double*>(k.guess);  // the batch's guess buffer
+    for (int64_t i0 = item.c0; i0 < item.c1; i0 += kTile)
+      infer_tile(a.q, p, guess, k.S, lchi, i0, item.c1, smem);
   }
 }
 
@@ -905,6 +982,93 @@ static int phys_args(PhysArgs& p, const double* E, const double* F, const double
   return 0;
 }
 
+// Pack the weights for the fused path if they changed, and fill the
+// weight, statistic and kind fields of q.  The inference kernels' dynamic LDS
+// limit is raised once per process.
+static int prepare_infer(mgrhd_mlp* m, hipStream_t s, const float* x_mean, const float* x_istd,
+                         const float* y_mean, const float* y_std, int32_t kind, InferArgs& q) {
+  static std::once_flag once;
+  static bool lds_ok = false;
+  std::call_once(once, [] {
+    lds_ok = hipFuncSetAttribute((const void*)k_infer, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 96 * 1024) == hipSuccess &&
+             hipFuncSetAttribute((const void*)k_infer_items,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 96 * 1024) == hipSuccess;
+  });
+  if (!lds_ok) return MGRHD_E_DEVICE;
+  if (m->dirty) {
+    for (int l = 0; l < 4; ++l)
+      hipLaunchKernelGGL(k_pack, grid1((int64_t)m->n_pad[l] * m->k_pad[l]), dim3(256), 0, s,
+                         m->params + m->w_off[l], m->params + m->b_off[l], m->out_dim[l],
+                         m->in_dim[l], m->n_pad[l], m->k_pad[l], m->wpack + m->wp_off[l],
+                         m->bpack + m->bp_off[l]);
+    m->dirty = false;
+  }
+  std::memset(&q, 0, sizeof(q));
+  q.xmean = x_mean;
+  q.xistd = x_istd;
+  q.ymean = y_mean;
+  q.ystd = y_std;
+  for (int l = 0; l < 4; ++l) {
+    q.W[l] = m->wpack + m->wp_off[l];
+    q.b[l] = m->bpack + m->bp_off[l];
+    q.K_pad[l] = m->k_pad[l];
+    q.N_pad[l] = m->n_pad[l];
+  }
+  q.n_in = m->n_in;
+  q.n_out = m->n_out;
+  q.kind = kind;
+  return 0;
+}
+
+static int num_cus() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus < 1)
+    cus = 256;
+  return cus;
+}
+
+}  // extern "C"
+
+namespace mgrhd {
+
+int mlp_check_patches(const mgrhd_mlp* m, int32_t n_groups) {
+  if (!m) return MGRHD_E_NULL;
+  if (m->n_hidden != kHidden || m->n_in != 2 + 3 * n_groups || m->n_out != 1 + n_groups ||
+      m->k_pad[0] > kMaxKin)
+    return MGRHD_E_SIZE;
+  return 0;
+}
+
+int mlp_infer_items(mgrhd_mlp* m, const KArgs* d_patches, const BatchItem* d_items, int64_t lo,
+                    int64_t hi, int32_t n_groups, int32_t kind, const float* x_mean,
+                    const float* x_istd, const float* y_mean, const float* y_std, hipStream_t s) {
+  int rc = mlp_check_patches(m, n_groups);
+  if (rc) return rc;
+  if (!x_mean || !x_istd || !y_mean || !y_std) return MGRHD_E_NULL;
+  if (kind < 0 || kind > 1) return MGRHD_E_OPTION;
+  if (hi <= lo) return 0;
+  InferItemsArgs a;
+  if ((rc = prepare_infer(m, s, x_mean, x_istd, y_mean, y_std, kind, a.q)) != 0) return rc;
+  a.patches = d_patches;
+  a.items = d_items;
+  a.lo = lo;
+  a.hi = hi;
+  const int64_t cap = (int64_t)num_cus() * 4;
+  const int64_t blocks = (hi - lo) < cap ? (hi - lo) : cap;
+  hipLaunchKernelGGL(k_infer_items, dim3((unsigned)blocks), dim3(256),
+                     infer_lds_bytes(m->k_pad[0], n_groups), s, a);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : (int)e;
+}
+
+}  // namespace mgrhd
+
+extern "C" {
+
 int mgrhd_mlp_features(const double* E_g, const double* F_g, const double* rho, const double* e_gas,
                        const double* v, int64_t n, const double* group_edges,
                        const mgrhd_opacity_params* op, double dt, double c_hat,
@@ -967,56 +1131,19 @@ int mgrhd_mlp_infer(mgrhd_mlp* m, const double* E_g, const double* F_g, const do
   if (rc) return rc;
   if (!x_mean || !x_istd || !y_mean || !y_std || !guess) return MGRHD_E_NULL;
   if (guess_kind < 0 || guess_kind > 1) return MGRHD_E_OPTION;
-  if (m->n_hidden != kHidden || m->n_in != 2 + 3 * p.ng || m->n_out != 1 + p.ng ||
-      m->k_pad[0] > kMaxKin)
-    return MGRHD_E_SIZE;
+  if ((rc = mgrhd::mlp_check_patches(m, p.ng)) != 0) return rc;
   if (n == 0) return 0;
   hipStream_t s = (hipStream_t)stream;
-  if (m->dirty) {
-    for (int l = 0; l < 4; ++l)
-      hipLaunchKernelGGL(k_pack, grid1((int64_t)m->n_pad[l] * m->k_pad[l]), dim3(256), 0, s,
-                         m->params + m->w_off[l], m->params + m->b_off[l], m->out_dim[l],
-                         m->in_dim[l], m->n_pad[l], m->k_pad[l], m->wpack + m->wp_off[l],
-                         m->bpack + m->bp_off[l]);
-    m->dirty = false;
-  }
   InferArgs q;
+  if ((rc = prepare_infer(m, s, x_mean, x_istd, y_mean, y_std, guess_kind, q)) != 0) return rc;
   q.p = p;
-  q.xmean = x_mean;
-  q.xistd = x_istd;
-  q.ymean = y_mean;
-  q.ystd = y_std;
-  for (int l = 0; l < 4; ++l) {
-    q.W[l] = m->wpack + m->wp_off[l];
-    q.b[l] = m->bpack + m->bp_off[l];
-    q.K_pad[l] = m->k_pad[l];
-    q.N_pad[l] = m->n_pad[l];
-  }
-  q.n_in = m->n_in;
-  q.n_out = m->n_out;
-  q.kind = guess_kind;
   q.S = opt ? opt->S_g : nullptr;
   q.guess = guess;
-  const int ldx = m->k_pad[0] + 8;
-  const size_t lds = sizeof(__bf16) * (size_t)kTile * ((ldx > kHPad ? ldx : kHPad) + kHPad) +
-                     sizeof(float) * (size_t)p.ng;
-  // once per process: the input tile of the widest networks needs more than
-  // the default 64 KB of dynamic LDS
-  static std::once_flag once;
-  static bool lds_ok = false;
-  std::call_once(once, [] {
-    lds_ok = hipFuncSetAttribute((const void*)k_infer, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 96 * 1024) == hipSuccess;
-  });
-  if (!lds_ok) return MGRHD_E_DEVICE;
-  int dev = 0, cus = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      cus < 1)
-    cus = 256;
   const int64_t tiles = (n + kTile - 1) / kTile;
-  const int64_t blocks = tiles < (int64_t)cus * 4 ? tiles : (int64_t)cus * 4;
-  hipLaunchKernelGGL(k_infer, dim3((unsigned)blocks), dim3(256), lds, s, q);
+  const int64_t cap = (int64_t)num_cus() * 4;
+  const int64_t blocks = tiles < cap ? tiles : cap;
+  hipLaunchKernelGGL(k_infer, dim3((unsigned)blocks), dim3(256),
+                     infer_lds_bytes(m->k_pad[0], p.ng), s, q);
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? 0 : (int)e;
 }

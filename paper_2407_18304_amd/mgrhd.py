@@ -257,7 +257,8 @@ class Patch(C.Structure):
                 ("dt", C.c_double), ("c_hat", C.c_double), ("trace", C.c_void_p)]
 
 
-SYMBOLS += ["mgrhd_batch_set_item_scope", "mgrhd_batch_get_item_scope", "mgrhd_batch_tune"]
+SYMBOLS += ["mgrhd_batch_set_item_scope", "mgrhd_batch_get_item_scope", "mgrhd_batch_tune",
+            "mgrhd_batch_attach_mlp", "mgrhd_batch_infer"]
 SYMBOLS += ["mgrhd_batch_create", "mgrhd_batch_set_tuning", "mgrhd_batch_get_tuning",
             "mgrhd_batch_run", "mgrhd_batch_capture", "mgrhd_batch_launch", "mgrhd_batch_cells",
             "mgrhd_batch_destroy"]
@@ -277,6 +278,10 @@ def _batch_lib():
         for f in ("mgrhd_batch_run", "mgrhd_batch_capture", "mgrhd_batch_launch"):
             getattr(L, f).restype = C.c_int
             getattr(L, f).argtypes = [C.c_void_p, C.c_void_p]
+        L.mgrhd_batch_attach_mlp.restype = C.c_int
+        L.mgrhd_batch_attach_mlp.argtypes = [C.c_void_p, C.c_int32] + [C.c_void_p] * 5
+        L.mgrhd_batch_infer.restype = C.c_int
+        L.mgrhd_batch_infer.argtypes = [C.c_void_p, C.c_void_p]
         L.mgrhd_batch_cells.restype = C.c_int64
         L.mgrhd_batch_cells.argtypes = [C.c_void_p]
         L.mgrhd_batch_destroy.restype = None
@@ -384,6 +389,25 @@ class Batch:
         rc = _batch_lib().mgrhd_batch_launch(self._h, self._stream(stream))
         if rc:
             raise MgrhdError(rc, "mgrhd_batch_launch")
+
+    def attach_mlp(self, n_groups, ws):
+        """Attach a warm-start network (warmstart.WarmStart) to the patches of
+        n_groups groups: every run/capture/launch then starts with one fused
+        inference launch per attached group count, writing each patch's
+        guess buffer, before the solve (mgrhd_batch_attach_mlp)."""
+        L = _batch_lib()
+        f = lambda t: t.data_ptr()
+        rc = L.mgrhd_batch_attach_mlp(self._h, int(n_groups), ws.net._h, f(ws.x_mean),
+                                      f(ws.x_istd), f(ws.y_mean), f(ws.y_std))
+        if rc:
+            raise MgrhdError(rc, "mgrhd_batch_attach_mlp")
+        self._keep_nets = getattr(self, "_keep_nets", []) + [ws]   # outlive the batch's use
+
+    def infer(self, stream=None):
+        """Only the attached networks' inference (mgrhd_batch_infer)."""
+        rc = _batch_lib().mgrhd_batch_infer(self._h, self._stream(stream))
+        if rc:
+            raise MgrhdError(rc, "mgrhd_batch_infer")
 
     @property
     def n_cells(self):

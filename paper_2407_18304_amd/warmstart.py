@@ -291,11 +291,20 @@ class PatchWarmStart:
     """Warm starts for batches of patches: one network per group count."""
     nets: dict           # N_g -> WarmStart
 
+    def attach(self, batch):
+        """Attach every network to the patches of its group count in a
+        mgrhd.Batch built with guess buffers: the batch's run/capture/launch
+        then starts with one fused inference launch per group count over all
+        of that count's patches (mgrhd_batch_attach_mlp)."""
+        for ng, ws in self.nets.items():
+            batch.attach_mlp(ng, ws)
+
     def guesses(self, dps, outs, kind=1):
         """Write the Newton guess of every patch (synth.DevicePatch-like:
         state, tables, kappa, layout.ng, consts()) into its buffer in `outs`
         with one fused inference launch per patch on the current stream;
-        allocates nothing, so the launches can be captured in a graph."""
+        allocates nothing, so the launches can be captured in a graph.
+        (attach() does the same with one launch per group count.)"""
         for dp, out in zip(dps, outs):
             self.nets[dp.layout.ng].guess(dp.state, dp.tables, dp.kappa, dp.consts(), kind=kind,
                                           out=out)

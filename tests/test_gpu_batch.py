@@ -194,10 +194,11 @@ def test_batch_bad_table_patch(gpl, scope):
 
 def test_batch_warm_start_matches_plain():
     """One network per group count, trained on solver pairs of patches drawn
-    with the training seed; the warm-started batch (temperature guess, one
-    fused inference launch per patch) gives the plain batch's results, eagerly
-    and replayed from one graph holding the inference launches and the batched
-    solve.  (Networks this small, trained on other patches' tables, need not
+    with the training seed and attached to the batch; the warm-started batch
+    (temperature guess, one fused inference launch per group count over all
+    of its patches, equal to the per-patch launches) gives the plain batch's
+    results, eagerly and replayed from the batch's graph holding the
+    inference launches and the batched solve.  (Networks this small, trained on other patches' tables, need not
     save Newton steps: the step counts are printed, and the benchmark measures
     the gain of fully trained networks.)"""
     from paper_2407_18304_amd import warmstart
@@ -245,27 +246,39 @@ def test_batch_warm_start_matches_plain():
         ip, iw = np.concatenate(it_p), np.concatenate(it_w)
         print(f"{label}: Newton steps per cell plain {ip.mean():.3f}, warm {iw.mean():.3f}")
 
+    # the per-patch inference (one launch per patch) for comparison
+    synth.fill_patches(dps)
+    per_patch = [torch.empty_like(g) for g in guesses]
+    with torch.cuda.stream(stream):
+        pws.guesses(dps, per_patch)
+    stream.synchronize()
+    pws.attach(bw)                            # one inference launch per group count
     synth.fill_patches(dps)                   # the same inputs again
     with torch.cuda.stream(stream):
-        pws.guesses(dps, guesses)
-        bw.run(stream.cuda_stream)
+        bw.infer(stream.cuda_stream)
+    stream.synchronize()
+    for g, q in zip(guesses, per_patch):      # same tiles, same kernel code
+        assert torch.equal(g, q)
+    synth.fill_patches(dps)
+    with torch.cuda.stream(stream):
+        bw.run(stream.cuda_stream)            # inference and solve
     stream.synchronize()
     check("eager")
-    g = torch.cuda.CUDAGraph()
-    synth.fill_patches(dps)
-    with torch.cuda.graph(g, stream=stream, capture_error_mode="thread_local"):
-        pws.guesses(dps, guesses)
-        bw.run(stream.cuda_stream)
+    with torch.cuda.stream(stream):
+        bw.capture(stream.cuda_stream)        # both in one graph
     torch.cuda.synchronize()
     for rep in range(2):
         synth.fill_patches(dps)
+        for g in guesses:
+            g.fill_(-1.0)                     # the replay must write them again
         x = torch.randn(1000, device="cuda").sum()      # eager work between replays
         torch.cuda.synchronize()
         with torch.cuda.stream(stream):
-            g.replay()
+            bw.launch(stream.cuda_stream)
         stream.synchronize()
         check(f"graph replay {rep}")
         del x
+    bw.close()
 
 
 def test_batch_full_size_sampled():
