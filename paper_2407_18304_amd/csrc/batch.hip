@@ -122,7 +122,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_batch(BatchArgs b) {
   __shared__ Tables<NGM> tabs[kBlock / kWave];
   using LS = LaneStore<G, G == 2>;
   __shared__ double lane_lds[LS::kSlots * kBlock];
-  const LS ls{lane_lds + threadIdx.x};
+  __shared__ double cell_lds[LS::kCellWords];
+  const LS ls{lane_lds + threadIdx.x, cell_lds};
   const int lane = threadIdx.x % kWave;
   Tables<NGM>& tab = tabs[threadIdx.x / kWave];
   int cur_patch = -1;
@@ -167,7 +168,8 @@ __global__ __launch_bounds__(kBlock, WPE) void k_batch_wg(BatchArgs b) {
   __shared__ int item_s, taken;
   using LS = LaneStore<G, G == 2>;
   __shared__ double lane_lds[LS::kSlots * kBlock];
-  const LS ls{lane_lds + threadIdx.x};
+  __shared__ double cell_lds[LS::kCellWords];
+  const LS ls{lane_lds + threadIdx.x, cell_lds};
   const int lane = threadIdx.x % kWave;
   int cur_patch = -1;
   bool table_ok = false;

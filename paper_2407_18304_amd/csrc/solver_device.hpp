@@ -238,22 +238,30 @@ __device__ __forceinline__ bool stage_tables(const KArgs& a, Tables<NGM>& t) {
 // Per-lane values held in LDS instead of registers: the fluxes F_k of the
 // lane's groups during the outer iteration (3G), in PC and PPL-fixed the
 // per-cell constants 1/tau_g = 1/(c_hat dt chi_0E,g) and 1/J_gg of eq. matrix
-// (2G), and with KEEP0 the old-time fluxes F^(t) (3G) and velocity v^(t) (3)
-// that every outer stage needs (without KEEP0 they are re-read from HBM).
-// Slot s of thread t lives at lds[s * kBlock + t]: the 64 lanes of a wave
-// touch 64 consecutive words, free of bank conflicts.
-template <int G, bool KEEP0>
+// (2G), and with KEEP0 the old-time fluxes F^(t) (3G) that every outer stage
+// needs (without KEEP0 they are re-read from HBM).  Slot s of thread t lives
+// at lds[s * kBlock + t]: the 64 lanes of a wave touch 64 consecutive words,
+// free of bank conflicts.  Per-cell values (with KEEP0 the old-time velocity
+// v^(t)) live once per cell, not once per lane: field f of cell slot c at
+// cells[f * CPB + c], CPB the most cells a workgroup holds at once (kBlock /
+// lanes per cell, or kBlock where the lane count varies between waves); all
+// lanes of a cell read the same word (an LDS broadcast).
+template <int G, bool KEEP0, int CPB = kBlock>
 struct LaneStore {
   static constexpr bool kKeep0 = KEEP0;
-  static constexpr int kSlots = 5 * G + (KEEP0 ? 3 * G + 3 : 0);
-  double* base;  // &lds[threadIdx.x]
+  static constexpr int kSlots = 5 * G + (KEEP0 ? 3 * G : 0);
+  static constexpr int kCPB = CPB;
+  static constexpr int kCellWords = (KEEP0 ? 3 : 1) * CPB;  // (one unused word-row without)
+  double* base;   // &lds[threadIdx.x]
+  double* cells;  // the cell area; at_cell() points it at one cell's slot
+  __device__ __forceinline__ LaneStore at_cell(int c) const { return LaneStore{base, cells + c}; }
   __device__ __forceinline__ double& F(int d, int k) const { return base[(d * G + k) * kBlock]; }
   __device__ __forceinline__ double& itau(int k) const { return base[(3 * G + k) * kBlock]; }
   __device__ __forceinline__ double& iJgg(int k) const { return base[(4 * G + k) * kBlock]; }
   __device__ __forceinline__ double& F0(int d, int k) const {
     return base[(5 * G + d * G + k) * kBlock];
   }
-  __device__ __forceinline__ double& v0(int d) const { return base[(8 * G + d) * kBlock]; }
+  __device__ __forceinline__ double& v0(int d) const { return cells[d * CPB]; }
 };
 
 // Material data of this lane's groups at one temperature.
@@ -544,7 +552,7 @@ __device__ __forceinline__ void load_cell(const KArgs& a, const Tables<NGM>& t, 
             isfinite(s.v[0]) && isfinite(s.v[1]) && isfinite(s.v[2]);
   s.rho_kappa = s.rho * kap;
   s.ircv = 1.0 / (s.rho * a.cv);
-  if (LS::kKeep0) {
+  if (LS::kKeep0 && j == 0) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) ls.v0(d) = s.v[d];
   }
@@ -908,10 +916,16 @@ struct BlockQueue {
 
 template <int G, int LPC, int MODE, int NGM, bool TD = false, bool FULL = false, class LS,
           class Q>
-__device__ __forceinline__ void run_cells(const KArgs& a, const Tables<NGM>& tab, const LS& ls,
-                                          int lane, Q q) {
+__device__ __forceinline__ void run_cells(const KArgs& a, const Tables<NGM>& tab,
+                                          const LS& ls_block, int lane, Q q) {
   static_assert(LPC >= 1 && LPC <= kWave && (LPC & (LPC - 1)) == 0, "lanes per cell");
   const int j = lane % LPC;
+  // this cell's slot in the per-cell area: with room for a cell per lane
+  // (CPB = kBlock, the batched kernels, whose waves may run different lane
+  // counts) the slot of the cell's first lane, else the cell's rank in the
+  // workgroup (every wave runs the same lane count)
+  const LS ls = ls_block.at_cell(LS::kCPB == kBlock ? (int)threadIdx.x - j
+                                                    : (int)threadIdx.x / LPC);
   CellState<G> s;
   s.phase = P_EMPTY;
   s.i = -1;

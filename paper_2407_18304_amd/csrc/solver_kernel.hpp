@@ -16,9 +16,10 @@ template <int G, int LPC, int MODE, int WPE, bool TD, bool FULL>
 __global__ __launch_bounds__(kBlock, WPE) void k_source_update(KArgs a) {
   constexpr int NGM = G * LPC;
   __shared__ Tables<NGM> tab;
-  using LS = LaneStore<G, true>;
+  using LS = LaneStore<G, true, kBlock / LPC>;
   __shared__ double lane_lds[LS::kSlots * kBlock];
-  const LS ls{lane_lds + threadIdx.x};
+  __shared__ double cell_lds[LS::kCellWords];
+  const LS ls{lane_lds + threadIdx.x, cell_lds};
   __shared__ int taken;  // cells of this workgroup's range handed out so far
   if (threadIdx.x == 0) taken = 0;
   const bool table_ok = stage_tables<NGM, MODE>(a, tab);  // (its barriers publish `taken`)
