@@ -3,9 +3,13 @@
 
 A step is one full source update (inner Newton, energy, flux and momentum
 updates, outer passes) of every cell of the workload.  The inputs are drawn
-in HBM by the device generator; before every step the pristine inputs are
-copied back over the in-place state (a device copy, inside the timed region),
-so every step solves the same input distribution.
+in HBM by the device generator.  The single-table workloads update out of
+place (mgrhd_options.E_g_out ...): every step reads the same inputs, left
+unchanged, and writes the updated state to separate arrays, as a time step
+from U^(n) to U^(n+1) does, so every step solves the same input
+distribution with nothing but the update in the timed region.  The batched
+patches update in place; there the pristine inputs are copied back before
+every step (a device copy, inside the timed region).
 
 Prints one JSON line (see the repository's benchmark contract)."""
 from __future__ import annotations
@@ -164,17 +168,13 @@ def run_single(name, args, extra=False):
     else:
         from paper_2407_18304_amd import autotune
         autotune.apply_cache(mode=args.mode)   # the autotuner's choices for this GPU
-    pristine = {k: v.clone() for k, v in dw.state.items()}
-    st = dw.state
+    st = dw.state     # the inputs: read by every step, never modified
+    res = {k: torch.empty_like(st[k]) for k in ("E_g", "F_g", "e_gas", "v")}   # the outputs
     iters = torch.zeros(n, dtype=torch.int32, device=dev)
     outer = torch.zeros(n, dtype=torch.int32, device=dev)
     status = torch.zeros(n, dtype=torch.int32, device=dev)
     tab = dw.tables
     stream = torch.cuda.current_stream(dev)
-
-    def restore():
-        for k in ("E_g", "F_g", "e_gas", "v"):
-            st[k].copy_(pristine[k])
 
     ws, winfo = None, None
     if args.warm and not extra:
@@ -192,18 +192,17 @@ def run_single(name, args, extra=False):
                             mean_mode=args.mode, polish=args.polish, closure=args.closure,
                             guess=guess, guess_kind=1,
                             iters=iters, outer=outer, status=status,
-                            stream=stream.cuda_stream, **dw.consts(), **dw.topacity())
+                            stream=stream.cuda_stream, **dw.consts(), **dw.topacity(),
+                            out=(res["E_g"], res["F_g"], res["e_gas"], res["v"]))
 
     def timed(warm):
         for _ in range(args.warmup):
-            restore()
             solve(warm)
         torch.cuda.synchronize()
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
               for _ in range(args.steps)]
         t0 = time.perf_counter()
         for k in range(args.steps):
-            restore()
             ev[k][0].record(stream)
             solve(warm)
             ev[k][1].record(stream)
@@ -216,7 +215,7 @@ def run_single(name, args, extra=False):
         _, _, plain_ms = timed(False)
         plain_it = iters.cpu().numpy().copy()
         plain_st = status.cpu().numpy().copy()
-        plain_state = {k: st[k].clone() for k in ("E_g", "F_g", "e_gas", "v")}
+        plain_state = {k: res[k].clone() for k in ("E_g", "F_g", "e_gas", "v")}
         # the ceiling of any temperature guess: the solve started from the
         # plain solution's own E_gas (guess kind 1), on the same inputs
         exact_guess = plain_state["e_gas"]
@@ -224,7 +223,6 @@ def run_single(name, args, extra=False):
         exact_it = iters.cpu().numpy().copy()
         # the fused inference kernel alone, on pristine inputs, against the
         # matrix-core peak: the products it computes (temperature output only)
-        restore()
         gbuf = torch.empty(n, dtype=torch.float64, device=dev)
         ws.guess(st, tab, dw.kappa, dw.consts(), out=gbuf)
         inf_ms = []
@@ -259,7 +257,7 @@ def run_single(name, args, extra=False):
     achieved_bw = bpc * n / kern_s
     # FP64 work of the last step (every step solves the same inputs)
     u = dw.consts()
-    T_fin = (st["e_gas"] - 0.5 * st["rho"] * (st["v"] ** 2).sum(0)) / (st["rho"] * u["c_v"])
+    T_fin = (res["e_gas"] - 0.5 * st["rho"] * (res["v"] ** 2).sum(0)) / (st["rho"] * u["c_v"])
     mix = F.edge_mix(W.spec_tables(name)[0], u["h_over_k"], T_fin.clamp(min=1e-300))
     valid = torch.from_numpy(((stt & 8) == 0).astype(np.float64)).to(dev)
     fpc = F.flops_per_cell(ng, args.mode, iters.double(), outer.double(), mix, valid=valid,
@@ -334,7 +332,7 @@ def run_single(name, args, extra=False):
         ok = (plain_st == 0) & ((stt & ~4) == 0)
         dev_max = 0.0
         for k in ("E_g", "e_gas"):
-            d = ((st[k] - plain_state[k]).abs() /
+            d = ((res[k] - plain_state[k]).abs() /
                  plain_state[k].abs().clamp(min=1e-300)).reshape(-1, n)[:, torch.from_numpy(ok).to(dev)]
             dev_max = max(dev_max, float(d.max()) if d.numel() else 0.0)
         winfo.update({
@@ -356,7 +354,6 @@ def run_single(name, args, extra=False):
         result["config"]["warm_start"] = "network temperature guess (guess kind 1)"
 
     if args.cpu_seconds > 0:
-        restore()
         torch.cuda.synchronize()
         result["cpu_baseline"] = cpu_baseline(dw, args.mode, args.cpu_seconds)
     return result

@@ -142,6 +142,17 @@ typedef struct {
                                      -1 for every pass that did not.  A record of
                                      where the stop tests ended each pass (a
                                      checker can replay it)                      */
+  /* Out-of-place update (mgrhd_source_update only): with all four set, the
+   * updated E_g, F_g, e_gas, v are written here (same layouts) and the input
+   * arrays are only read; a cell left untouched (invalid input, a table
+   * error, non-finite results) gets its input values copied.  All four NULL:
+   * the update is in place.  An output must be its input array or not
+   * overlap any argument.  The IMEX steps and the batch return
+   * MGRHD_E_OPTION when any is set. */
+  double* E_g_out;                /* [N_g][n]    */
+  double* F_g_out;                /* [3][N_g][n] */
+  double* e_gas_out;              /* [n]         */
+  double* v_out;                  /* [3][n]      */
 } mgrhd_options;
 
 /* Fill *opt with the defaults: c = a_rad = h_over_k = 1, c_v = 3/2,
@@ -149,7 +160,8 @@ typedef struct {
  * M1 closure, polish = 0, all optional arrays NULL. */
 void mgrhd_default_options(mgrhd_options* opt);
 
-/* The source update of n_cells cells, in place (see the top of this file).
+/* The source update of n_cells cells, in place (see the top of this file),
+ * or from the given arrays into opt's *_out arrays (out of place).
  *   E_g          [N_g][n]    in/out  group radiation energy densities
  *   F_g          [3][N_g][n] in/out  group radiation fluxes
  *   rho          [n]         in      gas density

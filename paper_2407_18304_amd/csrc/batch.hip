@@ -102,8 +102,10 @@ __device__ __forceinline__ void run_item_lpc(const KArgs& a, const Tables<NGM>& 
 // TRY_FULL: items whose N_g fills every slot (N_g = lanes per cell x G) run
 // the state machine compiled for that case (no per-slot group checks).
 template <int G, int MODE, int NGM, bool TRY_FULL, class LS, class Q>
-__device__ __forceinline__ void run_item(const KArgs& a, const Tables<NGM>& tab, const LS& ls,
-                                         int lane, Q q) {
+__device__ __forceinline__ void run_item(const KArgs& a, const Tables<NGM>& tab,
+                                         const LS& ls_block, int lane, Q q) {
+  // a is an entry of the batch's device array of patch arguments
+  const LS ls = ls_block.with_args((KArgsRef)&a);
   int lpc = 1;
   while (lpc * G < a.ng) lpc <<= 1;
   if (TRY_FULL && lpc * G == a.ng)
@@ -123,7 +125,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_batch(BatchArgs b) {
   using LS = LaneStore<G, G == 2>;
   __shared__ double lane_lds[LS::kSlots * kBlock];
   __shared__ double cell_lds[LS::kCellWords];
-  const LS ls{lane_lds + threadIdx.x, cell_lds};
+  const LS ls{lane_lds + threadIdx.x, cell_lds, nullptr};  // run_item sets the arguments
   const int lane = threadIdx.x % kWave;
   Tables<NGM>& tab = tabs[threadIdx.x / kWave];
   int cur_patch = -1;
@@ -169,7 +171,7 @@ __global__ __launch_bounds__(kBlock, WPE) void k_batch_wg(BatchArgs b) {
   using LS = LaneStore<G, G == 2>;
   __shared__ double lane_lds[LS::kSlots * kBlock];
   __shared__ double cell_lds[LS::kCellWords];
-  const LS ls{lane_lds + threadIdx.x, cell_lds};
+  const LS ls{lane_lds + threadIdx.x, cell_lds, nullptr};  // run_item sets the arguments
   const int lane = threadIdx.x % kWave;
   int cur_patch = -1;
   bool table_ok = false;
@@ -312,6 +314,8 @@ int mgrhd_batch_create(const mgrhd_patch* patches, int32_t n_patches, int32_t me
   mgrhd_default_options(&defaults);
   const mgrhd_options* opt = opt_in ? opt_in : &defaults;
   if (opt->closure < 0 || opt->closure > 1) return MGRHD_E_MODE;
+  if (opt->E_g_out || opt->F_g_out || opt->e_gas_out || opt->v_out)
+    return MGRHD_E_OPTION;  // patches are updated in place
   auto pos = [](double x) { return x > 0.0 && std::isfinite(x); };
   if (!pos(opt->c) || !pos(opt->a_rad) || !pos(opt->h_over_k) || !pos(opt->c_v))
     return MGRHD_E_SCALAR;
@@ -649,6 +653,10 @@ int mgrhd_batch_tune(mgrhd_batch* bt, mgrhd_stream_t stream) {
     t.rho = take(a.rho, 1);
     t.egas = take(a.egas, 1);
     t.v = take(a.v, 3);
+    t.Eo = t.E;  // the trial runs update the copies in place
+    t.Fo = t.F;
+    t.egaso = t.egas;
+    t.vo = t.v;
     t.kappa = a.kappa ? take(a.kappa, 1) : nullptr;
     t.S = a.S ? take(a.S, a.ng) : nullptr;
     t.guess = a.guess ? take(a.guess, a.guess_kind == 1 ? 1 : a.ng + 1) : nullptr;

@@ -86,6 +86,8 @@ int mgrhd_imex_step_noalloc(double* E_g, double* F_g, const double* rho, double*
   if (!opacity) return MGRHD_E_NULL;
   if (n_cells < 0 || opacity->n_groups < 1 || opacity->n_groups > MGRHD_MAX_GROUPS)
     return MGRHD_E_SIZE;
+  if (opt && (opt->E_g_out || opt->F_g_out || opt->e_gas_out || opt->v_out))
+    return MGRHD_E_OPTION;  // the IMEX step works in place
   const size_t need = mgrhd_imex_workspace_bytes(n_cells, opacity->n_groups);
   if (need > sizeof(double) * (size_t)MGRHD_IMEX_SCRATCH_DOUBLES) return MGRHD_E_SIZE;
   hipError_t err = hipSuccess;
@@ -103,6 +105,8 @@ int mgrhd_imex_step(double* E_g, double* F_g, const double* rho, double* e_gas, 
   if (!opacity || !work) return MGRHD_E_NULL;
   if (n_cells < 0 || opacity->n_groups < 1 || opacity->n_groups > MGRHD_MAX_GROUPS)
     return MGRHD_E_SIZE;
+  if (opt && (opt->E_g_out || opt->F_g_out || opt->e_gas_out || opt->v_out))
+    return MGRHD_E_OPTION;  // the IMEX step works in place
   if (work_bytes < mgrhd_imex_workspace_bytes(n_cells, opacity->n_groups)) return MGRHD_E_SIZE;
   if (!(dt > 0.0)) return MGRHD_E_SCALAR;
   if (n_cells == 0) return 0;

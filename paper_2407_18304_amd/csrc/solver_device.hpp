@@ -21,11 +21,15 @@
 namespace mgrhd {
 
 struct KArgs {
-  double* E;
+  double* E;  // inputs (in place: also the outputs)
   double* F;
   const double* rho;
   double* egas;
   double* v;
+  double* Eo;  // outputs: the inputs for an update in place
+  double* Fo;
+  double* egaso;
+  double* vo;
   const double* kappa;
   const double* S;
   const double* guess;
@@ -50,14 +54,71 @@ struct KArgs {
   int32_t stim, pad;
 };
 
-// Fill the derived constants of a (host side).
+// Fill the derived constants of a (host side); outputs left NULL are the
+// inputs (an update in place).
 inline void set_derived(KArgs& a) {
+  if (!a.Eo) {
+    a.Eo = a.E;
+    a.Fo = a.F;
+    a.egaso = a.egas;
+    a.vo = a.v;
+  }
   a.cc = a.c / a.chat;
   a.icc = a.chat / a.c;
   a.cdt = a.chat * a.dt;
   a.ic2 = 1.0 / (a.c * a.c);
   a.iccc = 1.0 / (a.c * a.chat);
   a.cdt_ic2 = a.cdt * a.ic2;
+}
+
+// The argument block of a launch where the device can read it with scalar
+// loads: the kernel-argument segment (single-table kernel) or the batch's
+// device array of patch arguments.  Only the state arrays are read through
+// it, where a finished cell is stored (see out_ptrs).
+typedef const KArgs __attribute__((address_space(4)))* KArgsRef;
+
+// The state arrays of a launch, read from its argument block where a finished
+// cell needs them: the block's address passes through an empty asm, so the
+// scalar loads stay at the use (once per finished cell) instead of being
+// hoisted out of the persistent loop, where the eight pointers would hold
+// sixteen scalar registers for the whole kernel (which spilled 74 of them).
+struct StatePtrs {
+  const double *E, *F, *egas, *v;  // inputs
+  double *Eo, *Fo, *egaso, *vo;     // outputs (the inputs for an update in place)
+};
+__device__ __forceinline__ StatePtrs state_ptrs(KArgsRef ap) {
+  asm volatile("" : "+s"(ap));
+  return StatePtrs{ap->E, ap->F, ap->egas, ap->v, ap->Eo, ap->Fo, ap->egaso, ap->vo};
+}
+
+// One field of the argument block, read where it is used (as state_ptrs).
+template <class T>
+__device__ __forceinline__ T arg_at_use(KArgsRef ap, T KArgs::*m) {
+  asm volatile("" : "+s"(ap));
+  return ap->*m;
+}
+
+// Out of place: the input state of cell i copied to the outputs, for a cell
+// the update leaves untouched (lane j of the cell's lpc lanes copies rows
+// j, j + lpc, ...).
+__device__ __forceinline__ void copy_through(const KArgs& a, const StatePtrs& p, int64_t i,
+                                             int j, int lpc) {
+  if (p.Eo == p.E) return;
+  const int64_t n = a.n;
+  const int ng = a.ng;
+  for (int r = j; r < 4 * ng + 4; r += lpc) {
+    if (r < ng) {
+      p.Eo[(int64_t)r * n + i] = p.E[(int64_t)r * n + i];
+    } else if (r < 4 * ng) {
+      const int64_t q = (int64_t)(r - ng) * n + i;
+      p.Fo[q] = p.F[q];
+    } else if (r == 4 * ng) {
+      p.egaso[i] = p.egas[i];
+    } else {
+      const int64_t q = (int64_t)(r - 4 * ng - 1) * n + i;
+      p.vo[q] = p.v[q];
+    }
+  }
 }
 
 constexpr int kBlock = 256;
@@ -254,7 +315,13 @@ struct LaneStore {
   static constexpr int kCellWords = (KEEP0 ? 3 : 1) * CPB;  // (one unused word-row without)
   double* base;   // &lds[threadIdx.x]
   double* cells;  // the cell area; at_cell() points it at one cell's slot
-  __device__ __forceinline__ LaneStore at_cell(int c) const { return LaneStore{base, cells + c}; }
+  KArgsRef args;  // the launch's argument block (state_ptrs)
+  __device__ __forceinline__ LaneStore at_cell(int c) const {
+    return LaneStore{base, cells + c, args};
+  }
+  __device__ __forceinline__ LaneStore with_args(KArgsRef ap) const {
+    return LaneStore{base, cells, ap};
+  }
   __device__ __forceinline__ double& F(int d, int k) const { return base[(d * G + k) * kBlock]; }
   __device__ __forceinline__ double& itau(int k) const { return base[(3 * G + k) * kBlock]; }
   __device__ __forceinline__ double& iJgg(int k) const { return base[(4 * G + k) * kBlock]; }
@@ -543,11 +610,14 @@ __device__ __forceinline__ void load_cell(const KArgs& a, const Tables<NGM>& t, 
   s.k_out = 0;
   s.polish_left = -1;
   s.fell_back = false;
-  s.rho = a.rho[i];
-  s.egas0 = a.egas[i];
+  const StatePtrs sp = state_ptrs(ls.args);
+  s.rho = arg_at_use(ls.args, &KArgs::rho)[i];
+  s.egas0 = sp.egas[i];
 #pragma unroll
-  for (int d = 0; d < 3; ++d) s.v[d] = a.v[(int64_t)d * n + i];
-  const double kap = a.kappa ? a.kappa[i] : 1.0;
+  for (int d = 0; d < 3; ++d) s.v[d] = sp.v[(int64_t)d * n + i];
+  const double* kappa = arg_at_use(ls.args, &KArgs::kappa);
+  const double* S = arg_at_use(ls.args, &KArgs::S);
+  const double kap = kappa ? kappa[i] : 1.0;
   bool ok = s.rho > 0.0 && isfinite(s.rho) && kap > 0.0 && isfinite(kap) && isfinite(s.egas0) &&
             isfinite(s.v[0]) && isfinite(s.v[1]) && isfinite(s.v[2]);
   s.rho_kappa = s.rho * kap;
@@ -567,14 +637,14 @@ __device__ __forceinline__ void load_cell(const KArgs& a, const Tables<NGM>& t, 
     double f[3] = {0.0, 0.0, 0.0};
     double it = 0.0, ij = -1.0;
     if (g < ng) {
-      const double e = a.E[(int64_t)g * n + i];
-      const double sg = a.S ? a.S[(int64_t)g * n + i] : 0.0;
+      const double e = sp.E[(int64_t)g * n + i];
+      const double sg = S ? S[(int64_t)g * n + i] : 0.0;
       ok = ok && e >= 0.0 && isfinite(e) && isfinite(sg);
       s.E0[k] = e + sg;
       sumE += e + sg;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        f[d] = a.F[((int64_t)d * ng + g) * n + i];
+        f[d] = sp.F[((int64_t)d * ng + g) * n + i];
         ok = ok && isfinite(f[d]);
       }
       s.vF[k] = s.v[0] * f[0] + s.v[1] * f[1] + s.v[2] * f[2];
@@ -598,18 +668,19 @@ __device__ __forceinline__ void load_cell(const KArgs& a, const Tables<NGM>& t, 
   s.ke = 0.5 * s.rho * (s.v[0] * s.v[0] + s.v[1] * s.v[1] + s.v[2] * s.v[2]);
   s.etot = s.egas0 + a.icc * sumE;  // E_tot of Sec. 3
   ok = bad == 0.0 && (s.egas0 - s.ke) > 0.0 && s.etot > 0.0;
-  s.warm = a.guess != nullptr;
+  const double* guess = arg_at_use(ls.args, &KArgs::guess);
+  s.warm = guess != nullptr;
   s.elim = false;
   s.egv = s.egas0;
   if (ok && s.warm) {
-    s.egv = a.guess[i];
+    s.egv = guess[i];
     if (a.guess_kind == 1) {
       s.elim = true;  // R_g from the group balances at the first evaluation
     } else {
 #pragma unroll
       for (int k = 0; k < G; ++k) {
         const int g = gidx<LPC>(j, k, s.lpc);
-        if (g < ng) s.R[k] = a.guess[(int64_t)(g + 1) * n + i];
+        if (g < ng) s.R[k] = guess[(int64_t)(g + 1) * n + i];
       }
     }
   }
@@ -638,31 +709,39 @@ __device__ __forceinline__ void finish_cell(const KArgs& a, int j, CellState<G>&
         if (!isfinite(ls.F(d, k))) bad = 1.0;
     }
     bad = cell_sum<LPC>(bad, s.lpc);
+    const StatePtrs p = state_ptrs(ls.args);
     if (bad != 0.0) {
       s.st |= MGRHD_ST_NONFINITE;
+      copy_through(a, p, i, j, s.lpc);
     } else {
 #pragma unroll
       for (int k = 0; k < G; ++k) {
         const int g = gidx<LPC>(j, k, s.lpc);
         if (g >= ng) continue;
-        a.E[(int64_t)g * n + i] = s.E0[k] + s.R[k];
+        p.Eo[(int64_t)g * n + i] = s.E0[k] + s.R[k];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) a.F[((int64_t)d * ng + g) * n + i] = ls.F(d, k);
+        for (int d = 0; d < 3; ++d) p.Fo[((int64_t)d * ng + g) * n + i] = ls.F(d, k);
       }
       if (j == 0) {
-        a.egas[i] = egas_new;
-        a.v[i] = s.v[0];
-        a.v[n + i] = s.v[1];
-        a.v[2 * n + i] = s.v[2];
+        p.egaso[i] = egas_new;
+        p.vo[i] = s.v[0];
+        p.vo[n + i] = s.v[1];
+        p.vo[2 * n + i] = s.v[2];
       }
     }
+  } else {
+    copy_through(a, state_ptrs(ls.args), i, j, s.lpc);
   }
   if (j == 0) {
-    if (a.status) a.status[i] = s.st;
-    if (a.iters) a.iters[i] = s.steps;
-    if (a.outer) a.outer[i] = s.passes;
-    if (a.trace)  // passes whose outer stage did not run (the last one's did if stored)
-      for (int k = store ? s.k_out + 1 : s.k_out; k < a.max_outer; ++k) a.trace[(int64_t)k * n + i] = -1;
+    int32_t* const status = arg_at_use(ls.args, &KArgs::status);
+    int32_t* const iters = arg_at_use(ls.args, &KArgs::iters);
+    int32_t* const outer = arg_at_use(ls.args, &KArgs::outer);
+    int32_t* const trace = arg_at_use(ls.args, &KArgs::trace);
+    if (status) status[i] = s.st;
+    if (iters) iters[i] = s.steps;
+    if (outer) outer[i] = s.passes;
+    if (trace)  // passes whose outer stage did not run (the last one's did if stored)
+      for (int k = store ? s.k_out + 1 : s.k_out; k < a.max_outer; ++k) trace[(int64_t)k * n + i] = -1;
   }
   s.phase = P_EMPTY;
 }
@@ -817,7 +896,10 @@ __device__ __forceinline__ bool flux_step(const KArgs& a, const Tables<NGM>& t, 
   const int ng = group_count<G, LPC, FULL>(a);
   const int64_t n = a.n, i = s.i;
   const double cdt = a.cdt;
-  if (a.trace && j == 0) a.trace[(int64_t)s.k_out * n + i] = s.steps;
+  if (j == 0) {
+    int32_t* const trace = arg_at_use(ls.args, &KArgs::trace);
+    if (trace) trace[(int64_t)s.k_out * n + i] = s.steps;
+  }
   double dmom[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int k = 0; k < G; ++k) {

@@ -19,7 +19,9 @@ __global__ __launch_bounds__(kBlock, WPE) void k_source_update(KArgs a) {
   using LS = LaneStore<G, true, kBlock / LPC>;
   __shared__ double lane_lds[LS::kSlots * kBlock];
   __shared__ double cell_lds[LS::kCellWords];
-  const LS ls{lane_lds + threadIdx.x, cell_lds};
+  // the arguments as the device reads them in place (a is the only argument)
+  const KArgsRef ap = (KArgsRef)__builtin_amdgcn_kernarg_segment_ptr();
+  const LS ls{lane_lds + threadIdx.x, cell_lds, ap};
   __shared__ int taken;  // cells of this workgroup's range handed out so far
   if (threadIdx.x == 0) taken = 0;
   const bool table_ok = stage_tables<NGM, MODE>(a, tab);  // (its barriers publish `taken`)
@@ -31,6 +33,7 @@ __global__ __launch_bounds__(kBlock, WPE) void k_source_update(KArgs a) {
   if (!table_ok) {
     // the table is unusable: report every cell of this workgroup's range
     for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
+      copy_through(a, state_ptrs(ap), i, 0, 1);
       if (a.status) a.status[i] = MGRHD_ST_BAD_TABLE;
       if (a.iters) a.iters[i] = 0;
       if (a.outer) a.outer[i] = 0;

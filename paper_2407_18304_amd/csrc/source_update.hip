@@ -213,6 +213,8 @@ int mgrhd_source_update(double* E_g, double* F_g, const double* rho, double* e_g
   if (ng < 1 || ng > MGRHD_MAX_GROUPS) return MGRHD_E_SIZE;
   if (op->mean_mode < 0 || op->mean_mode > 2) return MGRHD_E_MODE;
   if (opt->closure < 0 || opt->closure > 1) return MGRHD_E_MODE;
+  const int n_out = !!opt->E_g_out + !!opt->F_g_out + !!opt->e_gas_out + !!opt->v_out;
+  if (n_out != 0 && n_out != 4) return MGRHD_E_NULL;  // out of place needs all four
   if (n_cells == 0) return 0;
   if (!E_g || !F_g || !rho || !e_gas || !v || !group_edges || !op->chi_lo) return MGRHD_E_NULL;
   if (op->mean_mode != MGRHD_MEAN_PC && !op->alpha_chi && !op->chi_hi) return MGRHD_E_TABLE;
@@ -240,6 +242,12 @@ int mgrhd_source_update(double* E_g, double* F_g, const double* rho, double* e_g
   a.rho = rho;
   a.egas = e_gas;
   a.v = v;
+  if (n_out == 4) {
+    a.Eo = opt->E_g_out;
+    a.Fo = opt->F_g_out;
+    a.egaso = opt->e_gas_out;
+    a.vo = opt->v_out;
+  }
   a.kappa = op->kappa_scale;
   a.S = opt->S_g;
   a.guess = opt->guess;

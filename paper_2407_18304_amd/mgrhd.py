@@ -49,7 +49,9 @@ class Options(C.Structure):
                 ("max_newton", C.c_int32), ("max_outer", C.c_int32), ("closure", C.c_int32),
                 ("polish", C.c_int32), ("S_g", C.c_void_p), ("guess", C.c_void_p),
                 ("iters", C.c_void_p), ("outer", C.c_void_p), ("status", C.c_void_p),
-                ("guess_kind", C.c_int32), ("reserved", C.c_int32), ("trace", C.c_void_p)]
+                ("guess_kind", C.c_int32), ("reserved", C.c_int32), ("trace", C.c_void_p),
+                ("E_g_out", C.c_void_p), ("F_g_out", C.c_void_p), ("e_gas_out", C.c_void_p),
+                ("v_out", C.c_void_p)]
 
 
 _lib = None
@@ -195,8 +197,10 @@ def source_update(E_g, F_g, rho, e_gas, v, group_edges, chi_lo, *, dt, c_hat,
                   max_newton=100, max_outer=20, closure=CLOSURE_M1, polish=0, S_g=None,
                   guess=None, guess_kind=0, iters=None, outer=None, status=None, stream=None,
                   imex_work=None, imex_noalloc=False, t_exp=0.0, t_ref=1.0, stim=0,
-                  trace=None):
-    """In-place source update of the device state (see include/mgrhd.h).
+                  trace=None, out=None):
+    """Source update of the device state (see include/mgrhd.h): in place, or
+    with out=(E_g_out, F_g_out, e_gas_out, v_out) (tensors shaped as the
+    inputs) from the given state into those, leaving the inputs unchanged.
     guess_kind 0: guess is [N_g+1, n] (E_gas, R_g); 1: guess is [n] (E_gas).
     imex_work: a device tensor of at least imex_workspace_bytes(n, N_g) bytes
     turns the call into one two-stage IMEX step (mgrhd_imex_step);
@@ -218,6 +222,12 @@ def source_update(E_g, F_g, rho, e_gas, v, group_edges, chi_lo, *, dt, c_hat,
     o.outer = _ptr(outer, (n,), torch.int32, "outer")
     o.status = _ptr(status, (n,), torch.int32, "status")
     o.trace = _ptr(trace, (max_outer, n), torch.int32, "trace")
+    if out is not None:
+        Eo, Fo, eo, vo = out
+        o.E_g_out = _ptr(Eo, (ng, n), name="E_g_out")
+        o.F_g_out = _ptr(Fo, (3, ng, n), name="F_g_out")
+        o.e_gas_out = _ptr(eo, (n,), name="e_gas_out")
+        o.v_out = _ptr(vo, (3, n), name="v_out")
     op = OpacityParams(ng, mean_mode, _ptr(chi_lo, (ng,), name="chi_lo"),
                        _ptr(alpha_chi, (ng,), name="alpha_chi"),
                        _ptr(chi_hi, (ng,), name="chi_hi"),
