@@ -213,9 +213,10 @@ int mgrhd_variant_info(int32_t k, int32_t* lanes_per_cell, int32_t* groups_per_l
  *   U^(n+1/2) = U^(n) + dt S(U^(n+1/2))            (source update, theta dt = dt)
  *   U^(n+1)   = (U^(n) + U^(n+1/2))/2 + (dt/2) S(U^(n+1))   (theta dt = dt/2).
  * mgrhd_imex_step performs both stages in place on the state of
- * mgrhd_source_update (same arguments and layout), keeping U^(n) in the
- * caller's DEVICE workspace `work` of at least mgrhd_imex_workspace_bytes()
- * bytes (8 n (4 N_g + 4)); nothing is allocated.  opt->iters/outer/status
+ * mgrhd_source_update (same arguments and layout), the first stage writing
+ * U^(n+1/2) into the caller's DEVICE workspace `work` of at least
+ * mgrhd_imex_workspace_bytes() bytes (8 n (4 N_g + 4)), out of place, so
+ * that U^(n) is never copied; nothing is allocated.  opt->iters/outer/status
  * report the second stage.  Returns as mgrhd_source_update; MGRHD_E_SIZE if
  * the workspace is too small. */
 size_t mgrhd_imex_workspace_bytes(int64_t n_cells, int32_t n_groups);
@@ -227,8 +228,8 @@ int mgrhd_imex_step(double* E_g, double* F_g, const double* rho, double* e_gas, 
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the IMEX
- * step of mgrhd_imex_step with no workspace argument.  U^(n) is kept in an
- * array owned by the library, MGRHD_IMEX_SCRATCH_DOUBLES doubles (32 MiB) per
+ * step of mgrhd_imex_step with no workspace argument.  U^(n+1/2) is kept in
+ * an array owned by the library, MGRHD_IMEX_SCRATCH_DOUBLES doubles (32 MiB) per
  * GPU, held from the first call on that GPU until the process ends; the call
  * allocates nothing.  Limit: mgrhd_imex_workspace_bytes(n_cells, n_groups)
  * <= 32 MiB (e.g. 123 361 cells at 16 groups, 31 775 at 64), else

@@ -13,7 +13,7 @@
 namespace mgrhd {
 namespace imex {
 
-// Library-owned copy of U^(n) for mgrhd_imex_step_noalloc: a file-scope
+// Library-owned U^(n+1/2) for mgrhd_imex_step_noalloc: a file-scope
 // device array (one per GPU the library runs on, held until the process
 // ends).  Host code never uses this name as an address: it takes the array's
 // device address per device from hipGetSymbolAddress (scratch_ptr below).
@@ -114,23 +114,22 @@ int mgrhd_imex_step(double* E_g, double* F_g, const double* rho, double* e_gas, 
   hipStream_t s = (hipStream_t)stream;
   const int64_t n = n_cells, nE = n * opacity->n_groups;
   double* w = (double*)work;
-  // keep U^(n)
-  const struct {
-    const double* p;
-    int64_t count;
-  } parts[4] = {{E_g, nE}, {F_g, 3 * nE}, {e_gas, n}, {v, 3 * n}};
-  int64_t off = 0;
-  for (const auto& q : parts) {
-    if (hipMemcpyAsync(w + off, q.p, sizeof(double) * q.count, hipMemcpyDeviceToDevice, s) !=
-        hipSuccess)
-      return (int)hipGetLastError();
-    off += q.count;
-  }
-  // first stage: U^(n+1/2) = U^(n) + dt S(U^(n+1/2))
+  // first stage, out of place: U^(n+1/2) = U^(n) + dt S(U^(n+1/2)) into the
+  // workspace (E_g, F_g, e_gas, v end to end), U^(n) left in the caller's arrays
+  mgrhd_options o1;
+  if (opt)
+    o1 = *opt;
+  else
+    mgrhd_default_options(&o1);
+  o1.E_g_out = w;
+  o1.F_g_out = w + nE;
+  o1.e_gas_out = w + 4 * nE;
+  o1.v_out = w + 4 * nE + n;
   int rc = mgrhd_source_update(E_g, F_g, rho, e_gas, v, n, group_edges, opacity, dt, c_hat,
-                               stream, opt);
+                               stream, &o1);
   if (rc) return rc;
-  // second stage from the midpoint with theta dt = dt / 2
+  // second stage from the midpoint (U^(n) + U^(n+1/2))/2, formed in the
+  // caller's arrays, with theta dt = dt / 2, in place
   int64_t blocks = (4 * nE + 4 * n + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(mgrhd::imex::k_midpoint, dim3((unsigned)blocks), dim3(256), 0, s, E_g, F_g,

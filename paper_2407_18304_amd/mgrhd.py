@@ -204,7 +204,7 @@ def source_update(E_g, F_g, rho, e_gas, v, group_edges, chi_lo, *, dt, c_hat,
     guess_kind 0: guess is [N_g+1, n] (E_gas, R_g); 1: guess is [n] (E_gas).
     imex_work: a device tensor of at least imex_workspace_bytes(n, N_g) bytes
     turns the call into one two-stage IMEX step (mgrhd_imex_step);
-    imex_noalloc=True makes it the IMEX step that keeps U^(n) in the
+    imex_noalloc=True makes it the IMEX step that keeps U^(n+1/2) in the
     library's own array and allocates nothing (mgrhd_imex_step_noalloc).
     t_exp, t_ref, stim: temperature dependence of the opacity,
     (T/t_ref)^t_exp [1 - exp(-h nu / k T)]^stim.

@@ -31,7 +31,7 @@ def _step(w, noalloc, work=None):
 
 
 def test_noalloc_imex_step_matches_workspace_step():
-    cases = [W.config1(cells=np.arange(20000)),                  # 10.9 MB of U^(n)
+    cases = [W.config1(cells=np.arange(20000)),                  # 10.9 MB of U^(n+1/2)
              W.config2(cells=np.arange(3000), ng=24)]            # smaller, other group count
     for w in cases:
         need = mgrhd.imex_workspace_bytes(w.n, w.ng)
@@ -52,7 +52,7 @@ def test_noalloc_imex_step_matches_workspace_step():
 
 
 def test_noalloc_imex_step_rejects_oversize_input():
-    w = W.config1(cells=np.arange(130000))          # 35 MB of U^(n) > 32 MiB
+    w = W.config1(cells=np.arange(130000))          # 35 MB of U^(n+1/2) > 32 MiB
     assert mgrhd.imex_workspace_bytes(w.n, w.ng) > 8 * 4 * 1024 * 1024
     with pytest.raises(mgrhd.MgrhdError) as e:
         _step(w, True)
