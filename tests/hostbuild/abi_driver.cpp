@@ -76,6 +76,15 @@ int main() {
              MGRHD_E_OPTION, "max_newton");
   expect(mgrhd_source_update(f, f, f, f, f, 10, f, &op, -1.0, 1.0, nullptr, &o) ==
              MGRHD_E_SCALAR, "dt");
+  mgrhd_options outo = o;  // out of place: all four outputs or none
+  outo.E_g_out = f;
+  expect(mgrhd_source_update(f, f, f, f, f, 10, f, &op, 1.0, 1.0, nullptr, &outo) ==
+             MGRHD_E_NULL, "one output of four");
+  outo.F_g_out = outo.e_gas_out = outo.v_out = f;
+  expect(mgrhd_imex_step(f, f, f, f, f, 10, f, &op, 1.0, 1.0, nullptr, &outo, f, 1 << 20) ==
+             MGRHD_E_OPTION, "imex out of place");
+  expect(mgrhd_imex_step_noalloc(f, f, f, f, f, 10, f, &op, 1.0, 1.0, nullptr, &outo) ==
+             MGRHD_E_OPTION, "noalloc out of place");
   expect(mgrhd_imex_step(f, f, f, f, f, 10, f, &op, 1.0, 1.0, nullptr, &o, nullptr, 0) ==
              MGRHD_E_NULL, "imex workspace");
   expect(mgrhd_imex_step(f, f, f, f, f, 10, f, &op, 1.0, 1.0, nullptr, &o, f, 8) == MGRHD_E_SIZE,
@@ -93,6 +102,8 @@ int main() {
   expect(mgrhd_batch_create(nullptr, 3, 1, &o, &b) == MGRHD_E_NULL && b == nullptr, "batch null");
   expect(mgrhd_batch_set_item_scope(nullptr, 1) == MGRHD_E_NULL, "batch scope");
   expect(mgrhd_batch_tune(nullptr, nullptr) == MGRHD_E_NULL, "batch tune");
+  expect(mgrhd_batch_create(nullptr, 0, 1, &outo, &b) == MGRHD_E_OPTION && b == nullptr,
+         "batch out of place");
   mgrhd_mlp* m = nullptr;
   expect(mgrhd_mlp_create(0, 128, 5, 64, 1, &m) == MGRHD_E_SIZE && m == nullptr, "mlp dims");
   expect(mgrhd_mlp_create(10, 300, 5, 64, 1, &m) == MGRHD_E_SIZE, "mlp width");
