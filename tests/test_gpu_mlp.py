@@ -216,3 +216,76 @@ def test_parameters_save_and_load(tmp_path):
     with pytest.raises(mgrhd.MgrhdError) as e:
         b.load_params(tmp_path / "missing.bin")
     assert e.value.code == mgrhd.E_OPTION
+
+
+def _host_features(dw, x_mean, x_istd):
+    """The network's inputs written out on the host in FP64 from the state
+    (ln T, ln rho, per group ln(E_g / a T^4), |F_g|/(c E_g) and
+    ln(c_hat dt rho kappa chi_0,g) with the PPL-fixed group mean of eq. chiQg
+    at alpha_Q = -1, chi_0E,g / chi_0,g- = expm1(alpha L)/(alpha L)),
+    normalised with the same statistics.  Returns [2 + 3 N_g, n]."""
+    st = {k: v.cpu().numpy() for k, v in dw.state.items()}
+    ng, n = st["E_g"].shape
+    c = dw.consts()
+    rho, v = st["rho"], st["v"]
+    T = np.maximum((st["e_gas"] - 0.5 * rho * (v ** 2).sum(0)) / (rho * c["c_v"]), 1e-300)
+    aT4 = c["a_rad"] * T ** 4
+    kap = dw.kappa.cpu().numpy()
+    L = np.log(dw.edges[1:] / dw.edges[:-1])
+    aL = dw.alpha_chi * L
+    ratio = np.where(aL != 0.0, np.expm1(aL) / np.where(aL != 0.0, aL, 1.0), 1.0)
+    lchi = np.log(dw.chi_lo * ratio)
+    E = st["E_g"]
+    F = np.sqrt((st["F_g"] ** 2).sum(0))
+    pos = E > 0.0
+    with np.errstate(divide="ignore", invalid="ignore"):
+        le = np.where(pos, np.clip(np.log(E / aT4), -50.0, 50.0), -50.0)
+        fr = np.where(pos, np.minimum(F / (c["c"] * E), 2.0), 0.0)
+    lcell = np.log(c["c_hat"] * c["dt"] * rho * kap)
+    X = np.concatenate([np.log(T)[None], np.log(rho)[None], le, fr, lcell[None] + lchi[:, None]])
+    m = x_mean.cpu().numpy().astype(np.float64)[:, None]
+    s = x_istd.cpu().numpy().astype(np.float64)[:, None]
+    return (X - m) * s, T, rho, 0.5 * rho * (v ** 2).sum(0)
+
+
+def test_inference_against_host_reference():
+    """The features kernel, the three-kernel path and the fused inference
+    against a host reference: features from their definitions in FP64, the
+    network by the FP64 reference with BF16 operands (mlp_ref), the Newton
+    temperature guess from its output.  The GPU forms features in FP32 and
+    SiLU in FP32 before rounding to BF16; a value that lands on the other side
+    of a BF16 rounding boundary moves a product by 2^-8 of one term, so the
+    network output agrees to ~1e-3 of its scale, the guess (y_std = 0.05)
+    to ~1e-4 relative."""
+    n = 3000
+    dw = synth.device_workload("config2", n=n)
+    ng = dw.ng
+    net = warmstart.MLP(2 + 3 * ng, 1 + ng, 128, max_rows=4096, seed=7)
+    rng = np.random.default_rng(2)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+    Xr = warmstart.features(dw.state, dw.tables, dw.kappa, dw.consts(),
+                            torch.zeros(2 + 3 * ng, device="cuda"),
+                            torch.ones(2 + 3 * ng, device="cuda"))
+    x_mean = Xr.mean(1).contiguous()
+    x_istd = (1.0 / Xr.std(1).clamp_min(1e-3)).contiguous()
+    y_mean, y_std = t(rng.normal(0, 0.1, 1 + ng)), t(np.full(1 + ng, 0.05))
+    ws = warmstart.WarmStart(net, x_mean, x_istd, y_mean, y_std, [])
+    Xh, T, rho, ke = _host_features(dw, x_mean, x_istd)
+    # the features kernel (FP64 math, FP32 output)
+    Xg = warmstart.features(dw.state, dw.tables, dw.kappa, dw.consts(), x_mean, x_istd)
+    Xg = Xg.cpu().numpy().astype(np.float64)
+    assert np.abs(Xg - Xh).max() <= 1e-6 * (1.0 + np.abs(Xh).max()), np.abs(Xg - Xh).max()
+    # the network on the host, BF16 operands, FP64 sums
+    Ws, bs = net.unpack(net.get_params())
+    Ws = [w.astype(np.float64) for w in Ws]
+    bs = [b.astype(np.float64) for b in bs]
+    Y, _ = mlp_ref.forward(Ws, bs, Xh.T, mlp_ref.bf16_round)
+    yT = Y[:, 0] * float(y_std[0]) + float(y_mean[0])
+    g_ref = rho * dw.c_v * T * np.exp(np.clip(yT, -5.0, 5.0)) + ke
+    for fused in (True, False):
+        g = ws.guess(dw.state, dw.tables, dw.kappa, dw.consts(), kind=1, fused=fused)
+        torch.cuda.synchronize()
+        e = np.abs(g.cpu().numpy() - g_ref) / np.abs(g_ref)
+        print(f"fused={fused}: max rel guess error {e.max():.3e}, median {np.median(e):.3e}")
+        assert e.max() < 1e-3, (fused, e.max())
+        assert np.median(e) < 1e-5, (fused, np.median(e))
