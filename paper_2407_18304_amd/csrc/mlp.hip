@@ -454,8 +454,8 @@ __device__ __forceinline__ void infer_lchi(const PhysArgs& p, float* lchi) {
 // Every thread of the workgroup calls it (it synchronises); smem is the
 // dynamic LDS of k_infer, lchi that state's feature table.
 __device__ __forceinline__ void infer_tile(const InferArgs& q, const PhysArgs& p, double* guess,
-                                           const double* S, const float* lchi, int64_t i0,
-                                           int64_t i1, unsigned char* smem) {
+                                           const double* S, const float* lchi, const float* xs,
+                                           int64_t i0, int64_t i1, unsigned char* smem) {
   const int ng = p.ng;
   const int64_t n = p.n;
   const int ldx = q.K_pad[0] + 8;
@@ -464,28 +464,33 @@ __device__ __forceinline__ void infer_tile(const InferArgs& q, const PhysArgs& p
   const int r = threadIdx.x / 4, qd = threadIdx.x % 4;
   const int64_t i = i0 + r;
   const bool live = i < i1;
+  // the cell's temperature, density and kinetic energy, kept for the guess
+  double Tc = 1.0, rh = 1.0, ke = 0.0;
   // ---- features (normalised, bf16) ----
   {
-    float T = 1.f, rho = 1.f, lcell = 0.f, aT4 = 1.f;
+    float T = 1.f, rho = 1.f, lcell = 0.f;
+    double iaT4 = 1.0;  // 1/(a T^4)
     if (live) {
       const double v0 = p.v[i], v1 = p.v[n + i], v2 = p.v[2 * n + i];
-      const double rh = p.rho[i];
-      const double Td = fmax((p.egas[i] - 0.5 * rh * (v0 * v0 + v1 * v1 + v2 * v2)) / (rh * p.cv),
-                             1e-300);
+      rh = p.rho[i];
+      ke = 0.5 * rh * (v0 * v0 + v1 * v1 + v2 * v2);
+      Tc = fmax((p.egas[i] - ke) / (rh * p.cv), 1e-300);
       const double kap = p.kappa ? p.kappa[i] : 1.0;
-      T = (float)Td;
+      T = (float)Tc;
       rho = (float)rh;
-      aT4 = (float)(p.a * (Td * Td) * (Td * Td));
+      iaT4 = 1.0 / (p.a * (Tc * Tc) * (Tc * Tc));
       lcell = (float)log(p.chat * p.dt * rh * kap);
     }
     __bf16* xr = X + r * ldx;
-    auto put = [&](int f, float x) { xr[f] = (__bf16)((x - q.xmean[f]) * q.xistd[f]); };
+    // xs: the input statistics in LDS, mean [K_pad] then 1/std [K_pad]
+    auto put = [&](int f, float x) { xr[f] = (__bf16)((x - xs[f]) * xs[q.K_pad[0] + f]); };
     if (qd == 0) {
       put(0, live ? __logf(T) : 0.f);
       put(1, live ? __logf(rho) : 0.f);
     }
-    // four groups per chunk: their 16 loads are in flight together
-    constexpr int kU = 4;
+    // sixteen groups per chunk: their 64 loads are in flight together (all of
+    // a thread's loads at 64 groups)
+    constexpr int kU = 16;
     for (int g0 = qd; g0 < ng; g0 += 4 * kU) {
       double E[kU], f0[kU], f1[kU], f2[kU];
 #pragma unroll
@@ -505,7 +510,9 @@ __device__ __forceinline__ void infer_tile(const InferArgs& q, const PhysArgs& p
         if (g >= ng) break;
         float le = -50.f, fr = 0.f;
         if (E[u] > 0.0) {
-          le = fminf(fmaxf(__logf((float)(E[u] / (double)aT4)), -50.f), 50.f);
+          // E / (a T^4) rounded to FP32: beyond its range the logarithm is
+          // past the clamp at +-50 either way
+          le = fminf(fmaxf(__logf((float)(E[u] * iaT4)), -50.f), 50.f);
           fr = fminf((float)(sqrt(f0[u] * f0[u] + f1[u] * f1[u] + f2[u] * f2[u]) /
                              (p.c * E[u])), 2.f);
         }
@@ -532,10 +539,6 @@ __device__ __forceinline__ void infer_tile(const InferArgs& q, const PhysArgs& p
   __syncthreads();
   // ---- Newton guess ----
   if (live) {
-    const double v0 = p.v[i], v1 = p.v[n + i], v2 = p.v[2 * n + i];
-    const double rh = p.rho[i];
-    const double ke = 0.5 * rh * (v0 * v0 + v1 * v1 + v2 * v2);
-    const double Tc = fmax((p.egas[i] - ke) / (rh * p.cv), 1e-300);
     const float* o = out + r * ldo;
     if (qd == 0) {
       const double yT = (double)o[0] * q.ystd[0] + q.ymean[0];
@@ -555,24 +558,36 @@ __device__ __forceinline__ void infer_tile(const InferArgs& q, const PhysArgs& p
 }
 
 // LDS of the fused inference: the input tile (or a hidden tile), a hidden
-// tile, and the feature table of N_g floats.
+// tile, the feature table of N_g floats and the input statistics (2 K_pad
+// floats, after the table at a K_pad-float offset: N_g <= K_pad).
 __host__ __device__ inline size_t infer_lds_bytes(int k_pad0, int ng) {
   const int ldx = k_pad0 + 8;
+  (void)ng;
   return sizeof(__bf16) * (size_t)kTile * ((ldx > kHPad ? ldx : kHPad) + kHPad) +
-         sizeof(float) * (size_t)ng;
+         sizeof(float) * 3 * (size_t)k_pad0;
 }
 
-__global__ __launch_bounds__(256) void k_infer(InferArgs q) {
+// The input statistics into LDS (mean, then 1/std; zero beyond n_in).
+__device__ __forceinline__ void infer_stats(const InferArgs& q, float* xs) {
+  for (int f = threadIdx.x; f < q.K_pad[0]; f += blockDim.x) {
+    xs[f] = f < q.n_in ? q.xmean[f] : 0.f;
+    xs[q.K_pad[0] + f] = f < q.n_in ? q.xistd[f] : 0.f;
+  }
+}
+
+__global__ __launch_bounds__(256, 2) void k_infer(InferArgs q) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const PhysArgs& p = q.p;
   const int ldx = q.K_pad[0] + 8;
   float* lchi = (float*)(smem + sizeof(__bf16) * (size_t)kTile *
                                     ((ldx > kHPad ? ldx : kHPad) + kHPad));
+  float* xs = lchi + q.K_pad[0];
   infer_lchi(p, lchi);
+  infer_stats(q, xs);
   __syncthreads();
   const int64_t tiles = (p.n + kTile - 1) / kTile;
   for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x)
-    infer_tile(q, p, q.guess, q.S, lchi, tile * kTile, p.n, smem);
+    infer_tile(q, p, q.guess, q.S, lchi, xs, tile * kTile, p.n, smem);
 }
 
 // The fused inference over the work items [lo, hi) of a batch of patches
@@ -586,11 +601,13 @@ struct InferItemsArgs {
   int64_t lo, hi;
 };
 
-__global__ __launch_bounds__(256) void k_infer_items(InferItemsArgs a) {
+__global__ __launch_bounds__(256, 2) void k_infer_items(InferItemsArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int ldx = a.q.K_pad[0] + 8;
   float* lchi = (float*)(smem + sizeof(__bf16) * (size_t)kTile *
                                     ((ldx > kHPad ? ldx : kHPad) + kHPad));
+  float* xs = lchi + a.q.K_pad[0];
+  infer_stats(a.q, xs);  // (published by the first patch's barrier below)
   int cur = -1;
   for (int64_t it = a.lo + blockIdx.x; it < a.hi; it += gridDim.x) {
     const BatchItem item = a.items[it];
@@ -621,7 +638,7 @@ __global__ __launch_bounds__(256) void k_infer_items(InferItemsArgs a) {
     }
     double* guess = const_cast<double*>(k.guess);  // the batch's guess buffer
     for (int64_t i0 = item.c0; i0 < item.c1; i0 += kTile)
-      infer_tile(a.q, p, guess, k.S, lchi, i0, item.c1, smem);
+      infer_tile(a.q, p, guess, k.S, lchi, xs, i0, item.c1, smem);
   }
 }
 
