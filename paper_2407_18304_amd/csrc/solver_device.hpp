@@ -73,8 +73,9 @@ inline void set_derived(KArgs& a) {
 
 // The argument block of a launch where the device can read it with scalar
 // loads: the kernel-argument segment (single-table kernel) or the batch's
-// device array of patch arguments.  Only the state arrays are read through
-// it, where a finished cell is stored (see out_ptrs).
+// device array of patch arguments (never a copy in private memory).  The
+// arrays a cell needs once, at its load or its store, are read through it
+// (state_ptrs, arg_at_use).
 typedef const KArgs __attribute__((address_space(4)))* KArgsRef;
 
 // The state arrays of a launch, read from its argument block where a finished
