@@ -98,3 +98,17 @@ def test_out_of_place_argument_errors():
                                          tab["edges"].data_ptr(), C.byref(op), w.dt, w.c_hat,
                                          None, C.byref(o))
     assert rc == mgrhd.E_NULL
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_out_of_place_temperature_dependent_opacity(mode):
+    """The temperature-dependent kernels (the pulse test's opacity) out of
+    place: the same bits as in place, the inputs unchanged."""
+    w = W.config5(cells=np.arange(2500))
+    rng = np.random.default_rng(21 + mode)
+    bad = _with_invalid_cells(w, rng)
+    a = U.run_gpu(w, mode)
+    b = U.run_gpu(w, mode, out_of_place=True)
+    _same(a, b)
+    for k in U.FIELDS:
+        np.testing.assert_array_equal(b[0][k][..., bad], w.state[k][..., bad])
