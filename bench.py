@@ -128,6 +128,9 @@ def main():
     ap.add_argument("--variant", default="",
                     help="kernel variant override LPCxG[xW] (lanes per cell, groups per lane, "
                          "waves per SIMD), e.g. 16x4 or 16x4x3")
+    ap.add_argument("--replicate-cell", type=int, default=-1,
+                    help="analysis: every cell gets the state (and opacity scale) of this "
+                         "cell, so the cells of a wave never diverge (single-table workloads)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -163,6 +166,11 @@ def run_single(name, args, extra=False):
     n = (0 if extra else args.cells) or W.SPECS[name]["n"]
     dw = synth.device_workload(name, n=n)
     ng = dw.ng
+    if args.replicate_cell >= 0 and not extra:
+        c = args.replicate_cell
+        for k, t in dw.state.items():
+            t.copy_(t[..., c:c + 1].expand_as(t))
+        dw.kappa.fill_(float(dw.kappa[c]))
     if args.variant:
         mgrhd.set_variant(ng, *(int(x) for x in args.variant.split("x")))
     else:
@@ -304,7 +312,9 @@ def run_single(name, args, extra=False):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (seeded counter-based generator, drawn in HBM)",
-        "config": {"workload": WORKLOADS[name] + ", " + ["PC", "PPL-fixed", "PPL-free"][args.mode],
+        "config": {"workload": WORKLOADS[name] + ", " + ["PC", "PPL-fixed", "PPL-free"][args.mode] +
+                   (f", every cell holding cell {args.replicate_cell}'s state"
+                    if args.replicate_cell >= 0 and not extra else ""),
                    "cells": n, "n_groups": ng,
                    "mean_mode": ["PC", "PPL-fixed", "PPL-free"][args.mode],
                    "kernel_variant": "x".join(map(str, mgrhd.get_variant(ng, args.mode))),
