@@ -244,3 +244,34 @@ def test_parity_random_combinations():
         U.compare(w, U.run_gpu(w, mode, closure=closure), U.run_oracle(w, mode, closure=closure),
                   label=f"random case {case}: {name} N_g={w.ng} n={n} mode {mode} closure {closure}",
                   max_flips=0.1 if w.ng <= 2 else U.MAX_SCHEDULE_FLIPS)
+
+
+def test_parity_random_variants_in_and_out_of_place():
+    """Seeded random combinations as above, each run on a random compiled lane
+    split that covers its group count, in place or out of place, against the
+    oracle."""
+    rng = np.random.default_rng(18)
+    full = {"config0": 16 ** 3, "config1": 128 ** 3, "config2": 256 ** 3, "config5": 128 ** 3}
+    variants = mgrhd.variants()
+    for case in range(30):
+        name = str(rng.choice(list(full)))
+        # (N_g <= 2, where the outer stop test of up to a tenth of the cells
+        # is decided by the rounding of its single-group sum, is covered with
+        # its own allowance by the random combinations above)
+        ng = int(rng.choice([3, 4, 8, 13, 16, 32, 40, 64, 100, 128]))
+        n = int(rng.integers(1, 1200))
+        mode = int(rng.integers(0, 3))
+        oop = bool(rng.integers(0, 2))
+        cells = np.sort(rng.choice(full[name], n, replace=False))
+        w = (getattr(W, name)(cells=cells, ng=ng) if name in ("config1", "config2")
+             else getattr(W, name)(cells=cells))
+        fits = [v for v in variants if v[0] * v[1] >= w.ng]
+        lpc, gpl, wps = fits[int(rng.integers(0, len(fits)))]
+        try:
+            mgrhd.set_variant(w.ng, lpc, gpl, wps)
+            res = U.run_gpu(w, mode, out_of_place=oop)
+        finally:
+            mgrhd.set_variant(w.ng, 0, 0)
+        U.compare(w, res, U.run_oracle(w, mode),
+                  label=f"variant case {case}: {name} N_g={w.ng} n={n} mode {mode} "
+                        f"{lpc}x{gpl}x{wps} {'out of place' if oop else 'in place'}")
