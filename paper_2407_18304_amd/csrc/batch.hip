@@ -122,7 +122,7 @@ template <int G, int MODE, int NGM>
 __global__ __launch_bounds__(kBlock, 2) void k_batch(BatchArgs b) {
   static_assert(G * kWave >= NGM, "a wave holds the widest patch");
   __shared__ Tables<NGM> tabs[kBlock / kWave];
-  using LS = LaneStore<G, G == 2>;
+  using LS = LaneStore<G, G == 2, kBlock, true>;  // constants read where used
   __shared__ double lane_lds[LS::kSlots * kBlock];
   __shared__ double cell_lds[LS::kCellWords];
   const LS ls{lane_lds + threadIdx.x, cell_lds, nullptr};  // run_item sets the arguments
@@ -168,7 +168,7 @@ __global__ __launch_bounds__(kBlock, WPE) void k_batch_wg(BatchArgs b) {
   static_assert(G * kWave >= NGM, "a wave holds the widest patch");
   __shared__ Tables<NGM> tab;
   __shared__ int item_s, taken;
-  using LS = LaneStore<G, G == 2>;
+  using LS = LaneStore<G, G == 2, kBlock, true>;  // constants read where used
   __shared__ double lane_lds[LS::kSlots * kBlock];
   __shared__ double cell_lds[LS::kCellWords];
   const LS ls{lane_lds + threadIdx.x, cell_lds, nullptr};  // run_item sets the arguments

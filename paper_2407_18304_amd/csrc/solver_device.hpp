@@ -93,6 +93,11 @@ __device__ __forceinline__ StatePtrs state_ptrs(KArgsRef ap) {
 }
 
 // One field of the argument block, read where it is used (as state_ptrs).
+// The batched kernels read the constants of a Newton step or an outer stage
+// this way too (LaneStore::cst): a patch's arguments live in device memory,
+// and held across the loop they spilled hundreds of scalar registers (the
+// batched launch over 2000 patches: 631 -> 542 ms); in the single-table
+// kernel the scalar loads' waits cost more than its few spills (1%).
 template <class T>
 __device__ __forceinline__ T arg_at_use(KArgsRef ap, T KArgs::*m) {
   asm volatile("" : "+s"(ap));
@@ -308,7 +313,7 @@ __device__ __forceinline__ bool stage_tables(const KArgs& a, Tables<NGM>& t) {
 // cells[f * CPB + c], CPB the most cells a workgroup holds at once (kBlock /
 // lanes per cell, or kBlock where the lane count varies between waves); all
 // lanes of a cell read the same word (an LDS broadcast).
-template <int G, bool KEEP0, int CPB = kBlock>
+template <int G, bool KEEP0, int CPB = kBlock, bool CONST_AT_USE = false>
 struct LaneStore {
   static constexpr bool kKeep0 = KEEP0;
   static constexpr int kSlots = 5 * G + (KEEP0 ? 3 * G : 0);
@@ -322,6 +327,21 @@ struct LaneStore {
   }
   __device__ __forceinline__ LaneStore with_args(KArgsRef ap) const {
     return LaneStore{base, cells, ap};
+  }
+  // a field of the launch's arguments, read where it is used (arg_at_use)
+  template <class T>
+  __device__ __forceinline__ T arg(T KArgs::*m) const {
+    return arg_at_use(args, m);
+  }
+  // a constant of the launch (c/c_hat, the tolerances, ...): read where it is
+  // used with CONST_AT_USE (the batched kernels), else from a as the
+  // compiler likes (the single-table kernel, where it stays in registers)
+  template <class T>
+  __device__ __forceinline__ T cst(const KArgs& a, T KArgs::*m) const {
+    if constexpr (CONST_AT_USE)
+      return arg_at_use(args, m);
+    else
+      return a.*m;
   }
   __device__ __forceinline__ double& F(int d, int k) const { return base[(d * G + k) * kBlock]; }
   __device__ __forceinline__ double& itau(int k) const { return base[(3 * G + k) * kBlock]; }
@@ -612,22 +632,22 @@ __device__ __forceinline__ void load_cell(const KArgs& a, const Tables<NGM>& t, 
   s.polish_left = -1;
   s.fell_back = false;
   const StatePtrs sp = state_ptrs(ls.args);
-  s.rho = arg_at_use(ls.args, &KArgs::rho)[i];
+  s.rho = ls.arg(&KArgs::rho)[i];
   s.egas0 = sp.egas[i];
 #pragma unroll
   for (int d = 0; d < 3; ++d) s.v[d] = sp.v[(int64_t)d * n + i];
-  const double* kappa = arg_at_use(ls.args, &KArgs::kappa);
-  const double* S = arg_at_use(ls.args, &KArgs::S);
+  const double* kappa = ls.arg(&KArgs::kappa);
+  const double* S = ls.arg(&KArgs::S);
   const double kap = kappa ? kappa[i] : 1.0;
   bool ok = s.rho > 0.0 && isfinite(s.rho) && kap > 0.0 && isfinite(kap) && isfinite(s.egas0) &&
             isfinite(s.v[0]) && isfinite(s.v[1]) && isfinite(s.v[2]);
   s.rho_kappa = s.rho * kap;
-  s.ircv = 1.0 / (s.rho * a.cv);
+  s.ircv = 1.0 / (s.rho * ls.cst(a, &KArgs::cv));
   if (LS::kKeep0 && j == 0) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) ls.v0(d) = s.v[d];
   }
-  const double cdt = a.cdt;
+  const double cdt = ls.cst(a, &KArgs::cdt);
   double sumE = 0.0;
 #pragma unroll
   for (int k = 0; k < G; ++k) {
@@ -667,15 +687,15 @@ __device__ __forceinline__ void load_cell(const KArgs& a, const Tables<NGM>& t, 
   sumE = cell_sum<LPC>(sumE, s.lpc);
   const double bad = cell_sum<LPC>(ok ? 0.0 : 1.0, s.lpc);
   s.ke = 0.5 * s.rho * (s.v[0] * s.v[0] + s.v[1] * s.v[1] + s.v[2] * s.v[2]);
-  s.etot = s.egas0 + a.icc * sumE;  // E_tot of Sec. 3
+  s.etot = s.egas0 + ls.cst(a, &KArgs::icc) * sumE;  // E_tot of Sec. 3
   ok = bad == 0.0 && (s.egas0 - s.ke) > 0.0 && s.etot > 0.0;
-  const double* guess = arg_at_use(ls.args, &KArgs::guess);
+  const double* guess = ls.arg(&KArgs::guess);
   s.warm = guess != nullptr;
   s.elim = false;
   s.egv = s.egas0;
   if (ok && s.warm) {
     s.egv = guess[i];
-    if (a.guess_kind == 1) {
+    if (ls.cst(a, &KArgs::guess_kind) == 1) {
       s.elim = true;  // R_g from the group balances at the first evaluation
     } else {
 #pragma unroll
@@ -734,15 +754,16 @@ __device__ __forceinline__ void finish_cell(const KArgs& a, int j, CellState<G>&
     copy_through(a, state_ptrs(ls.args), i, j, s.lpc);
   }
   if (j == 0) {
-    int32_t* const status = arg_at_use(ls.args, &KArgs::status);
-    int32_t* const iters = arg_at_use(ls.args, &KArgs::iters);
-    int32_t* const outer = arg_at_use(ls.args, &KArgs::outer);
-    int32_t* const trace = arg_at_use(ls.args, &KArgs::trace);
+    int32_t* const status = ls.arg(&KArgs::status);
+    int32_t* const iters = ls.arg(&KArgs::iters);
+    int32_t* const outer = ls.arg(&KArgs::outer);
+    int32_t* const trace = ls.arg(&KArgs::trace);
     if (status) status[i] = s.st;
     if (iters) iters[i] = s.steps;
     if (outer) outer[i] = s.passes;
     if (trace)  // passes whose outer stage did not run (the last one's did if stored)
-      for (int k = store ? s.k_out + 1 : s.k_out; k < a.max_outer; ++k) trace[(int64_t)k * n + i] = -1;
+      for (int k = store ? s.k_out + 1 : s.k_out; k < ls.cst(a, &KArgs::max_outer); ++k)
+        trace[(int64_t)k * n + i] = -1;
   }
   s.phase = P_EMPTY;
 }
@@ -773,7 +794,7 @@ __device__ __forceinline__ void newton_done(const KArgs& a, int j, CellState<G>&
 #pragma unroll
   for (int k = 0; k < G; ++k) sumR += s.R[k];
   sumR = cell_sum<LPC>(sumR, s.lpc);
-  s.egv = s.egas0 - a.cc * sumR;  // E_gas^(t+1) of this pass
+  s.egv = s.egas0 - ls.cst(a, &KArgs::cc) * sumR;  // E_gas^(t+1) of this pass
   s.phase = P_FLUX;
 }
 
@@ -785,8 +806,8 @@ __device__ __forceinline__ void group_balance(const KArgs& a, const Tables<NGM>&
                                               CellState<G>& s, const LS& ls,
                                               const Cache<G>& c) {
   const int ng = group_count<G, LPC, FULL>(a);
-  const double cdt = a.cdt;
-  const double ic2 = a.ic2;
+  const double cdt = ls.cst(a, &KArgs::cdt);
+  const double ic2 = ls.cst(a, &KArgs::ic2);
 #pragma unroll
   for (int k = 0; k < G; ++k) {
     const int g = gidx<LPC>(j, k, s.lpc);
@@ -813,9 +834,9 @@ __device__ __forceinline__ void newton_step(const KArgs& a, const Tables<NGM>& t
                                             CellState<G>& s, const LS& ls,
                                             const Cache<G>& c) {
   const int ng = group_count<G, LPC, FULL>(a);
-  const double cc = a.cc;
-  const double cdt = a.cdt;
-  const double ic2 = a.ic2;
+  const double cc = ls.cst(a, &KArgs::cc);
+  const double cdt = ls.cst(a, &KArgs::cdt);
+  const double ic2 = ls.cst(a, &KArgs::ic2);
   const double ircv = s.ircv;
   double sumR = 0.0, sumAbs = 0.0, sumA = 0.0, sumB = 0.0;
   double ag[G], bg[G];
@@ -852,14 +873,14 @@ __device__ __forceinline__ void newton_step(const KArgs& a, const Tables<NGM>& t
   sumB = cell_sum<LPC>(sumB, s.lpc);
   const double FG = s.egv - s.egas0 + cc * sumR;
   // the stop test of Sec. 3, |F_G| / E_tot < eps and (c/c_hat) sum |F_R,g| / E_tot < eps
-  const double tol = a.eps * s.etot;
+  const double tol = ls.cst(a, &KArgs::eps) * s.etot;
   const bool conv = fabs(FG) < tol && cc * sumAbs < tol;
-  if (s.polish_left < 0 && conv) s.polish_left = a.polish;
+  if (s.polish_left < 0 && conv) s.polish_left = ls.cst(a, &KArgs::polish);
   if (s.polish_left == 0) {
     newton_done<G, LPC, FULL>(a, j, s, ls, 0);
     return;
   }
-  if (s.polish_left < 0 && s.steps >= a.max_newton) {
+  if (s.polish_left < 0 && s.steps >= ls.cst(a, &KArgs::max_newton)) {
     newton_done<G, LPC, FULL>(a, j, s, ls, 1);
     return;
   }
@@ -896,9 +917,9 @@ __device__ __forceinline__ bool flux_step(const KArgs& a, const Tables<NGM>& t, 
                                           const Cache<G>& c) {
   const int ng = group_count<G, LPC, FULL>(a);
   const int64_t n = a.n, i = s.i;
-  const double cdt = a.cdt;
+  const double cdt = ls.cst(a, &KArgs::cdt);
   if (j == 0) {
-    int32_t* const trace = arg_at_use(ls.args, &KArgs::trace);
+    int32_t* const trace = ls.arg(&KArgs::trace);
     if (trace) trace[(int64_t)s.k_out * n + i] = s.steps;
   }
   double dmom[3] = {0.0, 0.0, 0.0};
@@ -911,7 +932,8 @@ __device__ __forceinline__ bool flux_step(const KArgs& a, const Tables<NGM>& t, 
         (MODE == MGRHD_MEAN_PPL_FREE || TD) ? c.chiE[k] : s.rho_kappa * t.chk[g];
     const double ac = TD ? c.ac[k] : t.achi[g];
     double Pv[3];
-    pressure_dot_v(a.closure, a.c, Enew, ls.F(0, k), ls.F(1, k), ls.F(2, k), s.v, Pv);
+    pressure_dot_v(ls.cst(a, &KArgs::closure), ls.cst(a, &KArgs::c), Enew, ls.F(0, k), ls.F(1, k),
+                   ls.F(2, k), s.v, Pv);
     const double iden = rcp_nr(1.0 + cdt * c.chiF[k]);  // >= 1
     const double q = (1.0 + ac) * chE;
 #pragma unroll
@@ -922,8 +944,8 @@ __device__ __forceinline__ bool flux_step(const KArgs& a, const Tables<NGM>& t, 
       dmom[d] += f - f0;
     }
   }
-  const double ccc = a.iccc;
-  const double irho = s.ircv * a.cv;
+  const double ccc = ls.cst(a, &KArgs::iccc);
+  const double irho = s.ircv * ls.cst(a, &KArgs::cv);
   double vn[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
@@ -944,18 +966,18 @@ __device__ __forceinline__ bool flux_step(const KArgs& a, const Tables<NGM>& t, 
     dW += kw * fma(-0x1p-46, fabs(vf_new), fabs(vf_new - s.vF[k]));
     s.vF[k] = vf_new;
   }
-  dW = cell_sum<LPC>(dW, s.lpc) * a.cdt_ic2;
+  dW = cell_sum<LPC>(dW, s.lpc) * ls.cst(a, &KArgs::cdt_ic2);
   const double ke_new = 0.5 * s.rho * (vn[0] * vn[0] + vn[1] * vn[1] + vn[2] * vn[2]);
   const double egas_new = s.egv;
   s.egv = egas_new + (ke_new - s.ke);
   s.ke = ke_new;
 #pragma unroll
   for (int d = 0; d < 3; ++d) s.v[d] = vn[d];
-  if (dW < a.eps_out * s.etot) {
+  if (dW < ls.cst(a, &KArgs::eps_out) * s.etot) {
     finish_cell<G, LPC, FULL>(a, j, s, ls, true, egas_new);
     return false;
   }
-  if (s.k_out + 1 >= a.max_outer) {
+  if (s.k_out + 1 >= ls.cst(a, &KArgs::max_outer)) {
     s.st |= MGRHD_ST_OUTER_MAXIT;
     finish_cell<G, LPC, FULL>(a, j, s, ls, true, egas_new);
     return false;
@@ -1053,14 +1075,15 @@ __device__ __forceinline__ void run_cells(const KArgs& a, const Tables<NGM>& tab
     double Ecur[G];
 #pragma unroll
     for (int k = 0; k < G; ++k) Ecur[k] = s.E0[k] + s.R[k];
-    const double aT4 = a.a * (T * T) * (T * T);
+    const double aT4 = ls.cst(a, &KArgs::a) * (T * T) * (T * T);
     OpacityT ot{1.0, false};
     if (TD) {
-      ot.fT = a.t_exp != 0.0 ? exp(a.t_exp * log(T * a.itref)) : 1.0;
-      ot.stim = a.stim != 0;
+      const double t_exp = ls.cst(a, &KArgs::t_exp);
+      ot.fT = t_exp != 0.0 ? exp(t_exp * log(T * ls.cst(a, &KArgs::itref))) : 1.0;
+      ot.stim = ls.cst(a, &KArgs::stim) != 0;
     }
-    evaluate<G, LPC, MODE, NGM, TD>(tab, group_count<G, LPC, FULL>(a), j, s.lpc, T, aT4, a.hk,
-                                    s.rho_kappa, Ecur, c, ot);
+    evaluate<G, LPC, MODE, NGM, TD>(tab, group_count<G, LPC, FULL>(a), j, s.lpc, T, aT4,
+                                    ls.cst(a, &KArgs::hk), s.rho_kappa, Ecur, c, ot);
 
     if (s.phase == P_FLUX) {
       if (!flux_step<G, LPC, MODE, NGM, TD, FULL>(a, tab, j, s, ls, c)) continue;
