@@ -622,7 +622,7 @@ __device__ __forceinline__ void load_cell(const KArgs& a, const Tables<NGM>& t, 
                                           CellState<G>& s, const LS& ls) {
   // 1/tau_g and 1/J_gg are constants of the cell unless the means depend on T
   constexpr bool kFixedTau = MODE != MGRHD_MEAN_PPL_FREE && !TD;
-  const int64_t n = ls.cst(a, &KArgs::n);
+  const int64_t n = ls.arg(&KArgs::n);
   const int ng = group_count<G, LPC, FULL>(a);
   s.i = i;
   s.st = MGRHD_ST_OK;
@@ -716,7 +716,7 @@ __device__ __forceinline__ void load_cell(const KArgs& a, const Tables<NGM>& t, 
 template <int G, int LPC, bool FULL = false, class LS>
 __device__ __forceinline__ void finish_cell(const KArgs& a, int j, CellState<G>& s,
                                             const LS& ls, bool store, double egas_new = 0.0) {
-  const int64_t n = ls.cst(a, &KArgs::n), i = s.i;
+  const int64_t n = ls.arg(&KArgs::n), i = s.i;
   const int ng = group_count<G, LPC, FULL>(a);
   if (store) {
     double bad = (isfinite(egas_new) && isfinite(s.v[0]) && isfinite(s.v[1]) && isfinite(s.v[2]))
@@ -916,7 +916,7 @@ __device__ __forceinline__ bool flux_step(const KArgs& a, const Tables<NGM>& t, 
                                           CellState<G>& s, const LS& ls,
                                           const Cache<G>& c) {
   const int ng = group_count<G, LPC, FULL>(a);
-  const int64_t n = ls.cst(a, &KArgs::n), i = s.i;
+  const int64_t n = ls.arg(&KArgs::n), i = s.i;
   const double cdt = ls.cst(a, &KArgs::cdt);
   if (j == 0) {
     int32_t* const trace = ls.arg(&KArgs::trace);
