@@ -154,18 +154,51 @@ def field_errors(w, gpu, ora, mask=None):
     out = {}
     for k in FIELDS:
         a, b = gpu[k], ora[k]
-        if k in ("E_g", "e_gas"):
-            err = (np.abs(a - b) / np.maximum(np.abs(b), 1e-16 * etot)).reshape(-1, w.n)
-        elif k == "F_g":
-            nrm = np.sqrt((b * b).sum(0))                        # [N_g, n]
-            fl = 1e-16 * pscale * w.c * w.c_hat
-            err = np.abs(a - b).max(0) / np.maximum(nrm, fl)
-        else:
-            nrm = np.sqrt((b * b).sum(0))
-            err = (np.abs(a - b).max(0) / np.maximum(nrm, 1e-16 * pscale / st["rho"]))[None]
+        with np.errstate(invalid="ignore"):   # inf or NaN inputs of untouched cells, masked below
+            if k in ("E_g", "e_gas"):
+                err = (np.abs(a - b) / np.maximum(np.abs(b), 1e-16 * etot)).reshape(-1, w.n)
+            elif k == "F_g":
+                nrm = np.sqrt((b * b).sum(0))                        # [N_g, n]
+                fl = 1e-16 * pscale * w.c * w.c_hat
+                err = np.abs(a - b).max(0) / np.maximum(nrm, fl)
+            else:
+                nrm = np.sqrt((b * b).sum(0))
+                err = (np.abs(a - b).max(0) / np.maximum(nrm, 1e-16 * pscale / st["rho"]))[None]
         if mask is not None:
             err = err[:, mask]
         out[k] = float(err.max()) if err.size else 0.0
+    return out
+
+
+def unfloored_errors(w, gpu, ora, mask=None, tol=TOL):
+    """Per field: the same relative errors without the floors (elements whose
+    reference is exactly 0 left out), and the number of cells where only the
+    floor keeps the error within tol (reported beside the floored metric)."""
+    st = w.state
+    cc = w.c / w.c_hat
+    etot = st["e_gas"] + (1.0 / cc) * st["E_g"].sum(0)
+    pscale = np.abs(st["rho"] * st["v"]).sum(0) + np.abs(st["F_g"]).sum((0, 1)) / (w.c * w.c_hat)
+    out = {}
+    for k in FIELDS:
+        a, b = gpu[k], ora[k]
+        with np.errstate(invalid="ignore"):
+            d = np.abs(a - b)
+        if k in ("E_g", "e_gas"):
+            den = np.abs(b).reshape(-1, w.n)
+            d = d.reshape(-1, w.n)
+            fl = np.broadcast_to(1e-16 * etot, den.shape)
+        else:
+            den = np.sqrt((b * b).sum(0)).reshape(-1, w.n)
+            d = d.max(0).reshape(-1, w.n)
+            scale = pscale * w.c * w.c_hat if k == "F_g" else pscale / st["rho"]
+            fl = np.broadcast_to(1e-16 * scale, den.shape)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            raw = np.where(den > 0, d / den, 0.0)
+            floored = d / np.maximum(den, fl)
+        only_floor = ((raw > tol) & (floored <= tol)).any(0)
+        if mask is not None:
+            raw, only_floor = raw[:, mask], only_floor[mask]
+        out[k] = (float(raw.max()) if raw.size else 0.0, int(only_floor.sum()))
     return out
 
 
@@ -208,6 +241,7 @@ def compare(w, gpu, ref, label="", tol=TOL, max_flips=MAX_SCHEDULE_FLIPS):
     same = cmp_ & (gpu.trace == ref.trace).all(0)
     flip = cmp_ & ~same
     err = field_errors(w, g, o, same)
+    raw = unfloored_errors(w, g, o, same, tol)
     idx = np.nonzero(flip)[0]
     err_flip = {}
     if idx.size:
@@ -220,7 +254,8 @@ def compare(w, gpu, ref, label="", tol=TOL, max_flips=MAX_SCHEDULE_FLIPS):
     print(f"{label}: n={n} N_g={w.ng} compared {cmp_.sum()} status {np.unique(gs, return_counts=True)}"
           f" cap flips {cap_only.sum()} same schedule {same.sum()} errors {err} "
           f"schedule flips {flip.sum()} (outer count {(cmp_ & (go != oo)).sum()}) "
-          f"replayed {err_flip} not converged {capped.sum()} {err_cap}", flush=True)
+          f"replayed {err_flip} not converged {capped.sum()} {err_cap} "
+          f"unfloored (max, cells within tol by the floor only) {raw}", flush=True)
     for k, e in err.items():
         assert e < tol, (label, k, e)
     for k, e in err_cap.items():
