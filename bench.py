@@ -719,6 +719,7 @@ def cpu_baseline(dw, mode, target_s):
         dt = time.perf_counter() - t0
         m = m2
     return {"value": m / dt, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
+            "value_per_core": m / dt / cores,
             "sample": f"{m} random cells of the same workload, {dt:.1f} s on {cores} threads",
             "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
 
