@@ -26,7 +26,9 @@
  * Memory: all arrays are DEVICE pointers owned by the caller, FP64, structure
  * of arrays with the cell index fastest:
  *   E_g[g*n + i], F_g[(d*N_g + g)*n + i], v[d*n + i], rho[i], e_gas[i].
- * The state is updated in place.  Nothing is allocated by mgrhd_source_update.
+ * The state is updated in place, or written to separate output arrays of the
+ * same layout (mgrhd_options.E_g_out ... v_out) while the inputs are only
+ * read.  Nothing is allocated by mgrhd_source_update.
  * Calls are asynchronous on `stream`; results and per-cell status are valid
  * after the caller synchronises the stream.
  *
