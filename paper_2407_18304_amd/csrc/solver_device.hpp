@@ -106,23 +106,23 @@ __device__ __forceinline__ T arg_at_use(KArgsRef ap, T KArgs::*m) {
 
 // Out of place: the input state of cell i copied to the outputs, for a cell
 // the update leaves untouched (lane j of the cell's lpc lanes copies rows
-// j, j + lpc, ...).
+// j, j + lpc, ...).  Each array is copied unless its output is the input
+// itself (an update may be in place for some arrays and not for others).
 __device__ __forceinline__ void copy_through(const KArgs& a, const StatePtrs& p, int64_t i,
                                              int j, int lpc) {
-  if (p.Eo == p.E) return;
   const int64_t n = a.n;
   const int ng = a.ng;
   for (int r = j; r < 4 * ng + 4; r += lpc) {
     if (r < ng) {
-      p.Eo[(int64_t)r * n + i] = p.E[(int64_t)r * n + i];
+      if (p.Eo != p.E) p.Eo[(int64_t)r * n + i] = p.E[(int64_t)r * n + i];
     } else if (r < 4 * ng) {
       const int64_t q = (int64_t)(r - ng) * n + i;
-      p.Fo[q] = p.F[q];
+      if (p.Fo != p.F) p.Fo[q] = p.F[q];
     } else if (r == 4 * ng) {
-      p.egaso[i] = p.egas[i];
+      if (p.egaso != p.egas) p.egaso[i] = p.egas[i];
     } else {
       const int64_t q = (int64_t)(r - 4 * ng - 1) * n + i;
-      p.vo[q] = p.v[q];
+      if (p.vo != p.v) p.vo[q] = p.v[q];
     }
   }
 }

@@ -112,3 +112,26 @@ def test_out_of_place_temperature_dependent_opacity(mode):
     _same(a, b)
     for k in U.FIELDS:
         np.testing.assert_array_equal(b[0][k][..., bad], w.state[k][..., bad])
+
+
+@pytest.mark.parametrize("separate", [("F_g", "e_gas", "v"), ("E_g", "e_gas"), ("v",)])
+def test_partly_in_place(separate):
+    """Some arrays updated in place (output = input), the others into
+    separate outputs: the same bits as fully in place, the separate inputs
+    unchanged, and the untouched cells (invalid inputs, a rejected table)
+    copied through into every separate output."""
+    rng = np.random.default_rng(31)
+    for mode in (0, 1):
+        w = W.config1(cells=rng.choice(2 ** 21, 2500))
+        bad = _with_invalid_cells(w, rng)
+        a = U.run_gpu(w, mode)
+        b = U.run_gpu(w, mode, out_of_place=separate)
+        _same(a, b)
+        for k in U.FIELDS:
+            np.testing.assert_array_equal(b[0][k][..., bad], w.state[k][..., bad])
+    w = W.config0(cells=np.arange(300))
+    w.edges = w.edges[::-1].copy()          # descending: rejected on the device
+    g, gi, go, gs = U.run_gpu(w, 1, out_of_place=separate)
+    assert (gs == mgrhd.ST_BAD_TABLE).all()
+    for k in U.FIELDS:
+        assert np.array_equal(g[k], w.state[k])
