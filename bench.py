@@ -8,8 +8,9 @@ place (mgrhd_options.E_g_out ...): every step reads the same inputs, left
 unchanged, and writes the updated state to separate arrays, as a time step
 from U^(n) to U^(n+1) does, so every step solves the same input
 distribution with nothing but the update in the timed region.  The batched
-patches update in place; there the pristine inputs are copied back before
-every step (a device copy, inside the timed region).
+patches update in place; their inputs are drawn again in HBM by the device
+generator before every step, outside the timed region (HIP events bracket
+each graph launch).
 
 Prints one JSON line (see the repository's benchmark contract)."""
 from __future__ import annotations
