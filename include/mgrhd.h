@@ -234,7 +234,7 @@ int mgrhd_imex_step(double* E_g, double* F_g, const double* rho, double* e_gas, 
  * an array owned by the library, MGRHD_IMEX_SCRATCH_DOUBLES doubles (32 MiB) per
  * GPU, held from the first call on that GPU until the process ends; the call
  * allocates nothing.  Limit: mgrhd_imex_workspace_bytes(n_cells, n_groups)
- * <= 32 MiB (e.g. 123 361 cells at 16 groups, 31 775 at 64), else
+ * <= 32 MiB (at most 61 680 cells at 16 groups, 16 131 at 64), else
  * MGRHD_E_SIZE with nothing enqueued.  Every call on one GPU shares that
  * array: calls that overlap on one GPU (other streams or threads) race and
  * must be serialised by the caller.  Returns as mgrhd_imex_step, or a HIP

@@ -52,8 +52,28 @@ def test_noalloc_imex_step_matches_workspace_step():
 
 
 def test_noalloc_imex_step_rejects_oversize_input():
-    w = W.config1(cells=np.arange(130000))          # 35 MB of U^(n+1/2) > 32 MiB
+    w = W.config1(cells=np.arange(130000))          # 71 MB of U^(n+1/2) > 32 MiB
     assert mgrhd.imex_workspace_bytes(w.n, w.ng) > 8 * 4 * 1024 * 1024
     with pytest.raises(mgrhd.MgrhdError) as e:
         _step(w, True)
     assert e.value.code == mgrhd.E_SIZE
+
+
+def test_noalloc_imex_step_at_its_limit():
+    """61 680 cells of 16 groups (4 N_g + 4 = 68 doubles each) fill the
+    32 MiB array; one more cell is refused with nothing enqueued."""
+    limit = 4 * 1024 * 1024 // 68
+    w = W.config1(cells=np.arange(limit + 1))
+    assert mgrhd.imex_workspace_bytes(w.n, w.ng) > 8 * 4 * 1024 * 1024
+    with pytest.raises(mgrhd.MgrhdError) as e:
+        _step(w, True)
+    assert e.value.code == mgrhd.E_SIZE
+    w = W.config1(cells=np.arange(limit))
+    assert mgrhd.imex_workspace_bytes(w.n, w.ng) <= 8 * 4 * 1024 * 1024
+    work = torch.empty(mgrhd.imex_workspace_bytes(w.n, w.ng) // 8, dtype=torch.float64,
+                       device="cuda")
+    ref, it_r, st_r = _step(w, False, work)
+    got, it_g, st_g = _step(w, True)
+    assert np.array_equal(st_g, st_r) and np.array_equal(it_g, it_r)
+    for k in U.FIELDS:
+        assert np.array_equal(got[k], ref[k]), k
