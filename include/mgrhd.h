@@ -144,13 +144,13 @@ typedef struct {
                                      -1 for every pass that did not.  A record of
                                      where the stop tests ended each pass (a
                                      checker can replay it)                      */
-  /* Out-of-place update (mgrhd_source_update only): with all four set, the
-   * updated E_g, F_g, e_gas, v are written here (same layouts) and the input
-   * arrays are only read; a cell left untouched (invalid input, a table
-   * error, non-finite results) gets its input values copied.  All four NULL:
-   * the update is in place.  An output must be its input array or not
-   * overlap any argument.  The IMEX steps and the batch return
-   * MGRHD_E_OPTION when any is set. */
+  /* Out-of-place update (mgrhd_source_update and the IMEX steps): with all
+   * four set, the updated E_g, F_g, e_gas, v are written here (same layouts)
+   * and the input arrays are only read; a cell left untouched (invalid
+   * input, a table error, non-finite results) gets its input values copied.
+   * All four NULL: the update is in place.  An output must be its input
+   * array or not overlap any argument.  The batch returns MGRHD_E_OPTION
+   * when any is set. */
   double* E_g_out;                /* [N_g][n]    */
   double* F_g_out;                /* [3][N_g][n] */
   double* e_gas_out;              /* [n]         */
@@ -214,11 +214,13 @@ int mgrhd_variant_info(int32_t k, int32_t* lanes_per_cell, int32_t* groups_per_l
  * With no transport term, one step of the paper's IMEX integrator is
  *   U^(n+1/2) = U^(n) + dt S(U^(n+1/2))            (source update, theta dt = dt)
  *   U^(n+1)   = (U^(n) + U^(n+1/2))/2 + (dt/2) S(U^(n+1))   (theta dt = dt/2).
- * mgrhd_imex_step performs both stages in place on the state of
- * mgrhd_source_update (same arguments and layout), the first stage writing
- * U^(n+1/2) into the caller's DEVICE workspace `work` of at least
- * mgrhd_imex_workspace_bytes() bytes (8 n (4 N_g + 4)), out of place, so
- * that U^(n) is never copied; nothing is allocated.  opt->iters/outer/status
+ * mgrhd_imex_step performs both stages on the state of mgrhd_source_update
+ * (same arguments and layout), in place, or with opt's *_out arrays set from
+ * U^(n) into those (U^(n) only read).  The first stage writes U^(n+1/2)
+ * into the caller's DEVICE workspace `work` of at least
+ * mgrhd_imex_workspace_bytes() bytes (8 n (4 N_g + 4)), so that U^(n) is
+ * never copied; the midpoint is formed where U^(n+1) goes and the second
+ * stage updates it there; nothing is allocated.  opt->iters/outer/status
  * report the second stage.  Returns as mgrhd_source_update; MGRHD_E_SIZE if
  * the workspace is too small. */
 size_t mgrhd_imex_workspace_bytes(int64_t n_cells, int32_t n_groups);

@@ -43,29 +43,34 @@ void* scratch_ptr(hipError_t* err) {
   return g_scratch[dev];
 }
 
-// x <- (x + y) / 2 over four arrays laid end to end in the workspace order
-__global__ void k_midpoint(double* __restrict__ E, double* __restrict__ F,
-                           double* __restrict__ eg, double* __restrict__ v,
-                           const double* __restrict__ w, int64_t nE, int64_t n) {
+// The four state arrays of one side of the midpoint.
+struct State4 {
+  double *E, *F, *eg, *v;
+};
+
+// y <- (x + w) / 2 over the four arrays, w laid end to end in the workspace
+// order (E_g, F_g, e_gas, v); y may be x (in place)
+__global__ void k_midpoint(State4 y, State4 x, const double* __restrict__ w, int64_t nE,
+                           int64_t n) {
   const int64_t total = 4 * nE + 4 * n;
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
        k += (int64_t)gridDim.x * blockDim.x) {
-    double* x;
+    double *dst, *src;
     int64_t o;
     if (k < nE) {
-      x = E;
+      dst = y.E, src = x.E;
       o = k;
     } else if (k < 4 * nE) {
-      x = F;
+      dst = y.F, src = x.F;
       o = k - nE;
     } else if (k < 4 * nE + n) {
-      x = eg;
+      dst = y.eg, src = x.eg;
       o = k - 4 * nE;
     } else {
-      x = v;
+      dst = y.v, src = x.v;
       o = k - 4 * nE - n;
     }
-    x[o] = 0.5 * (x[o] + w[k]);
+    dst[o] = 0.5 * (src[o] + w[k]);
   }
 }
 
@@ -86,8 +91,8 @@ int mgrhd_imex_step_noalloc(double* E_g, double* F_g, const double* rho, double*
   if (!opacity) return MGRHD_E_NULL;
   if (n_cells < 0 || opacity->n_groups < 1 || opacity->n_groups > MGRHD_MAX_GROUPS)
     return MGRHD_E_SIZE;
-  if (opt && (opt->E_g_out || opt->F_g_out || opt->e_gas_out || opt->v_out))
-    return MGRHD_E_OPTION;  // the IMEX step works in place
+  const int n_out = opt ? !!opt->E_g_out + !!opt->F_g_out + !!opt->e_gas_out + !!opt->v_out : 0;
+  if (n_out != 0 && n_out != 4) return MGRHD_E_NULL;  // out of place needs all four
   const size_t need = mgrhd_imex_workspace_bytes(n_cells, opacity->n_groups);
   if (need > sizeof(double) * (size_t)MGRHD_IMEX_SCRATCH_DOUBLES) return MGRHD_E_SIZE;
   hipError_t err = hipSuccess;
@@ -105,8 +110,8 @@ int mgrhd_imex_step(double* E_g, double* F_g, const double* rho, double* e_gas, 
   if (!opacity || !work) return MGRHD_E_NULL;
   if (n_cells < 0 || opacity->n_groups < 1 || opacity->n_groups > MGRHD_MAX_GROUPS)
     return MGRHD_E_SIZE;
-  if (opt && (opt->E_g_out || opt->F_g_out || opt->e_gas_out || opt->v_out))
-    return MGRHD_E_OPTION;  // the IMEX step works in place
+  const int n_out = opt ? !!opt->E_g_out + !!opt->F_g_out + !!opt->e_gas_out + !!opt->v_out : 0;
+  if (n_out != 0 && n_out != 4) return MGRHD_E_NULL;  // out of place needs all four
   if (work_bytes < mgrhd_imex_workspace_bytes(n_cells, opacity->n_groups)) return MGRHD_E_SIZE;
   if (!(dt > 0.0)) return MGRHD_E_SCALAR;
   if (n_cells == 0) return 0;
@@ -114,13 +119,17 @@ int mgrhd_imex_step(double* E_g, double* F_g, const double* rho, double* e_gas, 
   hipStream_t s = (hipStream_t)stream;
   const int64_t n = n_cells, nE = n * opacity->n_groups;
   double* w = (double*)work;
-  // first stage, out of place: U^(n+1/2) = U^(n) + dt S(U^(n+1/2)) into the
-  // workspace (E_g, F_g, e_gas, v end to end), U^(n) left in the caller's arrays
   mgrhd_options o1;
   if (opt)
     o1 = *opt;
   else
     mgrhd_default_options(&o1);
+  // where U^(n+1) goes: the caller's arrays (in place) or the outputs
+  const mgrhd::imex::State4 un{E_g, F_g, e_gas, v};
+  const mgrhd::imex::State4 un1 =
+      n_out ? mgrhd::imex::State4{o1.E_g_out, o1.F_g_out, o1.e_gas_out, o1.v_out} : un;
+  // first stage, out of place: U^(n+1/2) = U^(n) + dt S(U^(n+1/2)) into the
+  // workspace (E_g, F_g, e_gas, v end to end), U^(n) left in the caller's arrays
   o1.E_g_out = w;
   o1.F_g_out = w + nE;
   o1.e_gas_out = w + 4 * nE;
@@ -128,16 +137,18 @@ int mgrhd_imex_step(double* E_g, double* F_g, const double* rho, double* e_gas, 
   int rc = mgrhd_source_update(E_g, F_g, rho, e_gas, v, n, group_edges, opacity, dt, c_hat,
                                stream, &o1);
   if (rc) return rc;
-  // second stage from the midpoint (U^(n) + U^(n+1/2))/2, formed in the
-  // caller's arrays, with theta dt = dt / 2, in place
+  // second stage from the midpoint (U^(n) + U^(n+1/2))/2, formed where
+  // U^(n+1) goes, with theta dt = dt / 2, in place there
   int64_t blocks = (4 * nE + 4 * n + 255) / 256;
   if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(mgrhd::imex::k_midpoint, dim3((unsigned)blocks), dim3(256), 0, s, E_g, F_g,
-                     e_gas, v, (const double*)w, nE, n);
+  hipLaunchKernelGGL(mgrhd::imex::k_midpoint, dim3((unsigned)blocks), dim3(256), 0, s, un1, un,
+                     (const double*)w, nE, n);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return (int)e;
-  return mgrhd_source_update(E_g, F_g, rho, e_gas, v, n, group_edges, opacity, 0.5 * dt, c_hat,
-                             stream, opt);
+  mgrhd_options o2 = o1;
+  o2.E_g_out = o2.F_g_out = o2.e_gas_out = o2.v_out = nullptr;
+  return mgrhd_source_update(un1.E, un1.F, rho, un1.eg, un1.v, n, group_edges, opacity,
+                             0.5 * dt, c_hat, stream, &o2);
 }
 
 }  // extern "C"

@@ -172,17 +172,19 @@ def test_transport_and_batch_host_checks(lib):
 
 
 def test_out_of_place_options_checked_on_the_host(lib):
-    """The four output arrays of an out-of-place update go together, and only
-    mgrhd_source_update takes them (the pointers are never dereferenced)."""
+    """The four output arrays of an out-of-place update go together (the
+    source update and both IMEX steps reject one without the others before
+    anything is enqueued), and the batch takes none of them (the pointers are
+    never dereferenced)."""
     fake = C.c_void_p(64)
     op = mgrhd.OpacityParams(4, 1, fake, fake, None, None)
     o = mgrhd.default_options()
     o.E_g_out = 64                       # one of the four
     args = (fake, fake, fake, fake, fake, 10, fake, C.byref(op), 1.0, 1.0, None, C.byref(o))
     assert lib.mgrhd_source_update(*args) == mgrhd.E_NULL
+    assert lib.mgrhd_imex_step(*args, fake, 1 << 30) == mgrhd.E_NULL
+    assert lib.mgrhd_imex_step_noalloc(*args) == mgrhd.E_NULL
     o.F_g_out = o.e_gas_out = o.v_out = 64
-    assert lib.mgrhd_imex_step(*args, fake, 1 << 30) == mgrhd.E_OPTION
-    assert lib.mgrhd_imex_step_noalloc(*args) == mgrhd.E_OPTION
     L = C.CDLL(mgrhd.LIB_PATH)   # own function objects: the binding's argtypes stay as they are
     L.mgrhd_batch_create.restype = C.c_int
     L.mgrhd_batch_create.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]

@@ -76,18 +76,7 @@ def test_out_of_place_argument_errors():
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     st = {k: t(w.state[k]) for k in ("E_g", "F_g", "rho", "e_gas", "v")}
     tab = U.device_tables(w)
-    kw = dict(mean_mode=1, alpha_chi=tab["alpha"], kappa_scale=tab["kappa"], dt=w.dt,
-              c_hat=w.c_hat, c=w.c, a_rad=w.a_rad)
     outs = [torch.empty_like(st[k]) for k in U.FIELDS]
-    args = (st["E_g"], st["F_g"], st["rho"], st["e_gas"], st["v"], tab["edges"], tab["chi_lo"])
-    # the IMEX steps work in place only
-    work = torch.empty(mgrhd.imex_workspace_bytes(w.n, w.ng), dtype=torch.uint8, device="cuda")
-    with pytest.raises(mgrhd.MgrhdError) as e:
-        mgrhd.source_update(*args, **kw, imex_work=work, out=tuple(outs))
-    assert e.value.code == mgrhd.E_OPTION
-    with pytest.raises(mgrhd.MgrhdError) as e:
-        mgrhd.source_update(*args, **kw, imex_noalloc=True, out=tuple(outs))
-    assert e.value.code == mgrhd.E_OPTION
     # all four outputs or none
     o = mgrhd.default_options()
     o.E_g_out = outs[0].data_ptr()
@@ -135,3 +124,45 @@ def test_partly_in_place(separate):
     assert (gs == mgrhd.ST_BAD_TABLE).all()
     for k in U.FIELDS:
         assert np.array_equal(g[k], w.state[k])
+
+
+def _imex(w, *, noalloc, out_of_place):
+    """One IMEX step (workspace or no-allocation form) of workload w; with
+    out_of_place, into NaN-filled outputs, checking the inputs are unchanged."""
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float64)).cuda()
+    st = {k: t(w.state[k]) for k in ("E_g", "F_g", "rho", "e_gas", "v")}
+    outs = {k: torch.full_like(st[k], float("nan")) for k in U.FIELDS} if out_of_place else None
+    status = torch.full((w.n,), -1, dtype=torch.int32, device="cuda")
+    iters = torch.zeros(w.n, dtype=torch.int32, device="cuda")
+    tab = U.device_tables(w)
+    work = None if noalloc else torch.empty(mgrhd.imex_workspace_bytes(w.n, w.ng) // 8,
+                                            dtype=torch.float64, device="cuda")
+    mgrhd.source_update(st["E_g"], st["F_g"], st["rho"], st["e_gas"], st["v"], tab["edges"],
+                        tab["chi_lo"], alpha_chi=tab["alpha"], kappa_scale=tab["kappa"],
+                        mean_mode=1, polish=1, dt=w.dt, c_hat=w.c_hat, c=w.c, a_rad=w.a_rad,
+                        status=status, iters=iters, imex_work=work, imex_noalloc=noalloc,
+                        out=None if outs is None else tuple(outs[k] for k in U.FIELDS))
+    torch.cuda.synchronize()
+    res = {k: st[k].cpu().numpy() for k in U.FIELDS}
+    if outs is not None:
+        for k in U.FIELDS:
+            assert np.array_equal(res[k], w.state[k], equal_nan=True), f"input {k} modified"
+            res[k] = outs[k].cpu().numpy()
+    return res, iters.cpu().numpy(), status.cpu().numpy()
+
+
+@pytest.mark.parametrize("noalloc", [False, True])
+def test_imex_step_out_of_place(noalloc):
+    """The IMEX step from U^(n) into separate outputs: the same bits as the
+    step in place, U^(n) unchanged, untouched cells copied through."""
+    rng = np.random.default_rng(41)
+    w = W.config1(cells=rng.choice(2 ** 21, 4000))
+    bad = _with_invalid_cells(w, rng)
+    a, ia, sa = _imex(w, noalloc=noalloc, out_of_place=False)
+    b, ib, sb = _imex(w, noalloc=noalloc, out_of_place=True)
+    assert np.array_equal(sa, sb) and np.array_equal(ia, ib)
+    assert (sb[bad] & mgrhd.ST_INVALID).all()
+    for k in U.FIELDS:
+        assert np.array_equal(a[k], b[k], equal_nan=True), k
+        np.testing.assert_array_equal(b[k][..., bad], w.state[k][..., bad])
+    assert (np.abs(b["E_g"] - w.state["E_g"]) > 0).any()        # the step did something
