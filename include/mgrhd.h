@@ -149,8 +149,8 @@ typedef struct {
    * and the input arrays are only read; a cell left untouched (invalid
    * input, a table error, non-finite results) gets its input values copied.
    * All four NULL: the update is in place.  An output must be its input
-   * array or not overlap any argument.  The batch returns MGRHD_E_OPTION
-   * when any is set. */
+   * array or not overlap any argument.  The batch takes them per patch
+   * (mgrhd_patch) and returns MGRHD_E_OPTION when any is set here. */
   double* E_g_out;                /* [N_g][n]    */
   double* F_g_out;                /* [3][N_g][n] */
   double* e_gas_out;              /* [n]         */
@@ -315,6 +315,12 @@ typedef struct {
   double dt;
   double c_hat;
   int32_t* trace;             /* [max_outer][n] out or NULL (as mgrhd_options.trace) */
+  /* out of place, as mgrhd_options.E_g_out ... v_out: all four set, or all
+   * four NULL (the patch is updated in place) */
+  double* E_g_out;            /* [N_g][n] or NULL */
+  double* F_g_out;            /* [3][N_g][n] or NULL */
+  double* e_gas_out;          /* [n] or NULL */
+  double* v_out;              /* [3][n] or NULL */
 } mgrhd_patch;
 
 typedef struct mgrhd_batch mgrhd_batch;

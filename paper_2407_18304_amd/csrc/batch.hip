@@ -144,6 +144,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_batch(BatchArgs b) {
     }
     if (!table_ok) {
       for (int64_t i = item.c0 + lane; i < item.c1; i += kWave) {
+        copy_through(a, state_ptrs((KArgsRef)&a), i, 0, 1);  // out of place: inputs
         if (a.status) a.status[i] = MGRHD_ST_BAD_TABLE;
         if (a.iters) a.iters[i] = 0;
         if (a.outer) a.outer[i] = 0;
@@ -191,6 +192,7 @@ __global__ __launch_bounds__(kBlock, WPE) void k_batch_wg(BatchArgs b) {
     }
     if (!table_ok) {
       for (int64_t i = item.c0 + threadIdx.x; i < item.c1; i += kBlock) {
+        copy_through(a, state_ptrs((KArgsRef)&a), i, 0, 1);  // out of place: inputs
         if (a.status) a.status[i] = MGRHD_ST_BAD_TABLE;
         if (a.iters) a.iters[i] = 0;
         if (a.outer) a.outer[i] = 0;
@@ -315,7 +317,7 @@ int mgrhd_batch_create(const mgrhd_patch* patches, int32_t n_patches, int32_t me
   const mgrhd_options* opt = opt_in ? opt_in : &defaults;
   if (opt->closure < 0 || opt->closure > 1) return MGRHD_E_MODE;
   if (opt->E_g_out || opt->F_g_out || opt->e_gas_out || opt->v_out)
-    return MGRHD_E_OPTION;  // patches are updated in place
+    return MGRHD_E_OPTION;  // outputs are given per patch
   auto pos = [](double x) { return x > 0.0 && std::isfinite(x); };
   if (!pos(opt->c) || !pos(opt->a_rad) || !pos(opt->h_over_k) || !pos(opt->c_v))
     return MGRHD_E_SCALAR;
@@ -348,6 +350,11 @@ int mgrhd_batch_create(const mgrhd_patch* patches, int32_t n_patches, int32_t me
       delete bt;
       return MGRHD_E_SCALAR;
     }
+    const int n_out = !!q.E_g_out + !!q.F_g_out + !!q.e_gas_out + !!q.v_out;
+    if (n_out != 0 && n_out != 4) {  // out of place needs all four
+      delete bt;
+      return MGRHD_E_NULL;
+    }
     KArgs& a = bt->h_patches[p];
     std::memset(&a, 0, sizeof(a));
     a.E = q.E_g;
@@ -363,6 +370,10 @@ int mgrhd_batch_create(const mgrhd_patch* patches, int32_t n_patches, int32_t me
     a.outer = q.outer;
     a.status = q.status;
     a.trace = q.trace;
+    a.Eo = q.E_g_out;  // NULL: set_derived points them at the inputs (in place)
+    a.Fo = q.F_g_out;
+    a.egaso = q.e_gas_out;
+    a.vo = q.v_out;
     a.edges = q.group_edges;
     a.chi_lo = q.chi_lo;
     a.alpha = q.alpha_chi;

@@ -264,7 +264,9 @@ class Patch(C.Structure):
                 ("outer", C.c_void_p), ("status", C.c_void_p), ("group_edges", C.c_void_p),
                 ("chi_lo", C.c_void_p), ("alpha_chi", C.c_void_p), ("chi_hi", C.c_void_p),
                 ("n_cells", C.c_int64), ("n_groups", C.c_int32), ("reserved", C.c_int32),
-                ("dt", C.c_double), ("c_hat", C.c_double), ("trace", C.c_void_p)]
+                ("dt", C.c_double), ("c_hat", C.c_double), ("trace", C.c_void_p),
+                ("E_g_out", C.c_void_p), ("F_g_out", C.c_void_p), ("e_gas_out", C.c_void_p),
+                ("v_out", C.c_void_p)]
 
 
 SYMBOLS += ["mgrhd_batch_set_item_scope", "mgrhd_batch_get_item_scope", "mgrhd_batch_tune",
@@ -305,7 +307,8 @@ class Batch:
     from a captured hipGraph).  ``patches``: list of dicts with the device
     tensors of each patch (E_g, F_g, rho, e_gas, v, edges, chi_lo, and
     optionally alpha_chi, chi_hi, kappa_scale, S_g, guess, iters, outer,
-    status) and its dt, c_hat."""
+    status, trace, and out=(E_g_out, F_g_out, e_gas_out, v_out) to update the
+    patch out of place) and its dt, c_hat."""
 
     def __init__(self, patches, *, mean_mode=MEAN_PPL_FIXED, c=1.0, a_rad=1.0, h_over_k=1.0,
                  c_v=1.5, eps_newton=1e-11, eps_outer=1e-13, max_newton=100, max_outer=20,
@@ -335,6 +338,12 @@ class Batch:
             q.chi_hi = _ptr(p.get("chi_hi"), (ng,), name="chi_hi")
             q.n_cells, q.n_groups = n, ng
             q.dt, q.c_hat = float(p["dt"]), float(p["c_hat"])
+            if p.get("out") is not None:
+                Eo, Fo, eo, vo = p["out"]
+                q.E_g_out = _ptr(Eo, (ng, n), name="E_g_out")
+                q.F_g_out = _ptr(Fo, (3, ng, n), name="F_g_out")
+                q.e_gas_out = _ptr(eo, (n,), name="e_gas_out")
+                q.v_out = _ptr(vo, (3, n), name="v_out")
         o = default_options()
         o.c, o.a_rad, o.h_over_k, o.c_v = c, a_rad, h_over_k, c_v
         o.eps_newton, o.eps_outer = eps_newton, eps_outer

@@ -2,6 +2,8 @@
 own group counts, edges and tables in one persistent launch, direct and
 replayed from a captured hipGraph.  Checked per patch against the single-table
 entry point and against the oracle.  GPU only."""
+import ctypes as C
+
 import numpy as np
 import pytest
 import torch
@@ -373,3 +375,81 @@ def test_batch_random_combinations():
             U.compare(w, res, U.run_oracle(w, mode),
                       label=f"random batch {case} ({g},{scope},{chunk}): patch N_g={w.ng} n={w.n}")
         b.close()
+
+
+@pytest.mark.parametrize("gpl,scope", TUNINGS)
+def test_batch_out_of_place(gpl, scope):
+    """Patches with their own output arrays (mgrhd_patch.E_g_out ... v_out),
+    beside patches updated in place: the same bits as the whole batch in
+    place, the inputs of the out-of-place patches unchanged, and a patch
+    with a rejected table and cells with invalid inputs copied through."""
+    layouts = _layouts(8)
+    dps = synth.device_patches(layouts)
+    bad_table, bad_cells = 2, 5
+    runs = []
+    for oop in (False, True):
+        synth.fill_patches(dps)                                  # the same inputs twice
+        pd = _patch_dicts(dps)
+        pd[bad_table]["chi_lo"] = pd[bad_table]["chi_lo"].clone()
+        pd[bad_table]["chi_lo"][1] = -1.0
+        pd[bad_cells]["rho"] = pd[bad_cells]["rho"].clone()
+        pd[bad_cells]["rho"][::7] = -1.0
+        inputs = [{k: d[k].clone() for k in U.FIELDS} for d in pd]
+        outs = []
+        for i, d in enumerate(pd):
+            if oop and i % 3 != 1:                               # every third stays in place
+                o = {k: torch.full_like(d[k], float("nan")) for k in U.FIELDS}
+                d["out"] = tuple(o[k] for k in U.FIELDS)
+                outs.append(o)
+            else:
+                outs.append(None)
+        b = mgrhd.Batch(pd, mean_mode=1, polish=1, **_consts())
+        b.set_tuning(gpl, 0, 100)
+        b.set_item_scope(scope)
+        b.run()
+        torch.cuda.synchronize()
+        res = []
+        for d, o, x in zip(pd, outs, inputs):
+            if o is not None:
+                for k in U.FIELDS:                               # inputs only read
+                    assert torch.equal(d[k], x[k]), k
+            src = o if o is not None else d
+            res.append(({k: src[k].cpu().numpy() for k in U.FIELDS},
+                        d["status"].cpu().numpy(), d["iters"].cpu().numpy()))
+        runs.append((res, inputs))
+        b.close()
+    (a, _), (b_, inputs) = runs
+    for i, ((ra, sa, ia), (rb, sb, ib)) in enumerate(zip(a, b_)):
+        assert np.array_equal(sa, sb) and np.array_equal(ia, ib), i
+        for k in U.FIELDS:
+            assert np.array_equal(ra[k], rb[k]), (i, k)
+    st = b_[bad_table][1]
+    assert (st == mgrhd.ST_BAD_TABLE).all()
+    for k in U.FIELDS:
+        assert np.array_equal(b_[bad_table][0][k], inputs[bad_table][k].cpu().numpy()), k
+    sc = b_[bad_cells][1]
+    assert (sc[::7] & mgrhd.ST_INVALID).all()
+    for k in U.FIELDS:
+        assert np.array_equal(b_[bad_cells][0][k][..., ::7],
+                              inputs[bad_cells][k].cpu().numpy()[..., ::7]), k
+
+
+def test_batch_out_of_place_needs_all_four_outputs():
+    dps = synth.device_patches(_layouts(2))
+    pd = _patch_dicts(dps)
+    o = torch.empty_like(pd[0]["E_g"])
+    L = mgrhd._batch_lib()
+    arr = (mgrhd.Patch * 1)()
+    q = arr[0]
+    d = pd[0]
+    ng, n = d["E_g"].shape
+    q.E_g, q.F_g, q.rho = d["E_g"].data_ptr(), d["F_g"].data_ptr(), d["rho"].data_ptr()
+    q.e_gas, q.v = d["e_gas"].data_ptr(), d["v"].data_ptr()
+    q.group_edges, q.chi_lo = d["edges"].data_ptr(), d["chi_lo"].data_ptr()
+    q.alpha_chi = d["alpha_chi"].data_ptr()
+    q.n_cells, q.n_groups, q.dt, q.c_hat = n, ng, float(d["dt"]), float(d["c_hat"])
+    q.E_g_out = o.data_ptr()                                     # one of the four
+    h = C.c_void_p()
+    opt = mgrhd.default_options()
+    assert L.mgrhd_batch_create(arr, 1, 1, C.byref(opt), C.byref(h)) == mgrhd.E_NULL
+    assert not h.value
