@@ -44,11 +44,13 @@ def test_parity_config2_sample(mode):
 
 
 @pytest.mark.parametrize("name,mode,n_sample", [("config1", 1, 600), ("config1", 2, 300),
-                                                 ("config2", 1, 200)])
+                                                 ("config2", 1, 200), ("config2", 0, 200),
+                                                 ("config2", 2, 100), ("config5", 1, 300)])
 def test_parity_full_size_sampled(name, mode, n_sample):
     """The benchmark's workloads at their full sizes (128^3 x 16 and 256^3 x 64
-    groups), drawn on the device and solved in the benchmark's launch
-    configuration; sampled cells against the oracle on the same inputs."""
+    groups in every mean mode, and the 128^3 pulse-opacity workload), drawn on
+    the device and solved in the benchmark's launch configuration; sampled
+    cells against the oracle on the same inputs."""
     U.full_size_sampled(name, mode, n_sample, seed=3)
 
 
